@@ -1,0 +1,187 @@
+/*
+ * ttcross.h — C ABI of the MI355X (gfx950) tensor-train cross integration library.
+ *
+ * The library computes integrals over [0,1]^m of a built-in integrand by the
+ * tensor-product Gauss--Legendre rule (Dolgov & Savostyanov, arXiv:1903.11554,
+ * Sec. 4.1, eq. quad_product), approximating the weighted tensor
+ *     B(i_1..i_m) = w_{i_1} ... w_{i_m} f(t_{i_1}, ..., t_{i_m})
+ * (weights folded in, last paragraph of Sec. 4.1) by the TT cross formula
+ * eq. tt (Sec. 3.2).  The index sets grow by the dimension-parallel greedy
+ * cross of Alg. 6 (Sec. 3.4) with one superblock per GPU workgroup: every
+ * superblock runs one step of Alg. 2 (random then rook pivoting, eq. rook)
+ * against the previous sweep's index sets, and accepted pivots are appended
+ * after the sweep.  The integral is the product of 2m-1 matrices of Sec. 4.1.
+ *
+ * All compute runs in HIP kernels on the device; the host code only validates,
+ * allocates and launches.  Every function returns a tt_status (or a plain value
+ * where stated); no C++ exception crosses this boundary, and outputs are left
+ * untouched when an error is returned.
+ *
+ * Ownership: the library owns every device buffer it allocates (index sets,
+ * cores, interpolation cores, logs); they live from tt_cross_init to
+ * tt_cross_free.  Callers own tt_problem structs and their params arrays,
+ * which are copied at init.  Pointers documented as "device" must point to
+ * device memory of the context's GPU; all others are host pointers.
+ *
+ * Thread safety: a tt_job must be used from one host thread at a time; a
+ * tt_ctx may be shared, calls that enqueue work serialise on its stream.
+ */
+#ifndef TTCROSS_H
+#define TTCROSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TT_OK = 0,
+  TT_CONVERGED = 1,      /* every integral of the job met its stopping rule            */
+  TT_NOT_CONVERGED = 2,  /* work remains (more sweeps needed)                          */
+  TT_EINVAL = -1,        /* invalid argument (see each function)                       */
+  TT_ENOMEM = -2,        /* device allocation failed or footprint over the limit       */
+  TT_EDEVICE = -3,       /* a HIP runtime call failed                                  */
+  TT_ENUMERIC = -4       /* non-finite integrand value, zero start, singular cross     */
+} tt_status;
+
+/* Integrand families.
+ * Paper form (Sec. 5.1, eqs. c, d, e): m = d-1 modes, variables x_2..x_d in [0,1];
+ *   C_d = 2 int B_d, D_d = 2 int A_d B_d, E_d = 2 int A_d (factor 2 included).
+ * u-form: m = d modes, the (0,inf)^d form of C_d and D_d mapped by u = x/(1-x).
+ * Synthetic: m = d modes on [0,1]^d, params = a[0..d) followed by b[0..d):
+ *   PROD_EXP = prod_j exp(-a_j x_j); SUM2_EXP_COS = prod exp(-a_j x_j) + prod cos(b_j x_j). */
+typedef enum {
+  TT_ISING_C = 1, TT_ISING_D = 2, TT_ISING_E = 3,
+  TT_ISING_C_U = 11, TT_ISING_D_U = 12,
+  TT_PROD_EXP = 21, TT_SUM2_EXP_COS = 22
+} tt_integrand;
+
+typedef enum { TT_FP64 = 0 } tt_precision;
+
+/* Stop reasons reported in tt_info.reason. */
+enum { TT_RUNNING = 0, TT_STOP_CONVERGED = 1, TT_STOP_RANK_CAP = 2, TT_STOP_MAX_SWEEPS = 3 };
+
+/* Library limits (a problem beyond them is rejected with TT_EINVAL). */
+#define TT_MAX_MODES 32
+#define TT_MAX_RANK 64
+#define TT_MAX_NODES 256
+
+typedef struct {
+  int32_t integrand;   /* tt_integrand                                                   */
+  int32_t d;           /* Ising: the paper's d (number of u variables); synthetic: dim    */
+  int32_t n_nodes;     /* Gauss--Legendre nodes per mode on [0,1], 1..TT_MAX_NODES        */
+  int32_t rank_cap;    /* maximum TT rank of every bond, 1..TT_MAX_RANK                   */
+  double  tol;         /* relative tolerance > 0 (pivot acceptance and stopping rule)     */
+  int32_t precision;   /* tt_precision                                                    */
+  int32_t max_sweeps;  /* 0 selects 4*rank_cap; at most 1024                              */
+  uint64_t seed;       /* key of the SplitMix64 counter-based sample generator            */
+  const double *params;/* synthetic families: 2*d doubles (a then b); NULL otherwise      */
+} tt_problem;
+
+/* Per-integral result and progress. value is the current TT quadrature. */
+typedef struct {
+  int32_t sweeps;      /* sweeps done                                                     */
+  int32_t max_rank;    /* largest bond rank                                               */
+  int32_t reason;      /* TT_RUNNING or a TT_STOP_* code                                  */
+  int32_t err_flags;   /* bits: non-finite value (1), singular cross (2), zero start (4),
+                          internal rank bucket overflow (8)                               */
+  int64_t evals;       /* integrand evaluations so far (start, samples, fibers, cores)    */
+  double  value;       /* integral estimate                                               */
+  double  rel_change;  /* |I_s - I_{s-1}| / |I_s| of the last sweep                       */
+} tt_info;
+
+/* One accepted-or-rejected pivot search of one superblock in one sweep.
+ * row = alpha*n + i over (I_<=b-1 x nodes), col = j*r_{b+1} + beta over
+ * (nodes x I_>b+1), with the ranks at the time of the search. */
+typedef struct {
+  int32_t row, col;    /* pivot position in the superblock (-1: not searched)            */
+  int32_t accepted;    /* 1 if appended to the index sets                                 */
+  int32_t iters;       /* rook (column,row) pairs used, 1..5; 0 if not searched            */
+  double  err;         /* B - B~ at the pivot (signed)                                    */
+  double  value;       /* B at the pivot                                                  */
+} tt_pivot;
+
+typedef struct tt_ctx tt_ctx;
+typedef struct tt_job tt_job;
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run
+ * on (e.g. PyTorch's current stream), or NULL for a library-owned stream.
+ * Errors: TT_EINVAL (out == NULL), TT_EDEVICE (bad device / HIP failure). */
+tt_status tt_ctx_create(int device, void *hip_stream, tt_ctx **out);
+void tt_ctx_destroy(tt_ctx *ctx);
+
+/* Bytes of device memory one problem needs at its rank cap (0 if invalid). */
+size_t tt_job_footprint(const tt_problem *problem);
+
+/* Start a job of `count` independent integrals (a batch: every kernel launch
+ * serves all of them).  Generates the Gauss--Legendre nodes, draws the rank-1
+ * start of each integral (largest |B| among 1024 SplitMix64 grid samples),
+ * evaluates the first cores and the first quadrature value.  Synchronises.
+ * Errors: TT_EINVAL (bad problem: d < 1, modes > TT_MAX_MODES, n or rank out of
+ * range, tol <= 0, unknown integrand or precision, missing params),
+ * TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC (all start samples zero or non-finite). */
+tt_status tt_cross_init(tt_ctx *ctx, const tt_problem *problems, int32_t count, tt_job **out);
+
+/* Enqueue n_sweeps sweeps of Alg. 6 for every integral not yet stopped, then
+ * synchronise and fill info[count] (may be NULL).  Returns TT_CONVERGED when
+ * every integral has stopped, TT_NOT_CONVERGED otherwise. */
+tt_status tt_cross_sweep(tt_job *job, int32_t n_sweeps, tt_info *info);
+
+/* Sweep until every integral stops (stopping rule or max_sweeps); fills info. */
+tt_status tt_cross_run(tt_job *job, tt_info *info);
+
+/* Copy the integral values (count doubles, host) and infos (may be NULL). */
+tt_status tt_cross_integrate(tt_job *job, double *values, tt_info *info);
+
+/* Diagnostics for tests: the pivot log of integral k (sweeps x (m-1) records,
+ * host buffer of `capacity` records, *written = records copied), the
+ * integral after the start and after each sweep (sweeps+1 doubles), and the
+ * index sets: for bond b the left set I_<=b as rows of (b+1) node indices and
+ * the right set I_>b as rows of (m-b-1) node indices, packed bond by bond
+ * (left then right), each row in insertion order; ranks[m-1] receives r_b. */
+tt_status tt_job_pivot_log(tt_job *job, int32_t k, tt_pivot *log, int64_t capacity, int64_t *written);
+tt_status tt_job_history(tt_job *job, int32_t k, double *values, int64_t capacity, int64_t *written);
+tt_status tt_job_index_sets(tt_job *job, int32_t k, int32_t *ranks, int32_t *nodes,
+                            int64_t capacity, int64_t *written);
+/* Gauss--Legendre nodes and weights of integral k as generated on the device (n each). */
+tt_status tt_job_nodes(tt_job *job, int32_t k, double *t, double *w);
+void tt_cross_free(tt_job *job);
+
+/* Standalone batched integrand evaluation (the fiber-evaluation kernel of the
+ * sweep, exposed for parity checks and roofline measurement).
+ * tt_eval_points: B at npts multi-indices; d_idx is a device int32 array of
+ * npts*m node indices (row-major, one row per point), d_out a device double
+ * array of npts values.  Asynchronous on the context stream.
+ * tt_eval_fibers: B over the fiber set I_left x [n] x I_right at mode position
+ * `pos` (0 <= pos < m): d_left is device int32 [r_left * pos] node indices,
+ * d_right device int32 [r_right * (m-pos-1)]; d_out receives r_left*n*r_right
+ * doubles in the order (alpha, i, beta), beta fastest.  Asynchronous.
+ * Errors: TT_EINVAL (bad problem or sizes), TT_EDEVICE. */
+tt_status tt_eval_points(tt_ctx *ctx, const tt_problem *problem, const int32_t *d_idx,
+                         int64_t npts, double *d_out);
+tt_status tt_eval_fibers(tt_ctx *ctx, const tt_problem *problem, int32_t pos,
+                         const int32_t *d_left, int32_t r_left,
+                         const int32_t *d_right, int32_t r_right, double *d_out);
+
+/* Optional per-kernel timing with HIP events recorded on the context stream
+ * around every launch (adds two event records per launch).  tt_ctx_profile
+ * switches it on or off and clears the totals; tt_ctx_kernel_time returns the
+ * number of timed launches and their summed duration in ms for a kernel kind:
+ * 0 pivot search, 1 core update, 2 quadrature/stopping rule, 3 rank-1 start,
+ * 4 Gauss--Legendre nodes, 5 tt_eval_points, 6 tt_eval_fibers.
+ * Errors: TT_EINVAL (bad kind or NULL outputs). */
+tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
+tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);
+
+/* Synchronise the context stream. */
+tt_status tt_ctx_synchronize(tt_ctx *ctx);
+
+/* Human-readable name of a status code (static string). */
+const char *tt_status_string(tt_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTCROSS_H */

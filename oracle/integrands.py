@@ -29,7 +29,7 @@ recomputed from its factors), with no reordering for speed.
 
 Pinned by: closed forms C_2 = 1, D_2 = 1/3, E_2 = 6 - 8 ln 2 (1-D quadrature),
 C_3 = L_{-3}(2), C_4 = 7 zeta(3)/12, D_3, D_4 (brute-force tensor quadrature),
-the printed D_8 (Sec. 5.4 figure), u-form C_1 = 2, C_2 = 1, D_2 = 1/3 (adaptive
+the printed D_8 (Sec. 5.5 figure), u-form C_1 = 2, C_2 = 1, D_2 = 1/3 (adaptive
 quadrature), and the exact integrals of the synthetic families.
 """
 

@@ -1,0 +1,276 @@
+// Device-side building blocks for the gfx950 TT cross library:
+//   * double-double error-free transforms (Dekker 1971; Knuth TAOCP vol. 2;
+//     the accurate double-word sum/product of Joldes, Muller & Popescu 2017),
+//   * the SplitMix64 counter-based generator (Steele, Lea & Flood 2014),
+//   * the integrands of the Ising family (eqs. c, d, e of Sec. 5.1), their
+//     u-form, and the synthetic product families, evaluated one point per lane
+//     with the coordinates held in registers,
+//   * workgroup argmax / max reductions for 64-wide wavefronts.
+// All floating-point code is compiled with contraction off; every FMA below is
+// written explicitly, so a point gets the same bits in every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ttcross.h"
+
+namespace ttx {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ double-double
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ __forceinline__ dd quick_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ __forceinline__ dd dd_add(dd x, dd y) {
+  dd s = two_sum(x.hi, y.hi);
+  dd t = two_sum(x.lo, y.lo);
+  double e = s.lo + t.hi;
+  s = quick_two_sum(s.hi, e);
+  e = s.lo + t.lo;
+  return quick_two_sum(s.hi, e);
+}
+__device__ __forceinline__ dd dd_neg(dd x) { return {-x.hi, -x.lo}; }
+__device__ __forceinline__ dd dd_sub(dd x, dd y) { return dd_add(x, dd_neg(y)); }
+__device__ __forceinline__ dd dd_mul(dd x, dd y) {
+  dd p = two_prod(x.hi, y.hi);
+  double e = fma(x.hi, y.lo, fma(x.lo, y.hi, p.lo));
+  return quick_two_sum(p.hi, e);
+}
+__device__ __forceinline__ dd dd_mul_d(dd x, double y) {
+  dd p = two_prod(x.hi, y);
+  double e = fma(x.lo, y, p.lo);
+  return quick_two_sum(p.hi, e);
+}
+__device__ __forceinline__ dd dd_div(dd x, dd y) {
+  double q1 = x.hi / y.hi;
+  dd r = dd_sub(x, dd_mul_d(y, q1));
+  double q2 = r.hi / y.hi;
+  r = dd_sub(r, dd_mul_d(y, q2));
+  double q3 = r.hi / y.hi;
+  dd q = quick_two_sum(q1, q2);
+  return dd_add(q, dd{q3, 0.0});
+}
+__device__ __forceinline__ dd dd_from(double a) { return {a, 0.0}; }
+
+// ---------------------------------------------------------------- SplitMix64
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// (counter+1)-th output of the stream whose state starts at `seed`.
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t counter) {
+  return splitmix_mix(seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull);
+}
+// uniform integer in [0, n), n < 2^32, from the high 32 bits of a draw
+__device__ __forceinline__ uint32_t uniform_below(uint64_t u, uint32_t n) {
+  return (uint32_t)(((u >> 32) * (uint64_t)n) >> 32);
+}
+__device__ __forceinline__ uint64_t sample_counter(int sweep, int bond, int j) {
+  return ((uint64_t)sweep << 40) + ((uint64_t)bond << 24) + (uint64_t)j;
+}
+__device__ __forceinline__ uint64_t start_counter(int q, int k) {
+  return (1ull << 63) + ((uint64_t)q << 16) + (uint64_t)k;
+}
+
+// ---------------------------------------------------------------- integrands
+// y[0..m) holds the coordinates of one point (entries >= m are ignored).
+// Returns the unweighted integrand f(y) including its constant prefactor.
+
+// Paper form, y_k = x_{k+2}: the prefix sum 1 + sum_k y_1..y_k and the suffix
+// sum 1 + sum_k y_k..y_m by Horner's rule, and the pair product over all runs
+// y_a..y_b (1 <= a <= b <= m), i.e. over 1 <= i < j <= d with x_{i+1}..x_j.
+template <int MAXM>
+__device__ __forceinline__ double ising_paper(int family, int m, const double (&y)[MAXM]) {
+  double num = 2.0, den = 1.0;
+  if (family != TT_ISING_E) {
+    double q = 0.0, s = 0.0;
+#pragma unroll
+    for (int k = MAXM - 1; k >= 0; --k)
+      if (k < m) q = fma(q, y[k], y[k]);   // y_k (1 + q)
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k)
+      if (k < m) s = fma(s, y[k], y[k]);   // (1 + s) y_k
+    den = (1.0 + q) * (1.0 + s);
+  }
+  if (family != TT_ISING_C) {
+    double pn = 1.0, pd = 1.0;
+    // constant trip counts with uniform guards: fully unrolled, y stays in VGPRs
+#pragma unroll
+    for (int a = 0; a < MAXM; ++a) {
+      if (a < m) {
+        double p = 1.0;
+#pragma unroll
+        for (int b = a; b < MAXM; ++b) {
+          if (b < m) {
+            p *= y[b];
+            pn = fma(-pn, p, pn);    // pn * (1 - p)
+            pd = fma(pd, p, pd);     // pd * (1 + p)
+          }
+        }
+      }
+    }
+    if (m <= 31) {               // pd^2 <= 2^(m(m+1)) stays finite
+      num = num * pn * pn;
+      den = den * (pd * pd);
+    } else {
+      double r = pn / pd;
+      num = num * r * r;
+    }
+  }
+  return num / den;
+}
+
+// u-form, d = m variables x_j with u_j = x_j/(1-x_j):
+//   f = 4/d! [sum_j (u_j + 1/u_j)]^-2 prod_j 1/(x_j(1-x_j)) [* prod_{i<j} ((u_i-u_j)/(u_i+u_j))^2]
+// With h_j = x_j(1-x_j), g_j = x_j^2 + (1-x_j)^2: u_j + 1/u_j = g_j/h_j, so
+// f = (4/d!) H / G^2 with H = prod h_j and G = sum_j g_j prod_{i != j} h_i;
+// (u_i-u_j)/(u_i+u_j) = (x_i-x_j)/(x_i+x_j-2 x_i x_j).
+template <int MAXM>
+__device__ __forceinline__ double ising_u(int family, int m, const double (&y)[MAXM],
+                                          double four_over_mfact) {
+  double G = 0.0, H = 1.0;
+#pragma unroll
+  for (int k = 0; k < MAXM; ++k) {
+    if (k < m) {
+      double x = y[k], omx = 1.0 - x;
+      double h = x * omx;
+      double g = fma(x, x, omx * omx);
+      G = fma(G, h, g * H);
+      H = H * h;
+    }
+  }
+  double f = four_over_mfact * H / (G * G);
+  if (family == TT_ISING_D_U) {
+    // prod ((x_i-x_j)/(x_i+x_j-2x_i x_j))^2 as a ratio of two products, brought
+    // back to [1,2) by an exact power-of-two scaling after every row
+    double pn = 1.0, pd = 1.0;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (i < m) {
+#pragma unroll
+        for (int j = i + 1; j < MAXM; ++j) {
+          if (j < m) {
+            const double dn = y[i] - y[j];
+            const double dd_ = fma(-2.0 * y[i], y[j], y[i] + y[j]);
+            pn = pn * (dn * dn);
+            pd = pd * (dd_ * dd_);
+          }
+        }
+        const int e = ilogb(pd);
+        pn = ldexp(pn, -e);
+        pd = ldexp(pd, -e);
+      }
+    }
+    f = f * (pn / pd);
+  }
+  return f;
+}
+
+template <int MAXM>
+__device__ __forceinline__ double synthetic(int family, int m, const double (&y)[MAXM],
+                                            const double* __restrict__ a,
+                                            const double* __restrict__ b) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < MAXM; ++k)
+    if (k < m) s = fma(a[k], y[k], s);
+  double e = exp(-s);
+  if (family == TT_PROD_EXP) return e;
+  double c = 1.0;
+#pragma unroll
+  for (int k = 0; k < MAXM; ++k)
+    if (k < m) c = c * cos(b[k] * y[k]);
+  return e + c;
+}
+
+struct FamilyArgs {
+  int family, m;
+  double four_over_mfact;    // u-form prefactor 4/m!
+  const double* a;           // synthetic parameters (device)
+  const double* b;
+};
+
+template <int MAXM>
+__device__ __forceinline__ double integrand(const FamilyArgs& fa, const double (&y)[MAXM]) {
+  switch (fa.family) {
+    case TT_ISING_C:
+    case TT_ISING_D:
+    case TT_ISING_E:
+      return ising_paper<MAXM>(fa.family, fa.m, y);
+    case TT_ISING_C_U:
+    case TT_ISING_D_U:
+      return ising_u<MAXM>(fa.family, fa.m, y, fa.four_over_mfact);
+    default:
+      return synthetic<MAXM>(fa.family, fa.m, y, fa.a, fa.b);
+  }
+}
+
+// --------------------------------------------------------------- reductions
+// argmax of |e| with ties to the lowest index; NaN never wins (comparisons are false).
+struct ArgMax {
+  double v;   // |e| (or -1 for "nothing")
+  int idx;
+};
+__device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+__device__ __forceinline__ ArgMax wave_argmax(ArgMax a) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    double ov = __shfl_xor(a.v, off, kWave);
+    int oi = __shfl_xor(a.idx, off, kWave);
+    if (better(ov, oi, a.v, a.idx)) { a.v = ov; a.idx = oi; }
+  }
+  return a;
+}
+// Block-wide argmax; every thread receives the result.  scratch: >= 2*nwaves slots.
+__device__ __forceinline__ ArgMax block_argmax(ArgMax a, double* sv, int* si) {
+  a = wave_argmax(a);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  __syncthreads();
+  if (lane == 0) { sv[wid] = a.v; si[wid] = a.idx; }
+  __syncthreads();
+  ArgMax r{-1.0, 0x7fffffff};
+  for (int w = 0; w < nw; ++w)
+    if (better(sv[w], si[w], r.v, r.idx)) { r.v = sv[w]; r.idx = si[w]; }
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+__device__ __forceinline__ double block_max(double v, double* sv) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  __syncthreads();
+  if (lane == 0) sv[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < nw; ++w) r = fmax(r, sv[w]);
+  __syncthreads();
+  return r;
+}
+
+}  // namespace ttx

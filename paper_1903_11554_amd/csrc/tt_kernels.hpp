@@ -1,0 +1,848 @@
+// HIP kernels of the TT cross library (gfx950, wave64).
+//
+// One sweep of Alg. 6 (dimension-parallel greedy cross, Sec. 3.4) is three
+// launches over every integral of a job:
+//   k_search  one workgroup per superblock b: Alg. 2 on the (r_{b-1} n) x (n r_{b+1})
+//             matrix B(I_<=b-1 i_b, i_b+1 I_>b+1) with the previous sweep's sets:
+//             random samples, then column / row steps until the rook condition
+//             (eq. rook) holds; the approximation is B~ = C_b F_{b+1} with the
+//             interpolation core C_b = F_b M_b^-1 (Alg. 1's B matrix);
+//   k_update  one workgroup per core c: appends the accepted pivots of bonds c-1
+//             and c to I_<=c-1 and I_>c (nestedness, eq. nest), evaluates the
+//             new fibre entries of F_c = B(I_<=c-1, i_c, I_>c), refactorises the
+//             cross M_c = B(I_<=c, I_>c) and recomputes C_c; sums the core over
+//             its mode index for the quadrature;
+//   k_integral one workgroup per integral: commits the ranks, multiplies the
+//             2m-1 matrices of the TT quadrature (Sec. 4.1) and applies the
+//             stopping rule.
+#pragma once
+
+#include "tt_device.hpp"
+
+namespace ttx {
+
+struct PivRec {
+  int32_t row, col, acc, iters;
+  double err, val;
+};
+static_assert(sizeof(PivRec) == sizeof(tt_pivot), "PivRec must mirror tt_pivot");
+
+struct ProbState {
+  int32_t sweeps, done, reason, err_flags;
+  int32_t nacc, max_rank, pad0, pad1;
+  unsigned long long evals;
+  double value, rel, pad2;
+};
+
+struct ProbDesc {
+  int32_t family, m, n, R;
+  int32_t max_sweeps, nbonds, pad0, pad1;
+  double tol, four_over_mfact;
+  uint64_t seed;
+  double *t, *w, *pa, *pb;
+  int32_t *Lpar, *Lnode, *Rpar, *Rnode;  // [nbonds][R]
+  double *Lx, *Rx;                       // [nbonds][R][m]
+  double *Lw, *Rw;                       // [nbonds][R]
+  double *F;                             // cores, core c at F + Foff[c]
+  int64_t *Foff;
+  double *C;                             // interpolation cores (transposed), bond b at C + Coff[b]
+  int64_t *Coff;
+  double *S;                             // [m][R*R] core sums over the mode index
+  int32_t *rank;                         // [nbonds]
+  PivRec *piv;                           // [nbonds] current sweep's pivots
+  double *scale;                         // [nbonds] largest |B| seen per bond
+  PivRec *log;                           // [max_sweeps][nbonds]
+  double *hist;                          // [max_sweeps+1]
+  int32_t *start;                        // [m] start multi-index
+  ProbState *st;
+};
+
+constexpr int kBlock = 256;        // start, update, standalone evaluation
+constexpr int kSearchBlock = 512;  // pivot search: 8 waves per superblock
+constexpr int kStart = 1024;     // rank-1 start samples
+constexpr int kMaxSamples = 1024;
+constexpr int kRook = 5;
+
+__device__ __forceinline__ int rowcap(const ProbDesc& p, int c) { return c == 0 ? 1 : p.R; }
+__device__ __forceinline__ int colcap(const ProbDesc& p, int c) { return c == p.m - 1 ? 1 : p.R; }
+
+__device__ __forceinline__ FamilyArgs family_args(const ProbDesc& p) {
+  return FamilyArgs{p.family, p.m, p.four_over_mfact, p.pa, p.pb};
+}
+
+// ------------------------------------------------------------------ GL rule
+// Nodes on [0,1] = (x+1)/2 for the roots x of P_n; weights 1/((1-x^2) P_n'(x)^2).
+// Newton in double from the classical initial guess, then two Newton steps in
+// double-double; the dd results are rounded once to double.
+__device__ inline void legendre_dd(int n, dd x, dd& pn, dd& pn1) {
+  dd p0 = dd_from(1.0), p1 = x;
+  if (n == 0) { pn = p0; pn1 = dd_from(0.0); return; }
+  for (int k = 1; k < n; ++k) {
+    dd a = dd_mul_d(dd_mul(x, p1), (double)(2 * k + 1));
+    dd b = dd_mul_d(p0, (double)k);
+    dd p2 = dd_div(dd_sub(a, b), dd_from((double)(k + 1)));
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  pn1 = p0;
+}
+
+__device__ inline void gl_node(int n, int k, double& t_out, double& w_out) {
+  // k-th root in decreasing order of x
+  double x = cos(M_PI * ((double)k + 0.75) / ((double)n + 0.5));
+  for (int it = 0; it < 100; ++it) {
+    double p0 = 1.0, p1 = x;
+    for (int j = 1; j < n; ++j) {
+      double p2 = ((2 * j + 1) * x * p1 - j * p0) / (j + 1);
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (x * p1 - p0) / (x * x - 1.0);
+    double dx = p1 / dp;
+    x -= dx;
+    if (fabs(dx) < 1e-16) break;
+  }
+  dd X = dd_from(x), pn, pn1, dp;
+  for (int it = 0; it < 2; ++it) {
+    legendre_dd(n, X, pn, pn1);
+    dd x2m1 = dd_sub(dd_mul(X, X), dd_from(1.0));
+    dp = dd_div(dd_mul_d(dd_sub(dd_mul(X, pn), pn1), (double)n), x2m1);
+    X = dd_sub(X, dd_div(pn, dp));
+  }
+  legendre_dd(n, X, pn, pn1);
+  dd x2m1 = dd_sub(dd_mul(X, X), dd_from(1.0));
+  dp = dd_div(dd_mul_d(dd_sub(dd_mul(X, pn), pn1), (double)n), x2m1);
+  dd one_m_x2 = dd_neg(x2m1);
+  dd wk = dd_div(dd_from(1.0), dd_mul(one_m_x2, dd_mul(dp, dp)));   // = w_x / 2
+  dd tk = dd_mul_d(dd_add(X, dd_from(1.0)), 0.5);
+  t_out = tk.hi + tk.lo;
+  w_out = wk.hi + wk.lo;
+}
+
+__global__ void k_gl(int n, double* __restrict__ t, double* __restrict__ w) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    double tk, wk;
+    gl_node(n, k, tk, wk);
+    t[n - 1 - k] = tk;   // increasing order
+    w[n - 1 - k] = wk;
+  }
+}
+
+
+// ----------------------------------------------------- rank-1 start (m >= 0)
+template <int MAXM>
+__global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
+  const ProbDesc p = P[blockIdx.x];
+  const int m = p.m, n = p.n, tid = threadIdx.x;
+  const FamilyArgs fa = family_args(p);
+  __shared__ double sv[kBlock / kWave + 1];
+  __shared__ int si[kBlock / kWave + 1];
+  __shared__ int s_i0[MAXM];
+  __shared__ double s_buf[TT_MAX_NODES];
+  ProbState* st = p.st;
+
+  if (m <= 1) {   // no bond: the tensor is a vector (or a scalar for m = 0)
+    double val = 0.0;
+    if (m == 0) {
+      double y[MAXM];
+#pragma unroll
+      for (int k = 0; k < MAXM; ++k) y[k] = 0.0;
+      val = integrand<MAXM>(fa, y);
+    } else {
+      for (int i = tid; i < n; i += blockDim.x) {
+        double y[MAXM];
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) y[k] = 0.0;
+        y[0] = p.t[i];
+        s_buf[i] = p.w[i] * integrand<MAXM>(fa, y);
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int i = 0; i < n; ++i) val += s_buf[i];
+    }
+    if (tid == 0) {
+      p.hist[0] = val;
+      st->value = val;
+      st->rel = 0.0;
+      st->sweeps = 0;
+      st->done = 1;
+      st->reason = TT_STOP_CONVERGED;
+      st->evals = (m == 1) ? (unsigned long long)n : 0ull;
+      st->err_flags = isfinite(val) ? 0 : 1;
+      st->max_rank = 1;
+    }
+    return;
+  }
+
+  ArgMax best{-1.0, 0x7fffffff};
+  bool bad = false;
+  for (int q = tid; q < kStart; q += blockDim.x) {
+    double y[MAXM];
+    double W = 1.0;
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+      if (k < m) {
+        int ik = (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n);
+        y[k] = p.t[ik];
+        W = W * p.w[ik];
+      } else {
+        y[k] = 0.0;
+      }
+    }
+    double v = W * integrand<MAXM>(fa, y);
+    if (!isfinite(v)) bad = true;
+    if (better(fabs(v), q, best.v, best.idx)) { best.v = fabs(v); best.idx = q; }
+  }
+  best = block_argmax(best, sv, si);
+  int any_bad = __syncthreads_or(bad);
+  const int q = best.idx;
+  if (tid < m) s_i0[tid] = (int)uniform_below(splitmix_at(p.seed, start_counter(q, tid)), (uint32_t)n);
+  __syncthreads();
+  if (any_bad || !(best.v > 0.0)) {
+    if (tid == 0) {
+      st->err_flags = any_bad ? 1 : 4;
+      st->done = 1;
+      st->reason = TT_STOP_CONVERGED;
+      st->evals = kStart;
+      st->sweeps = 0;
+      st->max_rank = 0;
+      st->value = 0.0;
+      st->rel = __builtin_huge_val();
+    }
+    return;
+  }
+  const int nb = m - 1, R = p.R;
+  // left sets I_<=b = {(i0_0..i0_b)}, right sets I_>b = {(i0_b+1..i0_m-1)}
+  for (int e = tid; e < nb * m; e += blockDim.x) {
+    int b = e / m, k = e % m;
+    double tk = p.t[s_i0[k]];
+    if (k <= b) p.Lx[((size_t)b * R) * m + k] = tk;
+    else p.Rx[((size_t)b * R) * m + k] = tk;
+  }
+  if (tid == 0) {
+    double lw = 1.0;
+    for (int b = 0; b < nb; ++b) {
+      lw = lw * p.w[s_i0[b]];
+      p.Lw[(size_t)b * R] = lw;
+      p.Lpar[(size_t)b * R] = 0;
+      p.Lnode[(size_t)b * R] = s_i0[b];
+    }
+    double rw = 1.0;
+    for (int b = nb - 1; b >= 0; --b) {
+      rw = p.w[s_i0[b + 1]] * rw;
+      p.Rw[(size_t)b * R] = rw;
+      p.Rpar[(size_t)b * R] = 0;
+      p.Rnode[(size_t)b * R] = s_i0[b + 1];
+    }
+    for (int b = 0; b < nb; ++b) {
+      p.rank[b] = 1;
+      p.scale[b] = best.v;
+    }
+    for (int k = 0; k < m; ++k) p.start[k] = s_i0[k];
+    st->sweeps = 0;
+    st->done = 0;
+    st->reason = TT_RUNNING;
+    st->err_flags = 0;
+    st->evals = kStart;
+    st->max_rank = 1;
+    st->rel = __builtin_huge_val();
+  }
+}
+
+// ------------------------------------------------------------ k_search
+template <int MAXM>
+struct SearchSmem {
+  double Lx[TT_MAX_RANK * (MAXM + 1)];
+  double Rx[TT_MAX_RANK * (MAXM + 1)];
+  double Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
+  double t[TT_MAX_NODES], w[TT_MAX_NODES];
+  double vec[TT_MAX_RANK];
+  double red_v[kSearchBlock / kWave + 1];
+  int red_i[kSearchBlock / kWave + 1];
+  double e_star, a_star;
+};
+
+template <int MAXM>
+__global__ __launch_bounds__(kSearchBlock) void k_search(ProbDesc* __restrict__ P,
+                                                   const int2* __restrict__ tasks) {
+  constexpr int LD = MAXM + 1;
+  __shared__ SearchSmem<MAXM> sm;
+  const int2 tk = tasks[blockIdx.x];
+  const ProbDesc& p = P[tk.x];
+  const int b = tk.y, tid = threadIdx.x;
+  ProbState* st = p.st;
+  const int m = p.m, n = p.n, R = p.R, nb = p.nbonds;
+  if (st->done) return;
+  const int sweep = st->sweeps;
+  const int rb = p.rank[b];
+  const int rL = b > 0 ? p.rank[b - 1] : 1;
+  const int rR = b < m - 2 ? p.rank[b + 1] : 1;
+  if (rb >= R) {
+    if (tid == 0) {
+      PivRec rec{-1, -1, 0, 0, 0.0, 0.0};
+      p.piv[b] = rec;
+      p.log[(size_t)sweep * nb + b] = rec;
+    }
+    return;
+  }
+  const FamilyArgs fa = family_args(p);
+  // stage index-set coordinates, node table and weights in LDS
+  for (int e = tid; e < rL * b; e += blockDim.x) {
+    int a = e / b, k = e % b;
+    sm.Lx[a * LD + k] = p.Lx[((size_t)(b - 1) * R + a) * m + k];
+  }
+  const int nright = m - b - 2;
+  for (int e = tid; e < rR * nright; e += blockDim.x) {
+    int a = e / nright, k = b + 2 + e % nright;
+    sm.Rx[a * LD + k] = p.Rx[((size_t)(b + 1) * R + a) * m + k];
+  }
+  for (int a = tid; a < rL; a += blockDim.x) sm.Lw[a] = b > 0 ? p.Lw[(size_t)(b - 1) * R + a] : 1.0;
+  for (int a = tid; a < rR; a += blockDim.x)
+    sm.Rw[a] = (b + 1 <= m - 2) ? p.Rw[(size_t)(b + 1) * R + a] : 1.0;
+  for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = p.t[i]; sm.w[i] = p.w[i]; }
+  __syncthreads();
+
+  const int nrows = rL * n, ncols = n * rR;
+  const double* __restrict__ F1 = p.F + p.Foff[b + 1];
+  const int cc1 = colcap(p, b + 1);
+  const double* __restrict__ Cb = p.C + p.Coff[b];
+  const size_t ldC = (size_t)rowcap(p, b) * n;
+
+  auto evalA = [&](int row, int col) -> double {
+    const int al = row / n, i = row - al * n;
+    const int j = col / rR, be = col - j * rR;
+    double y[MAXM];
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+      double v = 0.0;
+      if (k < m) {
+        v = (k < b) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
+        v = (k == b) ? sm.t[i] : v;
+        v = (k == b + 1) ? sm.t[j] : v;
+      }
+      y[k] = v;
+    }
+    const double W = ((sm.Lw[al] * sm.w[i]) * sm.w[j]) * sm.Rw[be];
+    return W * integrand<MAXM>(fa, y);
+  };
+
+  double seen = 0.0;
+  bool bad = false;
+  // ---- random samples (Alg. 2, first step)
+  const int nsamp = min(nrows + ncols, kMaxSamples);
+  const uint32_t total = (uint32_t)nrows * (uint32_t)ncols;
+  ArgMax best{-1.0, 0x7fffffff};
+  for (int q = tid; q < nsamp; q += blockDim.x) {
+    const uint32_t id = uniform_below(splitmix_at(p.seed, sample_counter(sweep, b, q)), total);
+    const int row = (int)(id / (uint32_t)ncols), col = (int)(id % (uint32_t)ncols);
+    const double a = evalA(row, col);
+    const int j = col / rR, be = col - j * rR;
+    double s = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < rb; ++k) s = fma(Cb[k * ldC + row], F1[((size_t)k * n + j) * cc1 + be], s);
+    const double e = a - s;
+    bad |= !isfinite(e);
+    seen = fmax(seen, fabs(a));
+    if (better(fabs(e), q, best.v, best.idx)) { best.v = fabs(e); best.idx = q; }
+  }
+  best = block_argmax(best, sm.red_v, sm.red_i);
+  int row, col;
+  {
+    const uint32_t id = uniform_below(splitmix_at(p.seed, sample_counter(sweep, b, best.idx)), total);
+    row = (int)(id / (uint32_t)ncols);
+    col = (int)(id % (uint32_t)ncols);
+  }
+  // ---- rook pivoting: column step then row step, until the column repeats
+  int iters = 0;
+  bool invalid = !(best.v >= 0.0);
+  if (tid == 0) { sm.e_star = 0.0; sm.a_star = 0.0; }
+  for (int it = 0; it < kRook && !invalid; ++it) {
+    {   // column step: B~(:, col) = C_b F_{b+1}(:, col)
+      const int j = col / rR, be = col - j * rR;
+      if (tid < rb) sm.vec[tid] = F1[((size_t)tid * n + j) * cc1 + be];
+      __syncthreads();
+      ArgMax bc{-1.0, 0x7fffffff};
+      for (int r = tid; r < nrows; r += blockDim.x) {
+        const double a = evalA(r, col);
+        double s = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < rb; ++k) s = fma(Cb[k * ldC + r], sm.vec[k], s);
+        const double e = a - s;
+        bad |= !isfinite(e);
+        seen = fmax(seen, fabs(a));
+        if (better(fabs(e), r, bc.v, bc.idx)) { bc.v = fabs(e); bc.idx = r; }
+      }
+      bc = block_argmax(bc, sm.red_v, sm.red_i);
+      if (!(bc.v >= 0.0)) { invalid = true; break; }   // every error non-finite
+      row = bc.idx;
+    }
+    {   // row step: B~(row, :) = C_b(row, :) F_{b+1}
+      if (tid < rb) sm.vec[tid] = Cb[tid * ldC + row];
+      __syncthreads();
+      ArgMax br{-1.0, 0x7fffffff};
+      double my_e = 0.0, my_a = 0.0;
+      for (int c = tid; c < ncols; c += blockDim.x) {
+        const double a = evalA(row, c);
+        const int j = c / rR, be = c - j * rR;
+        double s = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < rb; ++k) s = fma(sm.vec[k], F1[((size_t)k * n + j) * cc1 + be], s);
+        const double e = a - s;
+        bad |= !isfinite(e);
+        seen = fmax(seen, fabs(a));
+        if (better(fabs(e), c, br.v, br.idx)) { br.v = fabs(e); br.idx = c; my_e = e; my_a = a; }
+      }
+      br = block_argmax(br, sm.red_v, sm.red_i);
+      if (!(br.v >= 0.0)) { invalid = true; break; }
+      if (br.idx % (int)blockDim.x == tid) {   // the thread that evaluated the winner
+        sm.e_star = my_e;
+        sm.a_star = my_a;
+      }
+      __syncthreads();
+      iters = it + 1;
+      const bool same = (br.idx == col);
+      col = br.idx;
+      if (same) break;
+    }
+  }
+  seen = block_max(seen, sm.red_v);
+  const int any_bad = __syncthreads_or(bad);
+  // is either half of the pivot already in its set? (one thread per set element)
+  const int al_s = row / n, i_s = row - al_s * n;
+  const int j_s = col / rR, be_s = col - j_s * rR;
+  int mine = 0;
+  if (tid < rb) {
+    mine = (p.Lpar[(size_t)b * R + tid] == al_s && p.Lnode[(size_t)b * R + tid] == i_s) ||
+           (p.Rnode[(size_t)b * R + tid] == j_s && p.Rpar[(size_t)b * R + tid] == be_s);
+  }
+  const int dup = __syncthreads_or(mine);
+  if (tid == 0) {
+    const double e_star = sm.e_star, a_star = sm.a_star;
+    const double scale = fmax(p.scale[b], seen);
+    p.scale[b] = scale;
+    const int acc = (fabs(e_star) > p.tol * scale) && !dup && !any_bad && !invalid;
+    PivRec rec{row, col, acc, iters, e_star, a_star};
+    p.piv[b] = rec;
+    p.log[(size_t)sweep * nb + b] = rec;
+    if (any_bad || invalid) atomicOr(&st->err_flags, 1);
+    atomicAdd(&st->evals, (unsigned long long)(nsamp + iters * (nrows + ncols)));
+  }
+}
+
+// ------------------------------------------------------------ k_update
+template <int MAXM, int RMAX>
+struct UpdateSmem {
+  union {
+    struct {                       // fibre evaluation stage
+      double Lx[TT_MAX_RANK * (MAXM + 1)];
+      double Rx[TT_MAX_RANK * (MAXM + 1)];
+      double Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
+      double t[TT_MAX_NODES], w[TT_MAX_NODES];
+    };
+    double A[RMAX * (RMAX + 1)];   // factorisation stage
+  };
+  double lcol[RMAX];
+  int perm[RMAX];
+  int rowidx[RMAX];
+  int piv;
+};
+
+template <int MAXM, int RMAX>
+__global__ __launch_bounds__(kBlock) void k_update(ProbDesc* __restrict__ P,
+                                                   const int2* __restrict__ tasks, int init) {
+  constexpr int LD = MAXM + 1;
+  constexpr int LA = RMAX + 1;
+  __shared__ UpdateSmem<MAXM, RMAX> sm;
+  const int2 tk = tasks[blockIdx.x];
+  const ProbDesc& p = P[tk.x];
+  const int c = tk.y, tid = threadIdx.x;
+  ProbState* st = p.st;
+  if (st->done) return;
+  const int m = p.m, n = p.n, R = p.R;
+  const FamilyArgs fa = family_args(p);
+  const bool hasL = c >= 1, hasR = c <= m - 2;
+  const int accL = (!init && hasL) ? p.piv[c - 1].acc : 0;
+  const int accR = (!init && hasR) ? p.piv[c].acc : 0;
+  const int rL_com = hasL ? p.rank[c - 1] : 1;
+  const int rR_com = hasR ? p.rank[c] : 1;
+  const int rL_old = init ? 0 : rL_com, rL_new = rL_com + accL;
+  const int rR_old = init ? 0 : rR_com, rR_new = rR_com + accR;
+
+  // ---- append the accepted pivots (each set element is written by exactly one workgroup)
+  if (accL) {   // new element of I_<=c-1: (alpha*, i*) with alpha* in I_<=c-2
+    const int bl = c - 1;
+    const int row = p.piv[bl].row;
+    const int al = row / n, i = row - al * n;
+    const size_t dst = (size_t)bl * R + rL_old;
+    for (int k = tid; k < bl; k += blockDim.x) p.Lx[dst * m + k] = p.Lx[((size_t)(bl - 1) * R + al) * m + k];
+    if (tid == 0) {
+      p.Lpar[dst] = al;
+      p.Lnode[dst] = i;
+      p.Lx[dst * m + bl] = p.t[i];
+      p.Lw[dst] = (bl >= 1 ? p.Lw[(size_t)(bl - 1) * R + al] : 1.0) * p.w[i];
+    }
+  }
+  if (accR) {   // new element of I_>c: (j*, beta*) with beta* in I_>c+1
+    const int rRR = (c + 1 <= m - 2) ? p.rank[c + 1] : 1;
+    const int col = p.piv[c].col;
+    const int j = col / rRR, be = col - j * rRR;
+    const size_t dst = (size_t)c * R + rR_old;
+    for (int k = c + 2 + tid; k < m; k += blockDim.x)
+      p.Rx[dst * m + k] = p.Rx[((size_t)(c + 1) * R + be) * m + k];
+    if (tid == 0) {
+      p.Rnode[dst] = j;
+      p.Rpar[dst] = be;
+      p.Rx[dst * m + c + 1] = p.t[j];
+      p.Rw[dst] = p.w[j] * ((c + 1 <= m - 2) ? p.Rw[(size_t)(c + 1) * R + be] : 1.0);
+    }
+  }
+  __syncthreads();
+  // ---- stage I_<=c-1 and I_>c coordinates
+  for (int e = tid; e < rL_new * c; e += blockDim.x) {
+    int a = e / c, k = e % c;
+    sm.Lx[a * LD + k] = p.Lx[((size_t)(c - 1) * R + a) * m + k];
+  }
+  const int nright = m - c - 1;
+  for (int e = tid; e < rR_new * nright; e += blockDim.x) {
+    int a = e / nright, k = c + 1 + e % nright;
+    sm.Rx[a * LD + k] = p.Rx[((size_t)c * R + a) * m + k];
+  }
+  for (int a = tid; a < rL_new; a += blockDim.x) sm.Lw[a] = hasL ? p.Lw[(size_t)(c - 1) * R + a] : 1.0;
+  for (int a = tid; a < rR_new; a += blockDim.x) sm.Rw[a] = hasR ? p.Rw[(size_t)c * R + a] : 1.0;
+  for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = p.t[i]; sm.w[i] = p.w[i]; }
+  __syncthreads();
+
+  // ---- evaluate the new entries of F_c = B(I_<=c-1, i_c, I_>c)
+  double* __restrict__ Fc = p.F + p.Foff[c];
+  const int cc = colcap(p, c);
+  const int nA = (rL_new - rL_old) * n * rR_new;            // new rows (all columns)
+  const int nBc = rR_new - rR_old;
+  const int nB = rL_old * n * nBc;                          // new column (old rows)
+  bool bad = false;
+  for (int e = tid; e < nA + nB; e += blockDim.x) {
+    int al, i, be;
+    if (e < nA) {
+      al = rL_old + e / (n * rR_new);
+      const int rem = e % (n * rR_new);
+      i = rem / rR_new;
+      be = rem % rR_new;
+    } else {
+      const int e2 = e - nA;
+      al = e2 / (n * nBc);
+      const int rem = e2 % (n * nBc);
+      i = rem / nBc;
+      be = rR_old + rem % nBc;
+    }
+    double y[MAXM];
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+      double v = 0.0;
+      if (k < m) {
+        v = (k < c) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
+        v = (k == c) ? sm.t[i] : v;
+      }
+      y[k] = v;
+    }
+    const double W = (sm.Lw[al] * sm.w[i]) * sm.Rw[be];
+    const double v = W * integrand<MAXM>(fa, y);
+    bad |= !isfinite(v);
+    Fc[((size_t)al * n + i) * cc + be] = v;
+  }
+  const int any_bad = __syncthreads_or(bad);
+  if (tid == 0) {
+    atomicAdd(&st->evals, (unsigned long long)(nA + nB));
+    if (any_bad) atomicOr(&st->err_flags, 1);
+  }
+
+  double* __restrict__ S = p.S + (size_t)c * R * R;
+  if (!hasR) {   // last core: S(alpha) = sum_i F(alpha, i)
+    for (int al = tid; al < rL_new; al += blockDim.x) {
+      double s = 0.0;
+#pragma unroll 16
+      for (int i = 0; i < n; ++i) s += Fc[(size_t)al * n + i];
+      S[(size_t)al * R] = s;
+    }
+    return;
+  }
+
+  // ---- C_c = F_c M_c^-1 with M_c = rows I_<=c of F_c (GEPP of M_c^T in LDS)
+  const int r = rR_new;
+  const int N = rL_new * n;
+  if (r > RMAX) {    // the host picks RMAX >= any rank reachable this sweep
+    if (tid == 0) atomicOr(&st->err_flags, 8);
+    return;
+  }
+  __syncthreads();   // the evaluation stage's LDS is reused for the factorisation
+  for (int e = tid; e < RMAX * LA; e += blockDim.x) sm.A[e] = 0.0;
+  if (tid < r) {
+    int ri;
+    if (tid < rR_com) ri = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
+    else ri = p.piv[c].row;    // the element appended to I_<=c this sweep
+    sm.rowidx[tid] = ri;
+    sm.perm[tid] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int a = e / r, q = e % r;            // M[a][q] = F_c(rowidx[a], q) -> A[q][a]
+    sm.A[q * LA + a] = Fc[(size_t)sm.rowidx[a] * cc + q];
+  }
+  __syncthreads();
+  bool singular = false;
+  for (int k = 0; k < r; ++k) {
+    if (tid < kWave) {   // wave 0: partial pivoting, first largest |A(i,k)| over i >= k
+      ArgMax a{-1.0, 0x7fffffff};
+      for (int i = k + tid; i < r; i += kWave) {
+        const double v = fabs(sm.A[i * LA + k]);
+        if (better(v, i, a.v, a.idx)) { a.v = v; a.idx = i; }
+      }
+      a = wave_argmax(a);
+      if (tid == 0) {
+        const int pv = a.v >= 0.0 ? a.idx : k;
+        sm.piv = pv;
+        if (pv != k) { int tmp = sm.perm[k]; sm.perm[k] = sm.perm[pv]; sm.perm[pv] = tmp; }
+      }
+    }
+    __syncthreads();
+    const int pv = sm.piv;
+    if (pv != k && tid < r) {
+      const double tmp = sm.A[k * LA + tid];
+      sm.A[k * LA + tid] = sm.A[pv * LA + tid];
+      sm.A[pv * LA + tid] = tmp;
+    }
+    __syncthreads();
+    const double dg = sm.A[k * LA + k];
+    if (dg == 0.0) singular = true;
+    const int w = r - k - 1;
+    if (tid < w) sm.lcol[tid] = sm.A[(k + 1 + tid) * LA + k] / dg;
+    __syncthreads();
+    for (int e = tid; e < w * (w + 1); e += blockDim.x) {
+      const int i = k + 1 + e / (w + 1), j = k + e % (w + 1);
+      const double l = sm.lcol[i - k - 1];
+      if (j == k) sm.A[i * LA + k] = l;
+      else sm.A[i * LA + j] = fma(-l, sm.A[k * LA + j], sm.A[i * LA + j]);
+    }
+    __syncthreads();
+  }
+  if (singular && tid == 0) atomicOr(&st->err_flags, 2);
+
+  double* __restrict__ Cc = p.C + p.Coff[c];
+  const size_t ldC = (size_t)rowcap(p, c) * n;
+  for (int row = tid; row < N; row += blockDim.x) {
+    const double* __restrict__ f = Fc + (size_t)row * cc;
+    double x[RMAX];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) x[i] = (i < r) ? f[sm.perm[i]] : 0.0;
+#pragma unroll
+    for (int i = 1; i < RMAX; ++i) {
+      if (i < r) {
+        double s = x[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) s = fma(-sm.A[i * LA + j], x[j], s);
+        x[i] = s;
+      }
+    }
+#pragma unroll
+    for (int i = RMAX - 1; i >= 0; --i) {
+      if (i < r) {
+        double s = x[i];
+#pragma unroll
+        for (int j = i + 1; j < RMAX; ++j) s = fma(-sm.A[i * LA + j], x[j], s);
+        x[i] = s / sm.A[i * LA + i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i < r) Cc[(size_t)i * ldC + row] = x[i];
+  }
+  __syncthreads();
+  // ---- S_c(alpha, k) = sum_i C_c(alpha, i, k)
+  for (int e = tid; e < rL_new * r; e += blockDim.x) {
+    const int al = e / r, k = e % r;
+    const double* __restrict__ src = Cc + (size_t)k * ldC + (size_t)al * n;
+    double s = 0.0;
+#pragma unroll 16
+    for (int i = 0; i < n; ++i) s += src[i];
+    S[(size_t)al * R + k] = s;
+  }
+}
+
+// ------------------------------------------------------------ k_integral
+constexpr int kIntBlock = 256;
+constexpr int kIntStage = 6144;   // doubles of S staged in LDS at once (48 KiB)
+
+__global__ __launch_bounds__(kIntBlock) void k_integral(ProbDesc* __restrict__ P, int init) {
+  const ProbDesc& p = P[blockIdx.x];
+  ProbState* st = p.st;
+  if (st->done) return;
+  __shared__ double v[TT_MAX_RANK], v2[TT_MAX_RANK];
+  __shared__ double stage[kIntStage];
+  __shared__ int s_rank[TT_MAX_MODES];
+  __shared__ int s_off[TT_MAX_MODES + 1];
+  const int m = p.m, R = p.R, nb = p.nbonds, tid = threadIdx.x;
+  // commit the ranks: r_b += accepted_b (one thread per bond)
+  int acc = 0, r = 0;
+  if (tid < nb) {
+    acc = init ? 0 : p.piv[tid].acc;
+    r = p.rank[tid] + acc;
+    p.rank[tid] = r;
+    s_rank[tid] = r;
+  }
+  const int nacc = __syncthreads_count(acc);
+  const int below_cap = __syncthreads_or(tid < nb && r < R);
+  int maxr = 1;
+  for (int b = 0; b < nb; ++b) maxr = max(maxr, s_rank[b]);
+  // v = S_0 (1 x r_0), then v <- v S_c for c = 1..m-1 (2m-1 matrices, inverses in C)
+  for (int k = tid; k < s_rank[0]; k += blockDim.x) v[k] = p.S[k];
+  int c0 = 1;
+  while (c0 < m) {
+    // stage as many consecutive S_c as fit, all loads in flight together
+    if (tid == 0) {
+      int off = 0, c = c0;
+      s_off[0] = 0;
+      while (c < m) {
+        const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
+        if (off + rl * rr > kIntStage && c > c0) break;
+        off += rl * rr;
+        s_off[c - c0 + 1] = off;
+        ++c;
+      }
+      s_off[TT_MAX_MODES] = c;
+    }
+    __syncthreads();
+    const int c1 = s_off[TT_MAX_MODES];
+    for (int c = c0; c < c1; ++c) {
+      const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
+      const double* __restrict__ S = p.S + (size_t)c * R * R;
+      double* dst = stage + s_off[c - c0];
+      for (int e = tid; e < rl * rr; e += blockDim.x) dst[e] = S[(size_t)(e / rr) * R + e % rr];
+    }
+    __syncthreads();
+    for (int c = c0; c < c1; ++c) {
+      const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
+      const double* Sc = stage + s_off[c - c0];
+      for (int k = tid; k < rr; k += blockDim.x) {
+        double s = 0.0;
+        for (int a = 0; a < rl; ++a) s = fma(v[a], Sc[a * rr + k], s);
+        v2[k] = s;
+      }
+      __syncthreads();
+      for (int k = tid; k < rr; k += blockDim.x) v[k] = v2[k];
+      __syncthreads();
+    }
+    c0 = c1;
+  }
+  if (tid != 0) return;
+  const double value = v[0];
+  st->max_rank = maxr;
+  if (!isfinite(value)) st->err_flags |= 1;
+  if (init) {
+    p.hist[0] = value;
+    st->value = value;
+    return;
+  }
+  const double prev = p.hist[st->sweeps];
+  const double rel = value != 0.0 ? fabs(value - prev) / fabs(value) : __builtin_huge_val();
+  const double prev_rel = st->rel;
+  const int s = st->sweeps + 1;
+  st->sweeps = s;
+  p.hist[s] = value;
+  st->value = value;
+  st->rel = rel;
+  st->nacc = nacc;
+  if (rel <= p.tol && prev_rel <= p.tol) {
+    st->done = 1;
+    st->reason = TT_STOP_CONVERGED;
+  } else if (nacc == 0) {
+    st->done = 1;
+    st->reason = below_cap ? TT_STOP_CONVERGED : TT_STOP_RANK_CAP;
+  } else if (s >= p.max_sweeps) {
+    st->done = 1;
+    st->reason = TT_STOP_MAX_SWEEPS;
+  }
+  if (st->err_flags) {
+    st->done = 1;
+    if (st->reason == TT_RUNNING) st->reason = TT_STOP_CONVERGED;
+  }
+}
+
+// ------------------------------------------------------- standalone eval
+template <int MAXM>
+__global__ __launch_bounds__(kBlock) void k_eval_points(FamilyArgs fa, const double* __restrict__ t,
+                                                        const double* __restrict__ w,
+                                                        const int32_t* __restrict__ idx,
+                                                        int64_t npts, double* __restrict__ out) {
+  const int m = fa.m;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < npts;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    double y[MAXM];
+    double W = 1.0;
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+      y[k] = 0.0;
+      if (k < m) {
+        const int ik = idx[q * m + k];
+        y[k] = t[ik];
+        W = W * w[ik];
+      }
+    }
+    out[q] = W * integrand<MAXM>(fa, y);
+  }
+}
+
+// Fibre set I_left x [n] x I_right at mode `pos`: one point per lane, the
+// index rows and node tables staged in LDS, output ordered (alpha, i, beta).
+template <int MAXM>
+__global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, const double* __restrict__ t,
+                                                        const double* __restrict__ w, int pos,
+                                                        const int32_t* __restrict__ left, int rl,
+                                                        const int32_t* __restrict__ right, int rr,
+                                                        double* __restrict__ out) {
+  constexpr int LD = MAXM + 1;
+  __shared__ double sLx[TT_MAX_RANK * LD], sRx[TT_MAX_RANK * LD];
+  __shared__ double sLw[TT_MAX_RANK], sRw[TT_MAX_RANK];
+  __shared__ double st[TT_MAX_NODES], sw[TT_MAX_NODES];
+  const int m = fa.m, tid = threadIdx.x, nr = m - pos - 1;
+  for (int i = tid; i < n; i += blockDim.x) { st[i] = t[i]; sw[i] = w[i]; }
+  __syncthreads();
+  for (int a = tid; a < rl; a += blockDim.x) {
+    double ww = 1.0;
+    for (int k = 0; k < pos; ++k) {
+      const int ik = left[a * pos + k];
+      sLx[a * LD + k] = st[ik];
+      ww = ww * sw[ik];
+    }
+    sLw[a] = ww;
+  }
+  for (int a = tid; a < rr; a += blockDim.x) {
+    double ww = 1.0;
+    for (int k = nr - 1; k >= 0; --k) {
+      const int ik = right[a * nr + k];
+      sRx[a * LD + pos + 1 + k] = st[ik];
+      ww = sw[ik] * ww;
+    }
+    sRw[a] = ww;
+  }
+  __syncthreads();
+  const int64_t total = (int64_t)rl * n * rr;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + tid; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int be = (int)(q % rr);
+    const int64_t rest = q / rr;
+    const int i = (int)(rest % n);
+    const int al = (int)(rest / n);
+    double y[MAXM];
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+      double v = 0.0;
+      if (k < m) {
+        v = (k < pos) ? sLx[al * LD + k] : sRx[be * LD + k];
+        v = (k == pos) ? st[i] : v;
+      }
+      y[k] = v;
+    }
+    const double W = (sLw[al] * sw[i]) * sRw[be];
+    out[q] = W * integrand<MAXM>(fa, y);
+  }
+}
+
+}  // namespace ttx

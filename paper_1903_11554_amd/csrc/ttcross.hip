@@ -1,0 +1,785 @@
+// Host side of the gfx950 TT cross library: the C ABI of include/ttcross.h.
+// The host validates problems, lays out one device arena per job, and
+// enqueues the kernels of tt_kernels.hpp; it never computes any part of the
+// method itself.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "tt_kernels.hpp"
+
+using namespace ttx;
+
+#define TT_HIP(call)                                    \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) {                             \
+      last_hip_error() = e_;                            \
+      return TT_EDEVICE;                                \
+    }                                                   \
+  } while (0)
+
+static hipError_t& last_hip_error() {
+  static thread_local hipError_t e = hipSuccess;
+  return e;
+}
+
+// kernel kinds timed by the optional event profiler
+enum { KK_SEARCH = 0, KK_UPDATE = 1, KK_INTEGRAL = 2, KK_START = 3, KK_GL = 4, KK_EVAL_POINTS = 5,
+       KK_EVAL_FIBERS = 6, KK_COUNT = 7 };
+
+struct tt_ctx {
+  int device = 0;
+  bool profiling = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;   // kind, (start, stop)
+  std::vector<hipEvent_t> pool;
+  double kernel_ms[KK_COUNT] = {0};
+  long long kernel_launches[KK_COUNT] = {0};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::mutex mu;
+  std::map<int, std::pair<double*, double*>> gl;   // n -> device (t, w)
+  double* params = nullptr;                        // device scratch for synthetic params
+  size_t params_cap = 0;
+  std::multimap<size_t, void*> arenas;             // freed job arenas kept for reuse
+  size_t arena_bytes_cached = 0;
+};
+
+// Arenas of freed jobs are kept by the context (up to this many bytes) and
+// handed to later jobs of the same or smaller size, so a stream of jobs does
+// not call hipMalloc/hipFree every time.
+static const size_t kArenaCacheBytes = size_t(4) << 30;
+
+struct tt_job {
+  tt_ctx* ctx = nullptr;
+  int nprob = 0;
+  std::vector<tt_problem> probs;
+  std::vector<int> modes;
+  std::vector<ProbDesc> hdesc;
+  void* arena = nullptr;
+  size_t bytes = 0;
+  ProbDesc* ddesc = nullptr;
+  int2* dbond = nullptr;
+  int nbond = 0;
+  int2* dcore = nullptr;
+  int ncore = 0;
+  int maxm = 0, maxR = 1;
+  int launched = 0;       // sweeps enqueued so far
+  int max_sweeps_all = 0;
+  ProbState* dstate = nullptr;
+  std::vector<char> image;   // host image of the table region (source of the async upload)
+};
+
+namespace {
+
+// Bracket one kernel launch with a pair of events on the context stream.
+struct Timed {
+  tt_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!c->pool.empty()) {
+      e = c->pool.back();
+      c->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  Timed(tt_ctx* ctx, int k) : c(ctx), kind(k) {
+    if (c->profiling) {
+      a = take();
+      b = take();
+      if (a && b) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timed() {
+    if (c->profiling && a && b) {
+      (void)hipEventRecord(b, c->stream);
+      c->pending.push_back({kind, {a, b}});
+    }
+  }
+};
+
+void drain_profile(tt_ctx* c) {
+  if (c->pending.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& pe : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      c->kernel_ms[pe.first] += ms;
+      c->kernel_launches[pe.first] += 1;
+    }
+    c->pool.push_back(pe.second.first);
+    c->pool.push_back(pe.second.second);
+  }
+  c->pending.clear();
+}
+
+int modes_of(const tt_problem& p) {
+  switch (p.integrand) {
+    case TT_ISING_C: case TT_ISING_D: case TT_ISING_E: return p.d - 1;
+    case TT_ISING_C_U: case TT_ISING_D_U: case TT_PROD_EXP: case TT_SUM2_EXP_COS: return p.d;
+    default: return -1;
+  }
+}
+
+bool is_synthetic(int f) { return f == TT_PROD_EXP || f == TT_SUM2_EXP_COS; }
+
+tt_status validate(const tt_problem* p) {
+  if (!p) return TT_EINVAL;
+  const int m = modes_of(*p);
+  if (m < 0 || p->d < 1 || m > TT_MAX_MODES) return TT_EINVAL;
+  if (p->n_nodes < 1 || p->n_nodes > TT_MAX_NODES) return TT_EINVAL;
+  if (p->rank_cap < 1 || p->rank_cap > TT_MAX_RANK) return TT_EINVAL;
+  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return TT_EINVAL;
+  if (p->precision != TT_FP64) return TT_EINVAL;
+  if (p->max_sweeps < 0 || p->max_sweeps > 1024) return TT_EINVAL;
+  if (is_synthetic(p->integrand) && !p->params) return TT_EINVAL;
+  // the superblock size r n n r must fit a 32-bit sample index
+  const double sb = (double)p->rank_cap * p->n_nodes * p->n_nodes * p->rank_cap;
+  if (sb >= 4294967296.0) return TT_EINVAL;
+  return TT_OK;
+}
+
+int max_sweeps_of(const tt_problem& p) { return p.max_sweeps > 0 ? p.max_sweeps : 4 * p.rank_cap; }
+
+// byte layout of one problem inside a job arena
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = (off + 255) & ~size_t(255);
+    off = o + bytes;
+    return o;
+  }
+};
+
+struct ProbOffsets {
+  size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, S, rank, piv, scale, log, hist, start;
+  std::vector<int64_t> foff, coff;
+};
+
+ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
+  ProbOffsets o;
+  const int m = modes_of(p), n = p.n_nodes, R = p.rank_cap;
+  const int nb = m > 1 ? m - 1 : 0;
+  const int ms = max_sweeps_of(p);
+  const size_t D = sizeof(double), I = sizeof(int32_t);
+  o.Lpar = L.take((size_t)nb * R * I);
+  o.Lnode = L.take((size_t)nb * R * I);
+  o.Rpar = L.take((size_t)nb * R * I);
+  o.Rnode = L.take((size_t)nb * R * I);
+  o.Lx = L.take((size_t)nb * R * m * D);
+  o.Rx = L.take((size_t)nb * R * m * D);
+  o.Lw = L.take((size_t)nb * R * D);
+  o.Rw = L.take((size_t)nb * R * D);
+  int64_t fsz = 0, csz = 0;
+  for (int c = 0; c < m; ++c) {
+    const int rc = c == 0 ? 1 : R, cc = c == m - 1 ? 1 : R;
+    o.foff.push_back(fsz);
+    fsz += (int64_t)rc * n * cc;
+  }
+  for (int b = 0; b < nb; ++b) {
+    const int rc = b == 0 ? 1 : R;
+    o.coff.push_back(csz);
+    csz += (int64_t)R * rc * n;
+  }
+  o.F = L.take((size_t)fsz * D);
+  o.C = L.take((size_t)csz * D);
+  o.S = L.take((size_t)(m > 0 ? m : 1) * R * R * D);
+  o.rank = L.take((size_t)(nb > 0 ? nb : 1) * I);
+  o.piv = L.take((size_t)(nb > 0 ? nb : 1) * sizeof(PivRec));
+  o.scale = L.take((size_t)(nb > 0 ? nb : 1) * D);
+  o.log = L.take((size_t)ms * (nb > 0 ? nb : 1) * sizeof(PivRec));
+  o.hist = L.take((size_t)(ms + 1) * D);
+  o.start = L.take((size_t)(m > 0 ? m : 1) * I);
+  return o;
+}
+
+int bucket_m(int m) { return m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : 32; }
+int bucket_r(int r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : 64; }
+
+double four_over_fact(int m) {
+  double f = 1.0;
+  for (int k = 2; k <= m; ++k) f *= k;
+  return 4.0 / f;
+}
+
+template <int MAXM>
+void launch_search(tt_job* j) {
+  Timed tm(j->ctx, KK_SEARCH);
+  hipLaunchKernelGGL(k_search<MAXM>, dim3(j->nbond), dim3(kSearchBlock), 0, j->ctx->stream, j->ddesc,
+                     (const int2*)j->dbond);
+}
+template <int MAXM, int RMAX>
+void launch_update(tt_job* j, int init) {
+  Timed tm(j->ctx, KK_UPDATE);
+  hipLaunchKernelGGL((k_update<MAXM, RMAX>), dim3(j->ncore), dim3(kBlock), 0, j->ctx->stream,
+                     j->ddesc, (const int2*)j->dcore, init);
+}
+template <int MAXM>
+void launch_update_r(tt_job* j, int rb, int init) {
+  switch (rb) {
+    case 4: launch_update<MAXM, 4>(j, init); break;
+    case 8: launch_update<MAXM, 8>(j, init); break;
+    case 16: launch_update<MAXM, 16>(j, init); break;
+    case 32: launch_update<MAXM, 32>(j, init); break;
+    default: launch_update<MAXM, 64>(j, init); break;
+  }
+}
+
+void enqueue_update(tt_job* j, int rb, int init) {
+  switch (bucket_m(j->maxm)) {
+    case 4: launch_update_r<4>(j, rb, init); break;
+    case 8: launch_update_r<8>(j, rb, init); break;
+    case 16: launch_update_r<16>(j, rb, init); break;
+    default: launch_update_r<32>(j, rb, init); break;
+  }
+}
+void enqueue_search(tt_job* j) {
+  switch (bucket_m(j->maxm)) {
+    case 4: launch_search<4>(j); break;
+    case 8: launch_search<8>(j); break;
+    case 16: launch_search<16>(j); break;
+    default: launch_search<32>(j); break;
+  }
+}
+
+tt_status enqueue_sweeps(tt_job* j, int n_sweeps) {
+  for (int s = 0; s < n_sweeps; ++s) {
+    if (j->launched >= j->max_sweeps_all) break;
+    if (j->nbond > 0) {
+      const int rb = bucket_r(std::min(j->maxR, j->launched + 2));
+      enqueue_search(j);
+      enqueue_update(j, rb, 0);
+      Timed tm(j->ctx, KK_INTEGRAL);
+      hipLaunchKernelGGL(k_integral, dim3(j->nprob), dim3(kIntBlock), 0, j->ctx->stream, j->ddesc, 0);
+    }
+    ++j->launched;
+  }
+  TT_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+tt_status read_states(tt_job* j, std::vector<ProbState>& st) {
+  st.resize(j->nprob);
+  TT_HIP(hipMemcpyAsync(st.data(), j->dstate, sizeof(ProbState) * j->nprob, hipMemcpyDeviceToHost,
+                        j->ctx->stream));
+  TT_HIP(hipStreamSynchronize(j->ctx->stream));
+  return TT_OK;
+}
+
+void fill_info(const ProbState& s, tt_info* out) {
+  out->sweeps = s.sweeps;
+  out->max_rank = s.max_rank;
+  out->reason = s.done ? s.reason : TT_RUNNING;
+  out->err_flags = s.err_flags;
+  out->evals = (int64_t)s.evals;
+  out->value = s.value;
+  out->rel_change = s.rel;
+}
+
+tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w) {
+  auto it = ctx->gl.find(n);
+  if (it == ctx->gl.end()) {
+    double *dt = nullptr, *dw = nullptr;
+    TT_HIP(hipMalloc(&dt, n * sizeof(double)));
+    TT_HIP(hipMalloc(&dw, n * sizeof(double)));
+    {
+      Timed tm(ctx, KK_GL);
+      hipLaunchKernelGGL(k_gl, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, dt, dw);
+    }
+    TT_HIP(hipGetLastError());
+    it = ctx->gl.emplace(n, std::make_pair(dt, dw)).first;
+  }
+  *t = it->second.first;
+  *w = it->second.second;
+  return TT_OK;
+}
+
+tt_status family_for(tt_ctx* ctx, const tt_problem* p, FamilyArgs* fa) {
+  const int m = modes_of(*p);
+  fa->family = p->integrand;
+  fa->m = m;
+  fa->four_over_mfact = four_over_fact(m);
+  fa->a = fa->b = nullptr;
+  if (is_synthetic(p->integrand)) {
+    const size_t need = 2 * (size_t)m * sizeof(double);
+    if (need > ctx->params_cap) {
+      TT_HIP(hipStreamSynchronize(ctx->stream));
+      if (ctx->params) TT_HIP(hipFree(ctx->params));
+      ctx->params = nullptr;
+      ctx->params_cap = 0;
+      TT_HIP(hipMalloc(&ctx->params, need));
+      ctx->params_cap = need;
+    }
+    // synchronous copy: earlier kernels may still read the old parameters
+    TT_HIP(hipStreamSynchronize(ctx->stream));
+    TT_HIP(hipMemcpy(ctx->params, p->params, need, hipMemcpyHostToDevice));
+    fa->a = ctx->params;
+    fa->b = ctx->params + m;
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tt_status_string(tt_status s) {
+  switch (s) {
+    case TT_OK: return "TT_OK";
+    case TT_CONVERGED: return "TT_CONVERGED";
+    case TT_NOT_CONVERGED: return "TT_NOT_CONVERGED";
+    case TT_EINVAL: return "TT_EINVAL: invalid argument";
+    case TT_ENOMEM: return "TT_ENOMEM: out of device memory";
+    case TT_EDEVICE: return "TT_EDEVICE: HIP runtime error";
+    case TT_ENUMERIC: return "TT_ENUMERIC: non-finite or singular values";
+  }
+  return "unknown tt_status";
+}
+
+tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
+  if (!out) return TT_EINVAL;
+  int count = 0;
+  TT_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return TT_EINVAL;
+  TT_HIP(hipSetDevice(device));
+  tt_ctx* c = new (std::nothrow) tt_ctx;
+  if (!c) return TT_ENOMEM;
+  c->device = device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return TT_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return TT_OK;
+}
+
+void tt_ctx_destroy(tt_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (auto& kv : c->gl) {
+    hipFree(kv.second.first);
+    hipFree(kv.second.second);
+  }
+  if (c->params) hipFree(c->params);
+  for (auto& kv : c->arenas) hipFree(kv.second);
+  for (auto& pe : c->pending) {
+    hipEventDestroy(pe.second.first);
+    hipEventDestroy(pe.second.second);
+  }
+  for (hipEvent_t e : c->pool) hipEventDestroy(e);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+tt_status tt_ctx_profile(tt_ctx* c, int32_t enable) {
+  if (!c) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(c->mu);
+  drain_profile(c);
+  c->profiling = enable != 0;
+  for (int k = 0; k < KK_COUNT; ++k) {
+    c->kernel_ms[k] = 0.0;
+    c->kernel_launches[k] = 0;
+  }
+  return TT_OK;
+}
+
+tt_status tt_ctx_kernel_time(tt_ctx* c, int32_t kind, int64_t* launches, double* total_ms) {
+  if (!c || kind < 0 || kind >= KK_COUNT || !launches || !total_ms) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(c->mu);
+  drain_profile(c);
+  *launches = c->kernel_launches[kind];
+  *total_ms = c->kernel_ms[kind];
+  return TT_OK;
+}
+
+tt_status tt_ctx_synchronize(tt_ctx* c) {
+  if (!c) return TT_EINVAL;
+  TT_HIP(hipStreamSynchronize(c->stream));
+  return TT_OK;
+}
+
+size_t tt_job_footprint(const tt_problem* p) {
+  if (validate(p) != TT_OK) return 0;
+  Layout L;
+  layout_problem(*p, L);
+  L.take(sizeof(ProbState));
+  L.take(sizeof(ProbDesc));
+  return L.off;
+}
+
+tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, tt_job** out) {
+  if (!ctx || !problems || count < 1 || !out) return TT_EINVAL;
+  for (int k = 0; k < count; ++k)
+    if (validate(&problems[k]) != TT_OK) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  TT_HIP(hipSetDevice(ctx->device));
+  tt_job* j = new (std::nothrow) tt_job;
+  if (!j) return TT_ENOMEM;
+  j->ctx = ctx;
+  j->nprob = count;
+  j->probs.assign(problems, problems + count);
+  // Gauss--Legendre tables are computed once per node count and shared by all jobs of the context
+  std::vector<std::pair<double*, double*>> gl(count);
+  for (int k = 0; k < count; ++k) {
+    tt_status s = gl_table(ctx, problems[k].n_nodes, &gl[k].first, &gl[k].second);
+    if (s != TT_OK) {
+      delete j;
+      return s;
+    }
+  }
+  // ---- layout: a small table region (uploaded in one copy), then the bulk per-problem state
+  std::vector<int2> bond_tasks, core_tasks;
+  for (int k = 0; k < count; ++k) {
+    const int m = modes_of(problems[k]);
+    j->modes.push_back(m);
+    j->maxm = std::max(j->maxm, m);
+    j->maxR = std::max(j->maxR, problems[k].rank_cap);
+    j->max_sweeps_all = std::max(j->max_sweeps_all, max_sweeps_of(problems[k]));
+    if (m >= 2) {
+      for (int b = 0; b < m - 1; ++b) bond_tasks.push_back(make_int2(k, b));
+      for (int c = 0; c < m; ++c) core_tasks.push_back(make_int2(k, c));
+    }
+  }
+  Layout L;
+  const size_t st_off = L.take(sizeof(ProbState) * count);
+  const size_t desc_off = L.take(sizeof(ProbDesc) * count);
+  const size_t bond_off = L.take(sizeof(int2) * (bond_tasks.size() + 1));
+  const size_t core_off = L.take(sizeof(int2) * (core_tasks.size() + 1));
+  std::vector<ProbOffsets> offs;
+  std::vector<size_t> foff_at(count), coff_at(count), par_at(count);
+  for (int k = 0; k < count; ++k) {
+    Layout pl;
+    offs.push_back(layout_problem(problems[k], pl));
+    const int m = modes_of(problems[k]);
+    foff_at[k] = L.take(sizeof(int64_t) * std::max(m, 1));
+    coff_at[k] = L.take(sizeof(int64_t) * std::max(m - 1, 1));
+    par_at[k] = L.take(sizeof(double) * 2 * std::max(m, 1));
+  }
+  const size_t table_bytes = L.take(0);
+  std::vector<size_t> bases;
+  for (int k = 0; k < count; ++k) {
+    Layout pl;
+    layout_problem(problems[k], pl);
+    bases.push_back(L.take(pl.off));
+  }
+  j->bytes = L.off;
+  // ---- device arena: reuse a cached one of a suitable size, else allocate
+  auto it = ctx->arenas.lower_bound(j->bytes);
+  if (it != ctx->arenas.end() && it->first <= 2 * j->bytes + (size_t(1) << 20)) {
+    j->arena = it->second;
+    j->bytes = it->first;
+    ctx->arena_bytes_cached -= it->first;
+    ctx->arenas.erase(it);
+  } else if (hipMalloc(&j->arena, j->bytes) != hipSuccess) {
+    delete j;
+    return TT_ENOMEM;
+  }
+  char* base = (char*)j->arena;
+  auto fail = [&](tt_status s) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(j->arena);
+    delete j;
+    return s;
+  };
+  j->dstate = (ProbState*)(base + st_off);
+  j->ddesc = (ProbDesc*)(base + desc_off);
+  j->dbond = (int2*)(base + bond_off);
+  j->dcore = (int2*)(base + core_off);
+  j->nbond = (int)bond_tasks.size();
+  j->ncore = (int)core_tasks.size();
+  j->image.assign(table_bytes, 0);
+  char* img = j->image.data();
+  for (int k = 0; k < count; ++k) {
+    const tt_problem& p = problems[k];
+    const ProbOffsets& o = offs[k];
+    char* pb = base + bases[k];
+    ProbDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.family = p.integrand;
+    d.m = modes_of(p);
+    d.n = p.n_nodes;
+    d.R = p.rank_cap;
+    d.max_sweeps = max_sweeps_of(p);
+    d.nbonds = d.m > 1 ? d.m - 1 : 0;
+    d.tol = p.tol;
+    d.four_over_mfact = four_over_fact(d.m);
+    d.seed = p.seed;
+    d.t = gl[k].first;
+    d.w = gl[k].second;
+    d.pa = (double*)(base + par_at[k]);
+    d.pb = d.pa + std::max(d.m, 1);
+    d.Lpar = (int32_t*)(pb + o.Lpar);
+    d.Lnode = (int32_t*)(pb + o.Lnode);
+    d.Rpar = (int32_t*)(pb + o.Rpar);
+    d.Rnode = (int32_t*)(pb + o.Rnode);
+    d.Lx = (double*)(pb + o.Lx);
+    d.Rx = (double*)(pb + o.Rx);
+    d.Lw = (double*)(pb + o.Lw);
+    d.Rw = (double*)(pb + o.Rw);
+    d.F = (double*)(pb + o.F);
+    d.Foff = (int64_t*)(base + foff_at[k]);
+    d.C = (double*)(pb + o.C);
+    d.Coff = (int64_t*)(base + coff_at[k]);
+    d.S = (double*)(pb + o.S);
+    d.rank = (int32_t*)(pb + o.rank);
+    d.piv = (PivRec*)(pb + o.piv);
+    d.scale = (double*)(pb + o.scale);
+    d.log = (PivRec*)(pb + o.log);
+    d.hist = (double*)(pb + o.hist);
+    d.start = (int32_t*)(pb + o.start);
+    d.st = j->dstate + k;
+    j->hdesc.push_back(d);
+    if (!o.foff.empty()) std::memcpy(img + foff_at[k], o.foff.data(), o.foff.size() * sizeof(int64_t));
+    if (!o.coff.empty()) std::memcpy(img + coff_at[k], o.coff.data(), o.coff.size() * sizeof(int64_t));
+    if (is_synthetic(p.integrand)) {
+      std::memcpy(img + par_at[k], p.params, d.m * sizeof(double));
+      std::memcpy(img + par_at[k] + std::max(d.m, 1) * sizeof(double), p.params + d.m, d.m * sizeof(double));
+    }
+  }
+  std::memcpy(img + desc_off, j->hdesc.data(), sizeof(ProbDesc) * count);
+  if (!bond_tasks.empty()) std::memcpy(img + bond_off, bond_tasks.data(), sizeof(int2) * bond_tasks.size());
+  if (!core_tasks.empty()) std::memcpy(img + core_off, core_tasks.data(), sizeof(int2) * core_tasks.size());
+  // one table upload (the host image lives until the job is freed), then the kernels, all in stream order
+  if (hipMemcpyAsync(base, img, table_bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+    return fail(TT_EDEVICE);
+  {
+    Timed tm(ctx, KK_START);
+    switch (bucket_m(j->maxm)) {
+      case 4: hipLaunchKernelGGL(k_start<4>, dim3(count), dim3(kBlock), 0, ctx->stream, j->ddesc); break;
+      case 8: hipLaunchKernelGGL(k_start<8>, dim3(count), dim3(kBlock), 0, ctx->stream, j->ddesc); break;
+      case 16: hipLaunchKernelGGL(k_start<16>, dim3(count), dim3(kBlock), 0, ctx->stream, j->ddesc); break;
+      default: hipLaunchKernelGGL(k_start<32>, dim3(count), dim3(kBlock), 0, ctx->stream, j->ddesc); break;
+    }
+  }
+  if (j->ncore > 0) {
+    enqueue_update(j, 4, 1);
+    Timed tm(ctx, KK_INTEGRAL);
+    hipLaunchKernelGGL(k_integral, dim3(count), dim3(kIntBlock), 0, ctx->stream, j->ddesc, 1);
+  }
+  if (hipGetLastError() != hipSuccess) return fail(TT_EDEVICE);
+  std::vector<ProbState> st;
+  if (read_states(j, st) != TT_OK) return fail(TT_EDEVICE);
+  for (int k = 0; k < count; ++k)
+    if (st[k].err_flags & (1 | 4)) return fail(TT_ENUMERIC);
+  *out = j;
+  return TT_OK;
+}
+
+tt_status tt_cross_sweep(tt_job* j, int32_t n_sweeps, tt_info* info) {
+  if (!j || n_sweeps < 0) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  TT_HIP(hipSetDevice(j->ctx->device));
+  tt_status s = enqueue_sweeps(j, n_sweeps);
+  if (s != TT_OK) return s;
+  std::vector<ProbState> st;
+  s = read_states(j, st);
+  if (s != TT_OK) return s;
+  bool all = true;
+  for (int k = 0; k < j->nprob; ++k) {
+    if (info) fill_info(st[k], &info[k]);
+    all = all && st[k].done;
+  }
+  return all ? TT_CONVERGED : TT_NOT_CONVERGED;
+}
+
+tt_status tt_cross_run(tt_job* j, tt_info* info) {
+  if (!j) return TT_EINVAL;
+  for (;;) {
+    const int before = j->launched;
+    tt_status s = tt_cross_sweep(j, 4, info);
+    if (s != TT_NOT_CONVERGED) return s;
+    if (j->launched == before) return TT_NOT_CONVERGED;   // max sweeps exhausted
+  }
+}
+
+tt_status tt_cross_integrate(tt_job* j, double* values, tt_info* info) {
+  if (!j || !values) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  TT_HIP(hipSetDevice(j->ctx->device));
+  std::vector<ProbState> st;
+  tt_status s = read_states(j, st);
+  if (s != TT_OK) return s;
+  for (int k = 0; k < j->nprob; ++k) {
+    values[k] = st[k].value;
+    if (info) fill_info(st[k], &info[k]);
+  }
+  return TT_OK;
+}
+
+tt_status tt_job_pivot_log(tt_job* j, int32_t k, tt_pivot* log, int64_t capacity, int64_t* written) {
+  if (!j || k < 0 || k >= j->nprob || !log || !written) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  std::vector<ProbState> st;
+  tt_status s = read_states(j, st);
+  if (s != TT_OK) return s;
+  const ProbDesc& d = j->hdesc[k];
+  const int64_t nrec = (int64_t)st[k].sweeps * d.nbonds;
+  if (nrec > capacity) return TT_EINVAL;
+  if (nrec > 0) TT_HIP(hipMemcpy(log, d.log, nrec * sizeof(PivRec), hipMemcpyDeviceToHost));
+  *written = nrec;
+  return TT_OK;
+}
+
+tt_status tt_job_history(tt_job* j, int32_t k, double* values, int64_t capacity, int64_t* written) {
+  if (!j || k < 0 || k >= j->nprob || !values || !written) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  std::vector<ProbState> st;
+  tt_status s = read_states(j, st);
+  if (s != TT_OK) return s;
+  const int64_t nv = st[k].sweeps + 1;
+  if (nv > capacity) return TT_EINVAL;
+  TT_HIP(hipMemcpy(values, j->hdesc[k].hist, nv * sizeof(double), hipMemcpyDeviceToHost));
+  *written = nv;
+  return TT_OK;
+}
+
+tt_status tt_job_index_sets(tt_job* j, int32_t k, int32_t* ranks, int32_t* nodes, int64_t capacity,
+                            int64_t* written) {
+  if (!j || k < 0 || k >= j->nprob || !ranks || !nodes || !written) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  TT_HIP(hipStreamSynchronize(j->ctx->stream));
+  const ProbDesc& d = j->hdesc[k];
+  const int m = d.m, R = d.R, nb = d.nbonds;
+  *written = 0;
+  if (nb == 0) return TT_OK;
+  std::vector<int32_t> rk(nb), lp(nb * R), ln(nb * R), rp(nb * R), rn(nb * R);
+  TT_HIP(hipMemcpy(rk.data(), d.rank, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(lp.data(), d.Lpar, nb * R * sizeof(int32_t), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(ln.data(), d.Lnode, nb * R * sizeof(int32_t), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(rp.data(), d.Rpar, nb * R * sizeof(int32_t), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(rn.data(), d.Rnode, nb * R * sizeof(int32_t), hipMemcpyDeviceToHost));
+  int64_t need = 0;
+  for (int b = 0; b < nb; ++b) need += (int64_t)rk[b] * m;
+  if (need > capacity) return TT_EINVAL;
+  // expand (parent, node) chains into full multi-indices
+  std::vector<std::vector<std::vector<int32_t>>> left(nb), right(nb);
+  for (int b = 0; b < nb; ++b) {
+    left[b].resize(rk[b]);
+    for (int a = 0; a < rk[b]; ++a) {
+      std::vector<int32_t> v;
+      if (b > 0) v = left[b - 1][lp[b * R + a]];
+      v.push_back(ln[b * R + a]);
+      left[b][a] = v;
+    }
+  }
+  for (int b = nb - 1; b >= 0; --b) {
+    right[b].resize(rk[b]);
+    for (int a = 0; a < rk[b]; ++a) {
+      std::vector<int32_t> v{rn[b * R + a]};
+      if (b < nb - 1) {
+        const auto& tail = right[b + 1][rp[b * R + a]];
+        v.insert(v.end(), tail.begin(), tail.end());
+      }
+      right[b][a] = v;
+    }
+  }
+  int64_t pos = 0;
+  for (int b = 0; b < nb; ++b) {
+    ranks[b] = rk[b];
+    for (int a = 0; a < rk[b]; ++a)
+      for (int32_t x : left[b][a]) nodes[pos++] = x;
+    for (int a = 0; a < rk[b]; ++a)
+      for (int32_t x : right[b][a]) nodes[pos++] = x;
+  }
+  *written = pos;
+  return TT_OK;
+}
+
+tt_status tt_job_nodes(tt_job* j, int32_t k, double* t, double* w) {
+  if (!j || k < 0 || k >= j->nprob || !t || !w) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  TT_HIP(hipStreamSynchronize(j->ctx->stream));
+  const ProbDesc& d = j->hdesc[k];
+  TT_HIP(hipMemcpy(t, d.t, d.n * sizeof(double), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(w, d.w, d.n * sizeof(double), hipMemcpyDeviceToHost));
+  return TT_OK;
+}
+
+void tt_cross_free(tt_job* j) {
+  if (!j) return;
+  tt_ctx* c = j->ctx;
+  std::lock_guard<std::mutex> lock(c->mu);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->arena_bytes_cached + j->bytes <= kArenaCacheBytes) {
+    c->arenas.emplace(j->bytes, j->arena);
+    c->arena_bytes_cached += j->bytes;
+  } else {
+    (void)hipFree(j->arena);
+  }
+  delete j;
+}
+
+tt_status tt_eval_points(tt_ctx* ctx, const tt_problem* p, const int32_t* d_idx, int64_t npts,
+                         double* d_out) {
+  if (!ctx || validate(p) != TT_OK || npts < 0 || (npts > 0 && (!d_idx || !d_out))) return TT_EINVAL;
+  if (npts == 0) return TT_OK;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  TT_HIP(hipSetDevice(ctx->device));
+  double *t, *w;
+  tt_status s = gl_table(ctx, p->n_nodes, &t, &w);
+  if (s != TT_OK) return s;
+  FamilyArgs fa;
+  s = family_for(ctx, p, &fa);
+  if (s != TT_OK) return s;
+  const int64_t blocks64 = std::min<int64_t>((npts + kBlock - 1) / kBlock, 1 << 20);
+  const dim3 grid((unsigned)blocks64), block(kBlock);
+  Timed tm(ctx, KK_EVAL_POINTS);
+  switch (bucket_m(fa.m)) {
+    case 4: hipLaunchKernelGGL(k_eval_points<4>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
+    case 8: hipLaunchKernelGGL(k_eval_points<8>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
+    case 16: hipLaunchKernelGGL(k_eval_points<16>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
+    default: hipLaunchKernelGGL(k_eval_points<32>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
+  }
+  TT_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const int32_t* d_left,
+                         int32_t r_left, const int32_t* d_right, int32_t r_right, double* d_out) {
+  if (!ctx || validate(p) != TT_OK) return TT_EINVAL;
+  const int m = modes_of(*p);
+  if (m < 1 || pos < 0 || pos >= m) return TT_EINVAL;
+  if (r_left < 1 || r_left > TT_MAX_RANK || r_right < 1 || r_right > TT_MAX_RANK || !d_out) return TT_EINVAL;
+  if ((pos > 0 && !d_left) || (pos < m - 1 && !d_right)) return TT_EINVAL;
+  if ((pos == 0 && r_left != 1) || (pos == m - 1 && r_right != 1)) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  TT_HIP(hipSetDevice(ctx->device));
+  double *t, *w;
+  tt_status s = gl_table(ctx, p->n_nodes, &t, &w);
+  if (s != TT_OK) return s;
+  FamilyArgs fa;
+  s = family_for(ctx, p, &fa);
+  if (s != TT_OK) return s;
+  const int64_t total = (int64_t)r_left * p->n_nodes * r_right;
+  const int64_t blocks64 = std::min<int64_t>((total + kBlock - 1) / kBlock, 1 << 20);
+  const dim3 grid((unsigned)blocks64), block(kBlock);
+  const int n = p->n_nodes;
+  Timed tm(ctx, KK_EVAL_FIBERS);
+  switch (bucket_m(m)) {
+    case 4: hipLaunchKernelGGL(k_eval_fibers<4>, grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
+    case 8: hipLaunchKernelGGL(k_eval_fibers<8>, grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
+    case 16: hipLaunchKernelGGL(k_eval_fibers<16>, grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
+    default: hipLaunchKernelGGL(k_eval_fibers<32>, grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
+  }
+  TT_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+}  // extern "C"

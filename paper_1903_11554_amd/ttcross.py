@@ -1,0 +1,296 @@
+"""ctypes binding of libttcross.so (include/ttcross.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  There is no CPU fallback: without the built library or a GPU the
+calls raise.  PyTorch is used only to hand device buffers (and optionally its
+current stream) to the library.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .workloads import Problem
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+FAMILY_IDS = {
+    "ising_c": 1, "ising_d": 2, "ising_e": 3,
+    "ising_c_u": 11, "ising_d_u": 12,
+    "prod_exp": 21, "sum2_exp_cos": 22,
+}
+STOP_REASONS = {0: "running", 1: "converged", 2: "rank_cap", 3: "max_sweeps"}
+
+TT_OK, TT_CONVERGED, TT_NOT_CONVERGED = 0, 1, 2
+TT_EINVAL, TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC = -1, -2, -3, -4
+
+
+class TTError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {_status_name(status)} ({status})")
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("integrand", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int32), ("rank_cap", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("max_sweeps", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("params", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("max_rank", ctypes.c_int32),
+                ("reason", ctypes.c_int32), ("err_flags", ctypes.c_int32),
+                ("evals", ctypes.c_int64), ("value", ctypes.c_double),
+                ("rel_change", ctypes.c_double)]
+
+
+class _Pivot(ctypes.Structure):
+    _fields_ = [("row", ctypes.c_int32), ("col", ctypes.c_int32),
+                ("accepted", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("err", ctypes.c_double), ("value", ctypes.c_double)]
+
+
+EXPORTS = [
+    "tt_ctx_create", "tt_ctx_destroy", "tt_ctx_synchronize", "tt_job_footprint",
+    "tt_cross_init", "tt_cross_sweep", "tt_cross_run", "tt_cross_integrate",
+    "tt_job_pivot_log", "tt_job_history", "tt_job_index_sets", "tt_job_nodes",
+    "tt_cross_free", "tt_eval_points", "tt_eval_fibers", "tt_status_string",
+    "tt_ctx_profile", "tt_ctx_kernel_time",
+]
+
+KERNEL_KINDS = {"search": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
+                "eval_points": 5, "eval_fibers": 6}
+
+_lib = None
+
+
+def library_path():
+    return os.environ.get("TTCROSS_LIB", os.path.join(HERE, "libttcross.so"))
+
+
+def load_library():
+    """Load libttcross.so and declare the C signatures (no GPU needed to load)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"libttcross.so not built at {path}: run `python -m paper_1903_11554_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "tt_ctx_create": (i32, [ctypes.c_int, vp, P(vp)]),
+        "tt_ctx_destroy": (None, [vp]),
+        "tt_ctx_synchronize": (i32, [vp]),
+        "tt_job_footprint": (ctypes.c_size_t, [P(_Problem)]),
+        "tt_cross_init": (i32, [vp, P(_Problem), i32, P(vp)]),
+        "tt_cross_sweep": (i32, [vp, i32, P(_Info)]),
+        "tt_cross_run": (i32, [vp, P(_Info)]),
+        "tt_cross_integrate": (i32, [vp, P(dbl), P(_Info)]),
+        "tt_job_pivot_log": (i32, [vp, i32, P(_Pivot), i64, P(i64)]),
+        "tt_job_history": (i32, [vp, i32, P(dbl), i64, P(i64)]),
+        "tt_job_index_sets": (i32, [vp, i32, P(i32), P(i32), i64, P(i64)]),
+        "tt_job_nodes": (i32, [vp, i32, P(dbl), P(dbl)]),
+        "tt_cross_free": (None, [vp]),
+        "tt_eval_points": (i32, [vp, P(_Problem), vp, i64, vp]),
+        "tt_eval_fibers": (i32, [vp, P(_Problem), i32, vp, i32, vp, i32, vp]),
+        "tt_status_string": (ctypes.c_char_p, [i32]),
+        "tt_ctx_profile": (i32, [vp, i32]),
+        "tt_ctx_kernel_time": (i32, [vp, i32, P(i64), P(dbl)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _status_name(status):
+    try:
+        return load_library().tt_status_string(status).decode()
+    except Exception:  # noqa: BLE001 - only used to format an error message
+        return str(status)
+
+
+def _check(status, what):
+    if status < 0:
+        raise TTError(status, what)
+    return status
+
+
+def _c_problem(p: Problem, keep):
+    params = None
+    if p.params is not None:
+        arr = np.ascontiguousarray(np.concatenate([np.asarray(p.params["a"], np.float64)[:p.d],
+                                                   np.asarray(p.params["b"], np.float64)[:p.d]]))
+        keep.append(arr)
+        params = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return _Problem(FAMILY_IDS[p.family], p.d, p.n, p.rank_cap, float(p.tol), 0,
+                    int(p.max_sweeps), int(p.seed) & ((1 << 64) - 1), params)
+
+
+def footprint(p: Problem):
+    keep = []
+    return int(load_library().tt_job_footprint(ctypes.byref(_c_problem(p, keep))))
+
+
+class Context:
+    """A device + stream.  stream: a torch.cuda.Stream (its handle is passed) or None."""
+
+    def __init__(self, device=0, stream=None):
+        lib = load_library()
+        self._lib = lib
+        handle = ctypes.c_void_p()
+        sptr = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(lib.tt_ctx_create(device, sptr, ctypes.byref(handle)), "tt_ctx_create")
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            self._lib.tt_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def synchronize(self):
+        _check(self._lib.tt_ctx_synchronize(self.handle), "tt_ctx_synchronize")
+
+    def profile(self, enable=True):
+        """Switch per-kernel event timing on/off (clears the totals)."""
+        _check(self._lib.tt_ctx_profile(self.handle, 1 if enable else 0), "tt_ctx_profile")
+
+    def kernel_time(self, kind):
+        """(launches, total_ms) of a kernel kind since profiling was switched on."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(self._lib.tt_ctx_kernel_time(self.handle, KERNEL_KINDS[kind], ctypes.byref(n),
+                                            ctypes.byref(ms)), "tt_ctx_kernel_time")
+        return n.value, ms.value
+
+    def job(self, problems):
+        return Job(self, problems)
+
+    def eval_points(self, p: Problem, idx_dev, out_dev, npts):
+        """B at npts multi-indices; idx_dev / out_dev are device pointers (ints)."""
+        keep = []
+        _check(self._lib.tt_eval_points(self.handle, ctypes.byref(_c_problem(p, keep)),
+                                        ctypes.c_void_p(idx_dev), npts, ctypes.c_void_p(out_dev)),
+               "tt_eval_points")
+
+    def eval_fibers(self, p: Problem, pos, left_dev, r_left, right_dev, r_right, out_dev):
+        keep = []
+        _check(self._lib.tt_eval_fibers(self.handle, ctypes.byref(_c_problem(p, keep)), pos,
+                                        ctypes.c_void_p(left_dev), r_left,
+                                        ctypes.c_void_p(right_dev), r_right,
+                                        ctypes.c_void_p(out_dev)), "tt_eval_fibers")
+
+
+class Job:
+    """A batch of integrals solved together (tt_cross_init ... tt_cross_free)."""
+
+    def __init__(self, ctx: Context, problems):
+        if isinstance(problems, Problem):
+            problems = [problems]
+        self.ctx, self._lib = ctx, ctx._lib
+        self.problems = list(problems)
+        keep = []
+        arr = (_Problem * len(self.problems))(*[_c_problem(p, keep) for p in self.problems])
+        handle = ctypes.c_void_p()
+        _check(self._lib.tt_cross_init(ctx.handle, arr, len(self.problems), ctypes.byref(handle)),
+               "tt_cross_init")
+        self.handle = handle
+
+    def free(self):
+        if self.handle:
+            self._lib.tt_cross_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def _infos(self):
+        return (_Info * len(self.problems))()
+
+    @staticmethod
+    def _info_dicts(infos):
+        return [dict(sweeps=i.sweeps, max_rank=i.max_rank, reason=STOP_REASONS.get(i.reason, i.reason),
+                     err_flags=i.err_flags, evals=i.evals, value=i.value, rel_change=i.rel_change)
+                for i in infos]
+
+    def sweep(self, n=1):
+        infos = self._infos()
+        st = _check(self._lib.tt_cross_sweep(self.handle, n, infos), "tt_cross_sweep")
+        return st == TT_CONVERGED, self._info_dicts(infos)
+
+    def run(self):
+        infos = self._infos()
+        _check(self._lib.tt_cross_run(self.handle, infos), "tt_cross_run")
+        return self._info_dicts(infos)
+
+    def values(self):
+        vals = (ctypes.c_double * len(self.problems))()
+        infos = self._infos()
+        _check(self._lib.tt_cross_integrate(self.handle, vals, infos), "tt_cross_integrate")
+        return list(vals), self._info_dicts(infos)
+
+    def pivot_log(self, k):
+        p = self.problems[k]
+        nb = max(p.modes() - 1, 0)
+        cap = max(1, nb * (p.max_sweeps if p.max_sweeps > 0 else 4 * p.rank_cap))
+        buf = (_Pivot * cap)()
+        written = ctypes.c_int64()
+        _check(self._lib.tt_job_pivot_log(self.handle, k, buf, cap, ctypes.byref(written)),
+               "tt_job_pivot_log")
+        recs = [dict(row=r.row, col=r.col, accepted=bool(r.accepted), iters=r.iters, err=r.err,
+                     value=r.value) for r in buf[:written.value]]
+        return [recs[s * nb:(s + 1) * nb] for s in range(written.value // nb)] if nb else []
+
+    def history(self, k):
+        p = self.problems[k]
+        cap = (p.max_sweeps if p.max_sweeps > 0 else 4 * p.rank_cap) + 1
+        buf = (ctypes.c_double * cap)()
+        written = ctypes.c_int64()
+        _check(self._lib.tt_job_history(self.handle, k, buf, cap, ctypes.byref(written)), "tt_job_history")
+        return list(buf[:written.value])
+
+    def index_sets(self, k):
+        """[(left rows, right rows)] per bond, each a list of tuples of node indices."""
+        p = self.problems[k]
+        m = p.modes()
+        nb = max(m - 1, 0)
+        if nb == 0:
+            return []
+        ranks = (ctypes.c_int32 * nb)()
+        cap = nb * p.rank_cap * m
+        nodes = (ctypes.c_int32 * cap)()
+        written = ctypes.c_int64()
+        _check(self._lib.tt_job_index_sets(self.handle, k, ranks, nodes, cap, ctypes.byref(written)),
+               "tt_job_index_sets")
+        out, pos = [], 0
+        for b in range(nb):
+            r = ranks[b]
+            left = [tuple(nodes[pos + a * (b + 1): pos + (a + 1) * (b + 1)]) for a in range(r)]
+            pos += r * (b + 1)
+            w = m - b - 1
+            right = [tuple(nodes[pos + a * w: pos + (a + 1) * w]) for a in range(r)]
+            pos += r * w
+            out.append((left, right))
+        return out
+
+    def nodes(self, k):
+        n = self.problems[k].n
+        t = (ctypes.c_double * n)()
+        w = (ctypes.c_double * n)()
+        _check(self._lib.tt_job_nodes(self.handle, k, t, w), "tt_job_nodes")
+        return np.array(t[:]), np.array(w[:])

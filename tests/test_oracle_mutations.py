@@ -1,0 +1,141 @@
+"""Planted mistakes: each plausible slip in the oracle must break one of its pins.
+
+A mutated copy of the oracle package is written to a temporary directory,
+imported under another name, and checked with the same kind of pin the
+regular tests use.  Every mutation must fail its pin, and the unmutated copy
+must pass it (so the pin is not failing for an unrelated reason).
+"""
+import importlib
+import os
+import shutil
+import sys
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+
+
+def load_copy(tmp_path, name, file=None, old=None, new=None):
+    pkg = tmp_path / name
+    shutil.copytree(ORACLE, pkg, ignore=shutil.ignore_patterns("__pycache__"))
+    if file is not None:
+        path = pkg / file
+        src = path.read_text()
+        assert src.count(old) >= 1, f"mutation anchor not found in {file}: {old!r}"
+        path.write_text(src.replace(old, new))
+    sys.path.insert(0, str(tmp_path))
+    try:
+        return {m: importlib.import_module(f"{name}.{m}")
+                for m in ("rng", "gauss", "integrands", "quadrature", "ttcross")}
+    finally:
+        sys.path.remove(str(tmp_path))
+
+
+def closed(key):
+    with mp.workdps(30):
+        L3 = (mp.zeta(2, mp.mpf(1) / 3) - mp.zeta(2, mp.mpf(2) / 3)) / 9
+        return float({"c3": L3, "c4": 7 * mp.zeta(3) / 12,
+                      "d4": 4 * mp.pi ** 2 / 9 - mp.mpf(1) / 6 - 7 * mp.zeta(3) / 2}[key])
+
+
+# ---------------------------------------------------------------- pins
+def pin_d2(o):
+    t, w = o["gauss"].gauss_legendre_01(40)
+    return abs(np.dot(w, o["integrands"].f_values("ising_d", t.reshape(-1, 1))) - 1 / 3) < 1e-15
+
+
+def pin_c2(o):
+    t, w = o["gauss"].gauss_legendre_01(40)
+    return abs(np.dot(w, o["integrands"].f_values("ising_c", t.reshape(-1, 1))) - 1.0) < 1e-15
+
+
+def pin_c3_brute(o):
+    return abs(o["quadrature"].tensor_quadrature("ising_c", 2, 24) / closed("c3") - 1) < 1e-14
+
+
+def pin_d4_tt(o):
+    tt = o["ttcross"].solve("ising_d", 4, 24, 32, 1e-13, seed=4)
+    return abs(tt.history[-1] / closed("d4") - 1) < 1e-12
+
+
+def pin_rank2(o):
+    r = np.random.default_rng(5)
+    params = {"a": r.uniform(0.5, 4, 4).tolist(), "b": r.uniform(0.5, 4, 4).tolist()}
+    try:
+        tt = o["ttcross"].solve("sum2_exp_cos", 4, 6, 8, 1e-12, seed=9, params=params)
+    except np.linalg.LinAlgError:
+        return False
+    q = o["quadrature"].tensor_quadrature("sum2_exp_cos", 4, 6, params)
+    # at exact rank 2 every later search must see errors at the rounding level only
+    late = [abs(rec.err) for sweep in tt.pivot_log[1:] for rec in sweep if rec.searched]
+    return (max(tt.ranks()) == 2 and abs(tt.history[-1] - q) < 1e-13 * abs(q)
+            and all(e < 1e-14 * abs(q) for e in late))
+
+
+def pin_gl(o):
+    t, w = o["gauss"].gauss_legendre_01(16)
+    return abs(w.sum() - 1) < 1e-15 and all(abs(np.dot(w, t ** k) - 1 / (k + 1)) < 1e-15
+                                            for k in range(32))
+
+
+def pin_rng(o):
+    return o["rng"].stream(0, 3) == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def pin_rook(o):
+    # the matrix case (m = 2): check Alg. 2's result against the skeleton
+    # formula eq. mat on the full matrix, over several sweeps
+    tt = o["ttcross"].TTCross("ising_d", 3, 16, 12, 1e-15, seed=6, max_sweeps=6)
+    full = np.array([[tt.B([(i, j)])[0] for j in range(16)] for i in range(16)])
+    ok = True
+    for _ in range(5):
+        cores = [tt.core(c) for c in range(tt.m)]
+        rec = tt.cross_step(0, tt.sweeps, cores)
+        I = [l[0] for l in tt.left[0]]
+        J = [r[0] for r in tt.right[0]]
+        err = full - full[:, J] @ np.linalg.solve(full[np.ix_(I, J)], full[I, :])
+        ok = ok and abs(err[rec.row, rec.col] - rec.err) < 1e-14 * np.abs(full).max()
+        ok = ok and abs(err[rec.row, rec.col]) >= np.abs(err[rec.row, :]).max() * (1 - 1e-12)
+        if rec.iters < o["ttcross"].T_ROOK:    # ended by the rook condition: column-dominant too
+            ok = ok and abs(err[rec.row, rec.col]) >= np.abs(err[:, rec.col]).max() * (1 - 1e-12)
+        tt.sweep()
+        if tt.stop_reason:
+            break
+    return ok
+
+
+MUTATIONS = [
+    # (file, original text, planted mistake, pin that must catch it)
+    ("integrands.py", "a_d = a_d * ((1.0 - p) / (1.0 + p)) ** 2", "a_d = a_d * ((1.0 - p) / (1.0 + p))",
+     pin_d2),                                                                # dropped square
+    ("integrands.py", "s_right = s_right + prod_range(k, d)", "s_right = s_right + prod_range(2, k)",
+     pin_c3_brute),                                                          # wrong index range
+    ("integrands.py", "f = np.full(npts, 2.0)", "f = np.full(npts, 1.0)", pin_c2),   # lost prefactor
+    ("integrands.py", "wt = np.prod(w[idx], axis=1)", "wt = np.prod(w[idx][:, :-1], axis=1)",
+     pin_c3_brute),                                                          # dropped weight
+    ("ttcross.py", "v = np.linalg.solve(M.T, v.T).T", "v = np.linalg.solve(M, v.T).T", pin_d4_tt),
+    ("ttcross.py", "X = np.linalg.solve(M, Fb1[:, cols])", "X = np.linalg.solve(M.T, Fb1[:, cols])",
+     pin_rank2),                                                             # transposed operand
+    ("ttcross.py", "row = argmax_abs(a_col - approx(all_rows, [col] * nrows))",
+     "row = argmax_abs(a_col)", pin_rook),                                   # dropped B~ term
+    ("gauss.py", "w.append(float(1 / ((1 - x * x) * dp * dp)))",
+     "w.append(float(2 / ((1 - x * x) * dp * dp)))", pin_gl),                # interval map
+    ("rng.py", "GAMMA = 0x9E3779B97F4A7C15", "GAMMA = 0x9E3779B97F4A7C13", pin_rng),
+    ("rng.py", "z = ((z ^ (z >> 27)) * M2) & MASK", "z = ((z ^ (z >> 28)) * M2) & MASK", pin_rng),
+]
+
+
+@pytest.mark.parametrize("k", range(len(MUTATIONS)))
+def test_planted_mistake_is_caught(tmp_path, k):
+    file, old, new, pin = MUTATIONS[k]
+    good = load_copy(tmp_path, f"oracle_ok_{k}")
+    assert pin(good), "the pin must pass on the unmodified oracle"
+    bad = load_copy(tmp_path, f"oracle_mut_{k}", file, old, new)
+    try:
+        caught = not pin(bad)
+    except (FloatingPointError, np.linalg.LinAlgError, ValueError, ZeroDivisionError):
+        caught = True
+    assert caught, f"planted mistake in {file} not caught: {new}"
