@@ -47,19 +47,24 @@ def flops_per_eval(family, m, weight_muls):
     return 4 * m + 4 + weight_muls
 
 
-def search_work(job, k, prob):
-    """Evaluations and algorithmic flops of the pivot-search kernel for integral k.
+def sweep_work(job, k, prob):
+    """Integrand evaluations and algorithmic FP64 flops of the sweep kernel for integral k.
 
-    Reconstructed exactly from the pivot log: in every sweep a searched bond b
-    evaluates min(r_{b-1} n + n r_{b+1}, 1024) samples plus, per rook iteration,
-    one column (r_{b-1} n points) and one row (n r_{b+1} points); each point
-    also costs an r_b-term dot product (2 r_b flops) for B~.
+    Reconstructed exactly from the pivot log (ranks start at 1 and grow by the
+    accepted pivots).  Per sweep and superblock b (if searched): samples
+    min(r_{b-1} n + n r_{b+1}, 1024) plus, per rook iteration, one column
+    (r_{b-1} n points) and one row (n r_{b+1} points), each point also an
+    r_b-term dot product (2 r_b flops).  Per core c: the new fibre entries
+    (new row: n r_c', new column: r_{c-1} n), the LU of the r x r cross
+    (2 r^3 / 3) and the triangular solves of its r_{c-1}' n rows (2 r^2 each),
+    and the core sum (r_{c-1}' n r_c'); the quadrature adds 2 r_{c-1} r_c per core.
     """
     m, n = prob.modes(), prob.n
     nb = m - 1
     ranks = [1] * nb
     evals = flops = 0
-    fe = flops_per_eval(prob.family, m, 4)
+    fs = flops_per_eval(prob.family, m, 4)
+    fc = flops_per_eval(prob.family, m, 3)
     for sweep in job.pivot_log(k):
         for b, rec in enumerate(sweep):
             if rec["row"] < 0:
@@ -69,10 +74,21 @@ def search_work(job, k, prob):
             nrows, ncols = rl * n, n * rr
             e = min(nrows + ncols, 1024) + rec["iters"] * (nrows + ncols)
             evals += e
-            flops += e * (fe + 2 * ranks[b])
-        for b, rec in enumerate(sweep):
-            if rec["accepted"]:
-                ranks[b] += 1
+            flops += e * (fs + 2 * ranks[b])
+        new = [ranks[b] + (1 if sweep[b]["accepted"] else 0) for b in range(nb)]
+        for c in range(m):
+            rl_old = ranks[c - 1] if c > 0 else 1
+            rl_new = new[c - 1] if c > 0 else 1
+            rr_old = ranks[c] if c < nb else 1
+            rr_new = new[c] if c < nb else 1
+            e = (rl_new - rl_old) * n * rr_new + rl_old * n * (rr_new - rr_old)
+            evals += e
+            flops += e * fc
+            if c < nb:
+                r = rr_new
+                flops += 2 * r ** 3 // 3 + 2 * rl_new * n * r * r + rl_new * n * r
+            flops += 2 * rl_new * rr_new
+        ranks = new
     return evals, flops
 
 
@@ -125,10 +141,10 @@ def run_gpu(args):
     # one extra step with per-kernel event timing (not part of the timed loop)
     ctx.profile(True)
     job, pinfos = step()
-    kt = {k: ctx.kernel_time(k) for k in ("search", "update", "integral", "start", "gl")}
+    kt = {k: ctx.kernel_time(k) for k in ("sweep", "update", "integral", "start", "gl")}
     s_evals = s_flops = 0
     for k, p in enumerate(probs):
-        e, f = search_work(job, k, p)
+        e, f = sweep_work(job, k, p)
         s_evals += e
         s_flops += f
     sweeps = max(i["sweeps"] for i in pinfos)
@@ -209,10 +225,11 @@ def main():
     def pct(q):
         return lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
 
-    nl_s, ms_s = r["kt"]["search"]
+    nl_s, ms_s = r["kt"]["sweep"]
     nl_u, ms_u = r["kt"]["update"]
     achieved = r["s_flops"] / (ms_s * 1e-3) / 1e12
-    roof = {"kernel": "k_search (pivot search: samples + rook fibres, one workgroup per superblock)",
+    roof = {"kernel": "k_sweep (one launch per sweep: pivot search of every superblock, core updates, "
+                      "quadrature and stopping rule; one workgroup per superblock)",
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
             "launches": nl_s, "avg_launch_ms": ms_s / max(nl_s, 1),
@@ -231,7 +248,7 @@ def main():
         "integrals_per_s": len(r["probs"]) * args.steps / r["elapsed"],
         "latency_ms_p50": pct(0.5), "latency_ms_p99": pct(0.99),
         "rel_err_vs_reference": r["errs"],
-        "kernel_ms_per_step": {"search": ms_s, "update": ms_u, "integral": r["kt"]["integral"][1],
+        "kernel_ms_per_step": {"sweep": ms_s, "init_update": ms_u, "init_integral": r["kt"]["integral"][1],
                                "start": r["kt"]["start"][1], "gl": r["kt"]["gl"][1]},
         "sweeps": r["sweeps"],
         "roofline": roof,

@@ -169,11 +169,24 @@ tt_status tt_eval_fibers(tt_ctx *ctx, const tt_problem *problem, int32_t pos,
  * around every launch (adds two event records per launch).  tt_ctx_profile
  * switches it on or off and clears the totals; tt_ctx_kernel_time returns the
  * number of timed launches and their summed duration in ms for a kernel kind:
- * 0 pivot search, 1 core update, 2 quadrature/stopping rule, 3 rank-1 start,
- * 4 Gauss--Legendre nodes, 5 tt_eval_points, 6 tt_eval_fibers.
+ * 0 sweep (pivot search, core updates, quadrature and stopping rule fused in
+ * one launch per sweep), 1 core update at init, 2 quadrature at init,
+ * 3 rank-1 start, 4 Gauss--Legendre nodes, 5 tt_eval_points, 6 tt_eval_fibers.
  * Errors: TT_EINVAL (bad kind or NULL outputs). */
 tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
 tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);
+
+/* Phase marks of the sweep kernel for integral k, recorded for jobs created
+ * while profiling is on (otherwise *written = 0): for every sweep and
+ * superblock, 16 wall-clock marks (0 start, 1 sets staged, 2 samples done,
+ * 3 rook pivoting done, 4 search done, 5 core updates done, 6 quadrature done,
+ * 7 end, then inside the workgroup's last core update: 8 hand-over done,
+ * 9 sets staged, 10 new entries evaluated, 11 cross factorised, 12 interpolation
+ * core solved, 13 core summed; 0 where the workgroup skipped a phase), in ticks
+ * of *clock_mhz MHz.  marks is a host buffer of `capacity` int64;
+ * sweeps x (m-1) x 16 values are written. */
+tt_status tt_job_phase_times(tt_job *job, int32_t k, int64_t *marks, int64_t capacity, int64_t *written,
+                             double *clock_mhz);
 
 /* Synchronise the context stream. */
 tt_status tt_ctx_synchronize(tt_ctx *ctx);

@@ -94,44 +94,51 @@ __device__ __forceinline__ uint64_t start_counter(int q, int k) {
 // y[0..m) holds the coordinates of one point (entries >= m are ignored).
 // Returns the unweighted integrand f(y) including its constant prefactor.
 
-// Paper form, y_k = x_{k+2}: the prefix sum 1 + sum_k y_1..y_k and the suffix
-// sum 1 + sum_k y_k..y_m by Horner's rule, and the pair product over all runs
-// y_a..y_b (1 <= a <= b <= m), i.e. over 1 <= i < j <= d with x_{i+1}..x_j.
+// Paper form, y_k = x_{k+2} (k = 0..m-1).  Every run y_a..y_b (a <= b), i.e.
+// every pair 1 <= i < j <= d with its product x_{i+1}..x_j, is visited once, in
+// the order of its last index b: after step b, z[a] holds y_a..y_b for a <= b
+// (the products are kept in place of the coordinates, so no extra registers).
+//   A_d: pn = prod (1 - y_a..y_b), pd = prod (1 + y_a..y_b), A_d = (pn/pd)^2;
+//   prefix sum q = sum_b y_0..y_b (the run starting at a = 0 after each step);
+//   suffix sum s = sum_a y_a..y_{m-1} (all runs after the last step);
+//   B_d = 1 / ((1 + q)(1 + s)).
+// One uniform guard per b: modes beyond m are skipped in one branch each.
 template <int MAXM>
 __device__ __forceinline__ double ising_paper(int family, int m, const double (&y)[MAXM]) {
-  double num = 2.0, den = 1.0;
-  if (family != TT_ISING_E) {
-    double q = 0.0, s = 0.0;
+  double z[MAXM];
 #pragma unroll
-    for (int k = MAXM - 1; k >= 0; --k)
-      if (k < m) q = fma(q, y[k], y[k]);   // y_k (1 + q)
+  for (int k = 0; k < MAXM; ++k) z[k] = (k < m) ? y[k] : 0.0;
+  const bool need_a = family != TT_ISING_C;
+  double pn = 1.0, pd = 1.0, q = 0.0;
 #pragma unroll
-    for (int k = 0; k < MAXM; ++k)
-      if (k < m) s = fma(s, y[k], y[k]);   // (1 + s) y_k
-    den = (1.0 + q) * (1.0 + s);
-  }
-  if (family != TT_ISING_C) {
-    double pn = 1.0, pd = 1.0;
-    // constant trip counts with uniform guards: fully unrolled, y stays in VGPRs
+  for (int b = 0; b < MAXM; ++b) {
+    if (b < m) {
+      const double yb = z[b];
 #pragma unroll
-    for (int a = 0; a < MAXM; ++a) {
-      if (a < m) {
-        double p = 1.0;
+      for (int a = 0; a < b; ++a) z[a] *= yb;      // z[a] = y_a..y_b
+      q += z[0];
+      if (need_a) {
 #pragma unroll
-        for (int b = a; b < MAXM; ++b) {
-          if (b < m) {
-            p *= y[b];
-            pn = fma(-pn, p, pn);    // pn * (1 - p)
-            pd = fma(pd, p, pd);     // pd * (1 + p)
-          }
+        for (int a = 0; a <= b; ++a) {
+          pn = fma(-pn, z[a], pn);                   // pn * (1 - y_a..y_b)
+          pd = fma(pd, z[a], pd);                    // pd * (1 + y_a..y_b)
         }
       }
     }
+  }
+  double num = 2.0, den = 1.0;
+  if (family != TT_ISING_E) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < MAXM; ++a) s += z[a];        // zero beyond m
+    den = (1.0 + q) * (1.0 + s);
+  }
+  if (need_a) {
     if (m <= 31) {               // pd^2 <= 2^(m(m+1)) stays finite
       num = num * pn * pn;
       den = den * (pd * pd);
     } else {
-      double r = pn / pd;
+      const double r = pn / pd;
       num = num * r * r;
     }
   }

@@ -1,0 +1,58 @@
+// Kernel instantiations for one integrand class (TT_FAM = FAM_PAPER, FAM_UFORM,
+// FAM_SYNTH or FAM_ANY), compiled once per class.
+#include "tt_kernels.hpp"
+#include "tt_launch.hpp"
+
+#ifndef TT_FAM
+#error "compile with -DTT_FAM=<integrand class>"
+#endif
+
+namespace ttx {
+namespace {
+
+template <int MAXM, int RMAX>
+void sweep(const LaunchArgs& a) {
+  hipLaunchKernelGGL((k_sweep<TT_FAM, MAXM, RMAX>), dim3(a.nbond), dim3(kSweepBlock), 0, a.stream, a.desc,
+                     a.bond_tasks);
+}
+
+template <int MAXM>
+void by_rank(const LaunchArgs& a, int what, int rb) {
+  if (what == LAUNCH_START) {
+    hipLaunchKernelGGL((k_start<TT_FAM, MAXM>), dim3(a.nprob), dim3(kBlock), 0, a.stream, a.desc);
+    return;
+  }
+  if (what == LAUNCH_INIT_UPDATE) {
+    hipLaunchKernelGGL((k_update<TT_FAM, MAXM, 8>), dim3(a.ncore), dim3(kSweepBlock), 0, a.stream, a.desc,
+                       a.core_tasks, 1);
+    return;
+  }
+  switch (rb) {
+    case 8: sweep<MAXM, 8>(a); break;
+    case 16: sweep<MAXM, 16>(a); break;
+    case 32: sweep<MAXM, 32>(a); break;
+    default: sweep<MAXM, 64>(a); break;
+  }
+}
+
+void dispatch(const LaunchArgs& a, int what, int rb) {
+  switch (a.mbucket) {
+    case 8: by_rank<8>(a, what, rb); break;
+    case 16: by_rank<16>(a, what, rb); break;
+    default: by_rank<32>(a, what, rb); break;
+  }
+}
+
+}  // namespace
+
+#if TT_FAM == 0
+void launch_paper(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }
+#elif TT_FAM == 1
+void launch_uform(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }
+#elif TT_FAM == 2
+void launch_synth(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }
+#else
+void launch_any(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }
+#endif
+
+}  // namespace ttx

@@ -1,20 +1,25 @@
 // HIP kernels of the TT cross library (gfx950, wave64).
 //
-// One sweep of Alg. 6 (dimension-parallel greedy cross, Sec. 3.4) is three
-// launches over every integral of a job:
-//   k_search  one workgroup per superblock b: Alg. 2 on the (r_{b-1} n) x (n r_{b+1})
-//             matrix B(I_<=b-1 i_b, i_b+1 I_>b+1) with the previous sweep's sets:
+// One sweep of Alg. 6 (dimension-parallel greedy cross, Sec. 3.4) over every
+// integral of a job is one launch of k_sweep, one workgroup per superblock,
+// running three phases that are handed over without any waiting (see k_sweep):
+//   search    Alg. 2 on the (r_{b-1} n) x (n r_{b+1}) matrix
+//             B(I_<=b-1 i_b, i_b+1 I_>b+1) with the previous sweep's sets:
 //             random samples, then column / row steps until the rook condition
 //             (eq. rook) holds; the approximation is B~ = C_b F_{b+1} with the
-//             interpolation core C_b = F_b M_b^-1 (Alg. 1's B matrix);
-//   k_update  one workgroup per core c: appends the accepted pivots of bonds c-1
-//             and c to I_<=c-1 and I_>c (nestedness, eq. nest), evaluates the
-//             new fibre entries of F_c = B(I_<=c-1, i_c, I_>c), refactorises the
-//             cross M_c = B(I_<=c, I_>c) and recomputes C_c; sums the core over
-//             its mode index for the quadrature;
-//   k_integral one workgroup per integral: commits the ranks, multiplies the
-//             2m-1 matrices of the TT quadrature (Sec. 4.1) and applies the
-//             stopping rule.
+//             interpolation core C_b = F_b M_b^-1 (Alg. 1's matrix B);
+//   update    per core c, run by the last of its two neighbouring superblocks:
+//             appends the accepted pivots of bonds c-1 and c to I_<=c-1 and
+//             I_>c (nestedness, eq. nest), evaluates the new fibre entries of
+//             F_c = B(I_<=c-1, i_c, I_>c), and brings C_c up to date: new rows
+//             are solved with the stored LU of the cross M_c = B(I_<=c, I_>c),
+//             the new column enters by the exact rank-1 (Schur complement)
+//             update of C_c, and the LU of M_c grows by one bordered row and
+//             column; then sums the core over its mode index for the quadrature;
+//   integral  per integral, run by the last core update: commits the ranks,
+//             multiplies the 2m-1 matrices of the TT quadrature (Sec. 4.1) and
+//             applies the stopping rule.
+// Kernels are specialised by integrand class, so each carries one integrand.
 #pragma once
 
 #include "tt_device.hpp"
@@ -39,7 +44,7 @@ struct ProbDesc {
   int32_t max_sweeps, nbonds, pad0, pad1;
   double tol, four_over_mfact;
   uint64_t seed;
-  double *t, *w, *pa, *pb;
+  const double *t, *w, *pa, *pb;
   int32_t *Lpar, *Lnode, *Rpar, *Rnode;  // [nbonds][R]
   double *Lx, *Rx;                       // [nbonds][R][m]
   double *Lw, *Rw;                       // [nbonds][R]
@@ -47,6 +52,7 @@ struct ProbDesc {
   int64_t *Foff;
   double *C;                             // interpolation cores (transposed), bond b at C + Coff[b]
   int64_t *Coff;
+  double *LU;                            // [nbonds][R*R] LU of M_b in insertion order (no pivoting)
   double *S;                             // [m][R*R] core sums over the mode index
   int32_t *rank;                         // [nbonds]
   PivRec *piv;                           // [nbonds] current sweep's pivots
@@ -54,14 +60,48 @@ struct ProbDesc {
   PivRec *log;                           // [max_sweeps][nbonds]
   double *hist;                          // [max_sweeps+1]
   int32_t *start;                        // [m] start multi-index
+  int32_t *sync;                         // [m+1] per-sweep dataflow counters (cores ready, cores done)
+  int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
+  long long *phase;                      // [max_sweeps][nbonds][kPhases] wall-clock marks, or null
   ProbState *st;
 };
 
-constexpr int kBlock = 256;        // start, update, standalone evaluation
-constexpr int kSearchBlock = 512;  // pivot search: 8 waves per superblock
-constexpr int kStart = 1024;     // rank-1 start samples
+// Phase marks of one superblock's workgroup in one sweep (wall clock, written by thread 0):
+// 0 start, 1 sets staged, 2 samples done, 3 rook pivoting done, 4 search done,
+// 5 core updates done, 6 quadrature done, 7 end; inside the last core update of the
+// workgroup: 8 hand-over done, 9 pivots appended and sets staged, 10 new entries
+// evaluated, 11 new rows solved, 12 cross LU bordered, 13 rank-1 update done, 14 core summed.
+constexpr int kPhases = 16;
+__device__ __forceinline__ void mark(const ProbDesc& p, int sweep, int b, int slot) {
+  if (p.phase != nullptr && threadIdx.x == 0)
+    p.phase[((size_t)sweep * p.nbonds + b) * kPhases + slot] = (long long)wall_clock64();
+}
+
+// Mirror "this integral has stopped" into pinned host memory so the host can
+// stop queueing sweeps without copying the device state back.
+__device__ __forceinline__ void signal_done(const ProbDesc& p) {
+  if (p.done_host) {
+    __hip_atomic_store(p.done_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+  }
+}
+
+constexpr int kBlock = 256;        // start, standalone evaluation
+constexpr int kSweepBlock = 512;   // sweep and update kernels: 8 waves per workgroup
+constexpr int kStart = 1024;       // rank-1 start samples
 constexpr int kMaxSamples = 1024;
 constexpr int kRook = 5;
+
+// integrand classes a kernel can be specialised for
+enum { FAM_PAPER = 0, FAM_UFORM = 1, FAM_SYNTH = 2, FAM_ANY = 3 };
+
+template <int FAM, int MAXM>
+__device__ __forceinline__ double integrand_fam(const FamilyArgs& fa, const double (&y)[MAXM]) {
+  if constexpr (FAM == FAM_PAPER) return ising_paper<MAXM>(fa.family, fa.m, y);
+  else if constexpr (FAM == FAM_UFORM) return ising_u<MAXM>(fa.family, fa.m, y, fa.four_over_mfact);
+  else if constexpr (FAM == FAM_SYNTH) return synthetic<MAXM>(fa.family, fa.m, y, fa.a, fa.b);
+  else return integrand<MAXM>(fa, y);
+}
 
 __device__ __forceinline__ int rowcap(const ProbDesc& p, int c) { return c == 0 ? 1 : p.R; }
 __device__ __forceinline__ int colcap(const ProbDesc& p, int c) { return c == p.m - 1 ? 1 : p.R; }
@@ -120,7 +160,7 @@ __device__ inline void gl_node(int n, int k, double& t_out, double& w_out) {
   w_out = wk.hi + wk.lo;
 }
 
-__global__ void k_gl(int n, double* __restrict__ t, double* __restrict__ w) {
+static __global__ void k_gl(int n, double* __restrict__ t, double* __restrict__ w) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     double tk, wk;
     gl_node(n, k, tk, wk);
@@ -131,7 +171,7 @@ __global__ void k_gl(int n, double* __restrict__ t, double* __restrict__ w) {
 
 
 // ----------------------------------------------------- rank-1 start (m >= 0)
-template <int MAXM>
+template <int FAM, int MAXM>
 __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   const ProbDesc p = P[blockIdx.x];
   const int m = p.m, n = p.n, tid = threadIdx.x;
@@ -148,14 +188,14 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       double y[MAXM];
 #pragma unroll
       for (int k = 0; k < MAXM; ++k) y[k] = 0.0;
-      val = integrand<MAXM>(fa, y);
+      val = integrand_fam<FAM, MAXM>(fa, y);
     } else {
       for (int i = tid; i < n; i += blockDim.x) {
         double y[MAXM];
 #pragma unroll
         for (int k = 0; k < MAXM; ++k) y[k] = 0.0;
         y[0] = p.t[i];
-        s_buf[i] = p.w[i] * integrand<MAXM>(fa, y);
+        s_buf[i] = p.w[i] * integrand_fam<FAM, MAXM>(fa, y);
       }
       __syncthreads();
       if (tid == 0)
@@ -190,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
         y[k] = 0.0;
       }
     }
-    double v = W * integrand<MAXM>(fa, y);
+    double v = W * integrand_fam<FAM, MAXM>(fa, y);
     if (!isfinite(v)) bad = true;
     if (better(fabs(v), q, best.v, best.idx)) { best.v = fabs(v); best.idx = q; }
   }
@@ -240,6 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       p.scale[b] = best.v;
     }
     for (int k = 0; k < m; ++k) p.start[k] = s_i0[k];
+    for (int k = 0; k <= m; ++k) p.sync[k] = 0;
     st->sweeps = 0;
     st->done = 0;
     st->reason = TT_RUNNING;
@@ -250,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   }
 }
 
-// ------------------------------------------------------------ k_search
+// ------------------------------------------------------------ search (Alg. 2)
 template <int MAXM>
 struct SearchSmem {
   double Lx[TT_MAX_RANK * (MAXM + 1)];
@@ -258,22 +299,19 @@ struct SearchSmem {
   double Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
   double t[TT_MAX_NODES], w[TT_MAX_NODES];
   double vec[TT_MAX_RANK];
-  double red_v[kSearchBlock / kWave + 1];
-  int red_i[kSearchBlock / kWave + 1];
+  double red_v[kSweepBlock / kWave + 1];
+  int red_i[kSweepBlock / kWave + 1];
   double e_star, a_star;
 };
 
-template <int MAXM>
-__global__ __launch_bounds__(kSearchBlock) void k_search(ProbDesc* __restrict__ P,
-                                                   const int2* __restrict__ tasks) {
+// One step of Alg. 2 on superblock b.  The random samples, every column step and
+// every row step run through the same evaluation loop (one inlined integrand).
+template <int FAM, int MAXM>
+__device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, SearchSmem<MAXM>& sm) {
   constexpr int LD = MAXM + 1;
-  __shared__ SearchSmem<MAXM> sm;
-  const int2 tk = tasks[blockIdx.x];
-  const ProbDesc& p = P[tk.x];
-  const int b = tk.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   ProbState* st = p.st;
   const int m = p.m, n = p.n, R = p.R, nb = p.nbonds;
-  if (st->done) return;
   const int sweep = st->sweeps;
   const int rb = p.rank[b];
   const int rL = b > 0 ? p.rank[b - 1] : 1;
@@ -287,125 +325,120 @@ __global__ __launch_bounds__(kSearchBlock) void k_search(ProbDesc* __restrict__ 
     return;
   }
   const FamilyArgs fa = family_args(p);
+  mark(p, sweep, b, 0);
   // stage index-set coordinates, node table and weights in LDS
   for (int e = tid; e < rL * b; e += blockDim.x) {
-    int a = e / b, k = e % b;
+    const int a = e / b, k = e % b;
     sm.Lx[a * LD + k] = p.Lx[((size_t)(b - 1) * R + a) * m + k];
   }
   const int nright = m - b - 2;
   for (int e = tid; e < rR * nright; e += blockDim.x) {
-    int a = e / nright, k = b + 2 + e % nright;
+    const int a = e / nright, k = b + 2 + e % nright;
     sm.Rx[a * LD + k] = p.Rx[((size_t)(b + 1) * R + a) * m + k];
   }
   for (int a = tid; a < rL; a += blockDim.x) sm.Lw[a] = b > 0 ? p.Lw[(size_t)(b - 1) * R + a] : 1.0;
   for (int a = tid; a < rR; a += blockDim.x)
     sm.Rw[a] = (b + 1 <= m - 2) ? p.Rw[(size_t)(b + 1) * R + a] : 1.0;
   for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = p.t[i]; sm.w[i] = p.w[i]; }
+  if (tid == 0) { sm.e_star = 0.0; sm.a_star = 0.0; }
   __syncthreads();
+  mark(p, sweep, b, 1);
 
   const int nrows = rL * n, ncols = n * rR;
   const double* __restrict__ F1 = p.F + p.Foff[b + 1];
   const int cc1 = colcap(p, b + 1);
   const double* __restrict__ Cb = p.C + p.Coff[b];
   const size_t ldC = (size_t)rowcap(p, b) * n;
-
-  auto evalA = [&](int row, int col) -> double {
-    const int al = row / n, i = row - al * n;
-    const int j = col / rR, be = col - j * rR;
-    double y[MAXM];
-#pragma unroll
-    for (int k = 0; k < MAXM; ++k) {
-      double v = 0.0;
-      if (k < m) {
-        v = (k < b) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
-        v = (k == b) ? sm.t[i] : v;
-        v = (k == b + 1) ? sm.t[j] : v;
-      }
-      y[k] = v;
-    }
-    const double W = ((sm.Lw[al] * sm.w[i]) * sm.w[j]) * sm.Rw[be];
-    return W * integrand<MAXM>(fa, y);
-  };
-
-  double seen = 0.0;
-  bool bad = false;
-  // ---- random samples (Alg. 2, first step)
   const int nsamp = min(nrows + ncols, kMaxSamples);
   const uint32_t total = (uint32_t)nrows * (uint32_t)ncols;
-  ArgMax best{-1.0, 0x7fffffff};
-  for (int q = tid; q < nsamp; q += blockDim.x) {
-    const uint32_t id = uniform_below(splitmix_at(p.seed, sample_counter(sweep, b, q)), total);
-    const int row = (int)(id / (uint32_t)ncols), col = (int)(id % (uint32_t)ncols);
-    const double a = evalA(row, col);
-    const int j = col / rR, be = col - j * rR;
-    double s = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < rb; ++k) s = fma(Cb[k * ldC + row], F1[((size_t)k * n + j) * cc1 + be], s);
-    const double e = a - s;
-    bad |= !isfinite(e);
-    seen = fmax(seen, fabs(a));
-    if (better(fabs(e), q, best.v, best.idx)) { best.v = fabs(e); best.idx = q; }
-  }
-  best = block_argmax(best, sm.red_v, sm.red_i);
-  int row, col;
-  {
-    const uint32_t id = uniform_below(splitmix_at(p.seed, sample_counter(sweep, b, best.idx)), total);
-    row = (int)(id / (uint32_t)ncols);
-    col = (int)(id % (uint32_t)ncols);
-  }
-  // ---- rook pivoting: column step then row step, until the column repeats
-  int iters = 0;
-  bool invalid = !(best.v >= 0.0);
-  if (tid == 0) { sm.e_star = 0.0; sm.a_star = 0.0; }
-  for (int it = 0; it < kRook && !invalid; ++it) {
-    {   // column step: B~(:, col) = C_b F_{b+1}(:, col)
+
+  double seen = 0.0;
+  bool bad = false, invalid = false;
+  int mode = 0;            // 0: random samples, 1: column step, 2: row step
+  int row = 0, col = 0, iters = 0;
+  for (;;) {
+    if (mode == 1) {          // B~(:, col) = C_b F_{b+1}(:, col)
       const int j = col / rR, be = col - j * rR;
       if (tid < rb) sm.vec[tid] = F1[((size_t)tid * n + j) * cc1 + be];
-      __syncthreads();
-      ArgMax bc{-1.0, 0x7fffffff};
-      for (int r = tid; r < nrows; r += blockDim.x) {
-        const double a = evalA(r, col);
-        double s = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < rb; ++k) s = fma(Cb[k * ldC + r], sm.vec[k], s);
-        const double e = a - s;
-        bad |= !isfinite(e);
-        seen = fmax(seen, fabs(a));
-        if (better(fabs(e), r, bc.v, bc.idx)) { bc.v = fabs(e); bc.idx = r; }
-      }
-      bc = block_argmax(bc, sm.red_v, sm.red_i);
-      if (!(bc.v >= 0.0)) { invalid = true; break; }   // every error non-finite
-      row = bc.idx;
+    } else if (mode == 2) {   // B~(row, :) = C_b(row, :) F_{b+1}
+      if (tid < rb) sm.vec[tid] = Cb[(size_t)tid * ldC + row];
     }
-    {   // row step: B~(row, :) = C_b(row, :) F_{b+1}
-      if (tid < rb) sm.vec[tid] = Cb[tid * ldC + row];
-      __syncthreads();
-      ArgMax br{-1.0, 0x7fffffff};
-      double my_e = 0.0, my_a = 0.0;
-      for (int c = tid; c < ncols; c += blockDim.x) {
-        const double a = evalA(row, c);
-        const int j = c / rR, be = c - j * rR;
-        double s = 0.0;
+    __syncthreads();
+    const int count = mode == 0 ? nsamp : (mode == 1 ? nrows : ncols);
+    ArgMax best{-1.0, 0x7fffffff};
+    double my_e = 0.0, my_a = 0.0;
+    for (int q = tid; q < count; q += blockDim.x) {
+      int pr, pc;
+      if (mode == 0) {
+        const uint32_t id = uniform_below(splitmix_at(p.seed, sample_counter(sweep, b, q)), total);
+        pr = (int)(id / (uint32_t)ncols);
+        pc = (int)(id % (uint32_t)ncols);
+      } else if (mode == 1) {
+        pr = q;
+        pc = col;
+      } else {
+        pr = row;
+        pc = q;
+      }
+      // B at (alpha, i, j, beta): coordinates of I_<=b-1[alpha], t_i, t_j, I_>b+1[beta]
+      const int al = pr / n, i = pr - al * n;
+      const int j = pc / rR, be = pc - j * rR;
+      double y[MAXM];
+#pragma unroll
+      for (int k = 0; k < MAXM; ++k) {
+        double v = 0.0;
+        if (k < m) {
+          v = (k < b) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
+          v = (k == b) ? sm.t[i] : v;
+          v = (k == b + 1) ? sm.t[j] : v;
+        }
+        y[k] = v;
+      }
+      const double W = ((sm.Lw[al] * sm.w[i]) * sm.w[j]) * sm.Rw[be];
+      const double a = W * integrand_fam<FAM, MAXM>(fa, y);
+      double s = 0.0;
+      if (mode == 0) {
+#pragma unroll 8
+        for (int k = 0; k < rb; ++k) s = fma(Cb[(size_t)k * ldC + pr], F1[((size_t)k * n + j) * cc1 + be], s);
+      } else if (mode == 1) {
+#pragma unroll 8
+        for (int k = 0; k < rb; ++k) s = fma(Cb[(size_t)k * ldC + pr], sm.vec[k], s);
+      } else {
 #pragma unroll 8
         for (int k = 0; k < rb; ++k) s = fma(sm.vec[k], F1[((size_t)k * n + j) * cc1 + be], s);
-        const double e = a - s;
-        bad |= !isfinite(e);
-        seen = fmax(seen, fabs(a));
-        if (better(fabs(e), c, br.v, br.idx)) { br.v = fabs(e); br.idx = c; my_e = e; my_a = a; }
       }
-      br = block_argmax(br, sm.red_v, sm.red_i);
-      if (!(br.v >= 0.0)) { invalid = true; break; }
-      if (br.idx % (int)blockDim.x == tid) {   // the thread that evaluated the winner
-        sm.e_star = my_e;
-        sm.a_star = my_a;
-      }
-      __syncthreads();
-      iters = it + 1;
-      const bool same = (br.idx == col);
-      col = br.idx;
-      if (same) break;
+      const double e = a - s;
+      bad |= !isfinite(e);
+      seen = fmax(seen, fabs(a));
+      if (better(fabs(e), q, best.v, best.idx)) { best.v = fabs(e); best.idx = q; my_e = e; my_a = a; }
     }
+    best = block_argmax(best, sm.red_v, sm.red_i);
+    if (!(best.v >= 0.0)) { invalid = true; break; }   // every error non-finite
+    if (mode == 0) {
+      mark(p, sweep, b, 2);
+      const uint32_t id = uniform_below(splitmix_at(p.seed, sample_counter(sweep, b, best.idx)), total);
+      row = (int)(id / (uint32_t)ncols);
+      col = (int)(id % (uint32_t)ncols);
+      mode = 1;
+      continue;
+    }
+    if (mode == 1) {
+      row = best.idx;
+      mode = 2;
+      continue;
+    }
+    if (best.idx % (int)blockDim.x == tid) {   // the thread that evaluated the winner
+      sm.e_star = my_e;
+      sm.a_star = my_a;
+    }
+    __syncthreads();
+    ++iters;
+    const bool same = (best.idx == col);   // rook condition: the row step kept the column
+    col = best.idx;
+    if (same || iters == kRook) break;
+    mode = 1;
   }
+  mark(p, sweep, b, 3);
   seen = block_max(seen, sm.red_v);
   const int any_bad = __syncthreads_or(bad);
   // is either half of the pivot already in its set? (one thread per set element)
@@ -426,11 +459,12 @@ __global__ __launch_bounds__(kSearchBlock) void k_search(ProbDesc* __restrict__ 
     p.piv[b] = rec;
     p.log[(size_t)sweep * nb + b] = rec;
     if (any_bad || invalid) atomicOr(&st->err_flags, 1);
-    atomicAdd(&st->evals, (unsigned long long)(nsamp + iters * (nrows + ncols)));
+    const int per_step = nrows + ncols;
+    atomicAdd(&st->evals, (unsigned long long)(nsamp + iters * per_step));
   }
 }
 
-// ------------------------------------------------------------ k_update
+// ------------------------------------------------------------ core update
 template <int MAXM, int RMAX>
 struct UpdateSmem {
   union {
@@ -440,23 +474,19 @@ struct UpdateSmem {
       double Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
       double t[TT_MAX_NODES], w[TT_MAX_NODES];
     };
-    double A[RMAX * (RMAX + 1)];   // factorisation stage
+    double A[RMAX * (RMAX + 1)];   // the stored LU of the cross, zero-padded to RMAX
   };
-  double lcol[RMAX];
-  int perm[RMAX];
+  double u[RMAX], cp[RMAX];
   int rowidx[RMAX];
-  int piv;
+  double delta;
 };
 
-template <int MAXM, int RMAX>
-__global__ __launch_bounds__(kBlock) void k_update(ProbDesc* __restrict__ P,
-                                                   const int2* __restrict__ tasks, int init) {
+template <int FAM, int MAXM, int RMAX>
+__device__ __forceinline__ void update_core(const ProbDesc& p, const int c, const int init,
+                                            UpdateSmem<MAXM, RMAX>& sm, const int mb = -1) {
   constexpr int LD = MAXM + 1;
   constexpr int LA = RMAX + 1;
-  __shared__ UpdateSmem<MAXM, RMAX> sm;
-  const int2 tk = tasks[blockIdx.x];
-  const ProbDesc& p = P[tk.x];
-  const int c = tk.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   ProbState* st = p.st;
   if (st->done) return;
   const int m = p.m, n = p.n, R = p.R;
@@ -468,6 +498,7 @@ __global__ __launch_bounds__(kBlock) void k_update(ProbDesc* __restrict__ P,
   const int rR_com = hasR ? p.rank[c] : 1;
   const int rL_old = init ? 0 : rL_com, rL_new = rL_com + accL;
   const int rR_old = init ? 0 : rR_com, rR_new = rR_com + accR;
+  const int msw = init ? 0 : st->sweeps;
 
   // ---- append the accepted pivots (each set element is written by exactly one workgroup)
   if (accL) {   // new element of I_<=c-1: (alpha*, i*) with alpha* in I_<=c-2
@@ -500,18 +531,19 @@ __global__ __launch_bounds__(kBlock) void k_update(ProbDesc* __restrict__ P,
   __syncthreads();
   // ---- stage I_<=c-1 and I_>c coordinates
   for (int e = tid; e < rL_new * c; e += blockDim.x) {
-    int a = e / c, k = e % c;
+    const int a = e / c, k = e % c;
     sm.Lx[a * LD + k] = p.Lx[((size_t)(c - 1) * R + a) * m + k];
   }
   const int nright = m - c - 1;
   for (int e = tid; e < rR_new * nright; e += blockDim.x) {
-    int a = e / nright, k = c + 1 + e % nright;
+    const int a = e / nright, k = c + 1 + e % nright;
     sm.Rx[a * LD + k] = p.Rx[((size_t)c * R + a) * m + k];
   }
   for (int a = tid; a < rL_new; a += blockDim.x) sm.Lw[a] = hasL ? p.Lw[(size_t)(c - 1) * R + a] : 1.0;
   for (int a = tid; a < rR_new; a += blockDim.x) sm.Rw[a] = hasR ? p.Rw[(size_t)c * R + a] : 1.0;
   for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = p.t[i]; sm.w[i] = p.w[i]; }
   __syncthreads();
+  if (mb >= 0) mark(p, msw, mb, 9);
 
   // ---- evaluate the new entries of F_c = B(I_<=c-1, i_c, I_>c)
   double* __restrict__ Fc = p.F + p.Foff[c];
@@ -545,11 +577,12 @@ __global__ __launch_bounds__(kBlock) void k_update(ProbDesc* __restrict__ P,
       y[k] = v;
     }
     const double W = (sm.Lw[al] * sm.w[i]) * sm.Rw[be];
-    const double v = W * integrand<MAXM>(fa, y);
+    const double v = W * integrand_fam<FAM, MAXM>(fa, y);
     bad |= !isfinite(v);
     Fc[((size_t)al * n + i) * cc + be] = v;
   }
   const int any_bad = __syncthreads_or(bad);
+  if (mb >= 0) mark(p, msw, mb, 10);
   if (tid == 0) {
     atomicAdd(&st->evals, (unsigned long long)(nA + nB));
     if (any_bad) atomicOr(&st->err_flags, 1);
@@ -566,94 +599,117 @@ __global__ __launch_bounds__(kBlock) void k_update(ProbDesc* __restrict__ P,
     return;
   }
 
-  // ---- C_c = F_c M_c^-1 with M_c = rows I_<=c of F_c (GEPP of M_c^T in LDS)
+  // ---- interpolation core C_c = F_c M_c^-1, M_c = rows I_<=c of F_c (insertion order)
+  const int r0 = rR_old;     // rank of bond c before this sweep
   const int r = rR_new;
   const int N = rL_new * n;
-  if (r > RMAX) {    // the host picks RMAX >= any rank reachable this sweep
+  if (r > RMAX) {            // the host picks RMAX >= any rank reachable this sweep
     if (tid == 0) atomicOr(&st->err_flags, 8);
     return;
   }
-  __syncthreads();   // the evaluation stage's LDS is reused for the factorisation
-  for (int e = tid; e < RMAX * LA; e += blockDim.x) sm.A[e] = 0.0;
-  if (tid < r) {
-    int ri;
-    if (tid < rR_com) ri = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
-    else ri = p.piv[c].row;    // the element appended to I_<=c this sweep
-    sm.rowidx[tid] = ri;
-    sm.perm[tid] = tid;
-  }
-  __syncthreads();
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const int a = e / r, q = e % r;            // M[a][q] = F_c(rowidx[a], q) -> A[q][a]
-    sm.A[q * LA + a] = Fc[(size_t)sm.rowidx[a] * cc + q];
-  }
-  __syncthreads();
-  bool singular = false;
-  for (int k = 0; k < r; ++k) {
-    if (tid < kWave) {   // wave 0: partial pivoting, first largest |A(i,k)| over i >= k
-      ArgMax a{-1.0, 0x7fffffff};
-      for (int i = k + tid; i < r; i += kWave) {
-        const double v = fabs(sm.A[i * LA + k]);
-        if (better(v, i, a.v, a.idx)) { a.v = v; a.idx = i; }
-      }
-      a = wave_argmax(a);
-      if (tid == 0) {
-        const int pv = a.v >= 0.0 ? a.idx : k;
-        sm.piv = pv;
-        if (pv != k) { int tmp = sm.perm[k]; sm.perm[k] = sm.perm[pv]; sm.perm[pv] = tmp; }
-      }
-    }
-    __syncthreads();
-    const int pv = sm.piv;
-    if (pv != k && tid < r) {
-      const double tmp = sm.A[k * LA + tid];
-      sm.A[k * LA + tid] = sm.A[pv * LA + tid];
-      sm.A[pv * LA + tid] = tmp;
-    }
-    __syncthreads();
-    const double dg = sm.A[k * LA + k];
-    if (dg == 0.0) singular = true;
-    const int w = r - k - 1;
-    if (tid < w) sm.lcol[tid] = sm.A[(k + 1 + tid) * LA + k] / dg;
-    __syncthreads();
-    for (int e = tid; e < w * (w + 1); e += blockDim.x) {
-      const int i = k + 1 + e / (w + 1), j = k + e % (w + 1);
-      const double l = sm.lcol[i - k - 1];
-      if (j == k) sm.A[i * LA + k] = l;
-      else sm.A[i * LA + j] = fma(-l, sm.A[k * LA + j], sm.A[i * LA + j]);
-    }
-    __syncthreads();
-  }
-  if (singular && tid == 0) atomicOr(&st->err_flags, 2);
-
+  double* __restrict__ LU = p.LU + (size_t)c * R * R;
   double* __restrict__ Cc = p.C + p.Coff[c];
   const size_t ldC = (size_t)rowcap(p, c) * n;
-  for (int row = tid; row < N; row += blockDim.x) {
-    const double* __restrict__ f = Fc + (size_t)row * cc;
-    double x[RMAX];
+  __syncthreads();   // the evaluation stage's LDS is reused below
+  if (init) {        // rank 1: M_c = (B(i0)), C_c = F_c / M_c
+    const int row0 = p.Lpar[(size_t)c * R] * n + p.Lnode[(size_t)c * R];
+    const double m00 = Fc[(size_t)row0 * cc];
+    if (tid == 0) {
+      LU[0] = m00;
+      if (m00 == 0.0) atomicOr(&st->err_flags, 2);
+    }
+    for (int row = tid; row < N; row += blockDim.x) Cc[row] = Fc[(size_t)row * cc] / m00;
+  } else {
+    for (int e = tid; e < RMAX * RMAX; e += blockDim.x) {
+      const int a = e / RMAX, q = e % RMAX;
+      sm.A[a * LA + q] = (a < r0 && q < r0) ? LU[(size_t)a * R + q] : 0.0;
+    }
+    if (tid < r0) sm.rowidx[tid] = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
+    __syncthreads();
+    // (a) rows of the new element of I_<=c-1: solve x M_c = f with M_c = L U
+    //     (x L) U = f: forward over columns for g = x L, then backward over rows for x
+    if (accL) {
+      for (int i = tid; i < n; i += blockDim.x) {
+        const int row = rL_old * n + i;
+        double x[RMAX];
 #pragma unroll
-    for (int i = 0; i < RMAX; ++i) x[i] = (i < r) ? f[sm.perm[i]] : 0.0;
+        for (int q = 0; q < RMAX; ++q) x[q] = (q < r0) ? Fc[(size_t)row * cc + q] : 0.0;
 #pragma unroll
-    for (int i = 1; i < RMAX; ++i) {
-      if (i < r) {
-        double s = x[i];
+        for (int q = 0; q < RMAX; ++q) {
+          if (q < r0) {
+            double s = x[q];
 #pragma unroll
-        for (int j = 0; j < i; ++j) s = fma(-sm.A[i * LA + j], x[j], s);
-        x[i] = s;
+            for (int pp = 0; pp < q; ++pp) s = fma(-x[pp], sm.A[pp * LA + q], s);
+            x[q] = s / sm.A[q * LA + q];
+          }
+        }
+#pragma unroll
+        for (int a = RMAX - 1; a >= 0; --a) {
+          if (a < r0) {
+            double s = x[a];
+#pragma unroll
+            for (int bb = a + 1; bb < RMAX; ++bb) s = fma(-x[bb], sm.A[bb * LA + a], s);
+            x[a] = s;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < RMAX; ++a)
+          if (a < r0) Cc[(size_t)a * ldC + row] = x[a];
       }
     }
+    if (mb >= 0) mark(p, msw, mb, 11);
+    if (accR) {
+      const int prow = p.piv[c].row;   // the row of F_c appended to I_<=c this sweep
+      // (c) border the LU: w = L^-1 u, l = v U^-1, delta = F_c(prow, r0) - l . w, with
+      //     u = F_c(I_<=c, r0) the new column at the old cross rows and v = F_c(prow, :r0)
+      if (tid < kWave) {
+        double wa = (tid < r0) ? Fc[(size_t)sm.rowidx[tid] * cc + r0] : 0.0;
+        double lq = (tid < r0) ? Fc[(size_t)prow * cc + tid] : 0.0;
+        if (tid < r0) sm.u[tid] = wa;
+        for (int k2 = 0; k2 < r0; ++k2) {
+          const double wk = __shfl(wa, k2, kWave);
+          if (tid > k2 && tid < r0) wa = fma(-sm.A[tid * LA + k2], wk, wa);
+        }
+        for (int k2 = 0; k2 < r0; ++k2) {
+          const double lk = __shfl(lq, k2, kWave) / sm.A[k2 * LA + k2];
+          if (tid == k2) lq = lk;
+          else if (tid > k2 && tid < r0) lq = fma(-lk, sm.A[k2 * LA + tid], lq);
+        }
+        double prod = (tid < r0) ? lq * wa : 0.0;
 #pragma unroll
-    for (int i = RMAX - 1; i >= 0; --i) {
-      if (i < r) {
-        double s = x[i];
+        for (int off = kWave / 2; off > 0; off >>= 1) prod += __shfl_xor(prod, off, kWave);
+        const double delta = Fc[(size_t)prow * cc + r0] - prod;
+        if (tid < r0) {
+          LU[(size_t)r0 * R + tid] = lq;
+          LU[(size_t)tid * R + r0] = wa;
+        }
+        if (tid == 0) {
+          LU[(size_t)r0 * R + r0] = delta;
+          sm.delta = delta;
+          if (delta == 0.0) atomicOr(&st->err_flags, 2);
+        }
+      }
+      if (tid < r0) sm.cp[tid] = Cc[(size_t)tid * ldC + prow];   // C_c(prow, :) before the update
+      __syncthreads();
+      if (mb >= 0) mark(p, msw, mb, 12);
+      // (b) rank-1 update of every row: e = F_c(:, r0) - C_c u, C_c <- [C_c - (e/delta) c_piv, e/delta]
+      const double delta = sm.delta;
+      for (int row = tid; row < N; row += blockDim.x) {
+        double x[RMAX];
 #pragma unroll
-        for (int j = i + 1; j < RMAX; ++j) s = fma(-sm.A[i * LA + j], x[j], s);
-        x[i] = s / sm.A[i * LA + i];
+        for (int k = 0; k < RMAX; ++k) x[k] = (k < r0) ? Cc[(size_t)k * ldC + row] : 0.0;
+        double e = Fc[(size_t)row * cc + r0];
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k)
+          if (k < r0) e = fma(-x[k], sm.u[k], e);
+        const double f = e / delta;
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k)
+          if (k < r0) Cc[(size_t)k * ldC + row] = fma(-f, sm.cp[k], x[k]);
+        Cc[(size_t)r0 * ldC + row] = f;
       }
     }
-#pragma unroll
-    for (int i = 0; i < RMAX; ++i)
-      if (i < r) Cc[(size_t)i * ldC + row] = x[i];
+    if (mb >= 0) mark(p, msw, mb, 13);
   }
   __syncthreads();
   // ---- S_c(alpha, k) = sum_i C_c(alpha, i, k)
@@ -665,20 +721,31 @@ __global__ __launch_bounds__(kBlock) void k_update(ProbDesc* __restrict__ P,
     for (int i = 0; i < n; ++i) s += src[i];
     S[(size_t)al * R + k] = s;
   }
+  if (mb >= 0) {
+    __syncthreads();
+    mark(p, msw, mb, 14);
+  }
 }
 
 // ------------------------------------------------------------ k_integral
-constexpr int kIntBlock = 256;
+constexpr int kIntBlock = 512;
 constexpr int kIntStage = 6144;   // doubles of S staged in LDS at once (48 KiB)
 
-__global__ __launch_bounds__(kIntBlock) void k_integral(ProbDesc* __restrict__ P, int init) {
-  const ProbDesc& p = P[blockIdx.x];
+struct IntSmem {
+  double v[TT_MAX_RANK], v2[TT_MAX_RANK];
+  double stage[kIntStage];
+  int s_rank[TT_MAX_MODES];
+  int s_off[TT_MAX_MODES + 1];
+};
+
+__device__ __forceinline__ void integral_problem(const ProbDesc& p, const int init, IntSmem& sm) {
   ProbState* st = p.st;
   if (st->done) return;
-  __shared__ double v[TT_MAX_RANK], v2[TT_MAX_RANK];
-  __shared__ double stage[kIntStage];
-  __shared__ int s_rank[TT_MAX_MODES];
-  __shared__ int s_off[TT_MAX_MODES + 1];
+  double* v = sm.v;
+  double* v2 = sm.v2;
+  double* stage = sm.stage;
+  int* s_rank = sm.s_rank;
+  int* s_off = sm.s_off;
   const int m = p.m, R = p.R, nb = p.nbonds, tid = threadIdx.x;
   // commit the ranks: r_b += accepted_b (one thread per bond)
   int acc = 0, r = 0;
@@ -764,6 +831,83 @@ __global__ __launch_bounds__(kIntBlock) void k_integral(ProbDesc* __restrict__ P
     st->done = 1;
     if (st->reason == TT_RUNNING) st->reason = TT_STOP_CONVERGED;
   }
+  if (st->done) signal_done(p);
+}
+
+// ------------------------------------------------------------ kernels
+template <int FAM, int MAXM, int RMAX>
+__global__ __launch_bounds__(kSweepBlock) void k_update(ProbDesc* __restrict__ P,
+                                                        const int2* __restrict__ tasks, int init) {
+  __shared__ UpdateSmem<MAXM, RMAX> sm;
+  const int2 tk = tasks[blockIdx.x];
+  update_core<FAM, MAXM, RMAX>(P[tk.x], tk.y, init, sm);
+}
+
+static __global__ __launch_bounds__(kIntBlock) void k_integral(ProbDesc* __restrict__ P, int init) {
+  __shared__ IntSmem sm;
+  integral_problem(P[blockIdx.x], init, sm);
+}
+
+template <int MAXM, int RMAX>
+union SweepSmem {
+  SearchSmem<MAXM> s;
+  UpdateSmem<MAXM, RMAX> u;
+  IntSmem i;
+};
+
+// One sweep of Alg. 6 in one launch, one workgroup per superblock.  Every
+// workgroup searches its superblock; a core is updated by whichever of its two
+// neighbouring superblocks finishes last, and the quadrature by whichever core
+// finishes last.  Each hand-over is a release fence plus an atomic increment,
+// observed by the arriving workgroup after an acquire fence; no workgroup waits
+// for another, so any subset of workgroups may be resident at a time.
+template <int FAM, int MAXM, int RMAX>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
+                                                       const int2* __restrict__ tasks) {
+  __shared__ SweepSmem<MAXM, RMAX> sm;
+  __shared__ int s_todo[3];
+  __shared__ int s_last;
+  const int2 tk = tasks[blockIdx.x];
+  const ProbDesc& p = P[tk.x];
+  const int b = tk.y, tid = threadIdx.x, m = p.m;
+  if (p.st->done) return;
+  const int sweep = p.st->sweeps;
+  search_bond<FAM, MAXM>(p, b, sm.s);
+  __syncthreads();
+  mark(p, sweep, b, 4);
+  if (tid == 0) {
+    __threadfence();
+    int nt = 0;
+    for (int c = b; c <= b + 1; ++c) {
+      const int target = (c >= 1 ? 1 : 0) + (c <= m - 2 ? 1 : 0);
+      if (atomicAdd(&p.sync[c], 1) + 1 == target) s_todo[nt++] = c;
+    }
+    s_todo[2] = nt;
+    __threadfence();
+  }
+  __syncthreads();
+  const int nt = s_todo[2];
+  mark(p, sweep, b, 8);
+  for (int q = 0; q < nt; ++q) {
+    const int c = s_todo[q];
+    update_core<FAM, MAXM, RMAX>(p, c, 0, sm.u, b);
+    __syncthreads();
+    mark(p, sweep, b, 5);
+    if (tid == 0) {
+      __threadfence();
+      s_last = (atomicAdd(&p.sync[m], 1) + 1 == m);
+      __threadfence();
+    }
+    __syncthreads();
+    if (s_last) {
+      integral_problem(p, 0, sm.i);
+      __syncthreads();
+      for (int k = tid; k <= m; k += blockDim.x) p.sync[k] = 0;   // every hand-over of this sweep is done
+      mark(p, sweep, b, 6);
+    }
+    __syncthreads();
+  }
+  mark(p, sweep, b, 7);
 }
 
 // ------------------------------------------------------- standalone eval
@@ -792,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(FamilyArgs fa, const dou
 
 // Fibre set I_left x [n] x I_right at mode `pos`: one point per lane, the
 // index rows and node tables staged in LDS, output ordered (alpha, i, beta).
-template <int MAXM>
+template <int FAM, int MAXM>
 __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, const double* __restrict__ t,
                                                         const double* __restrict__ w, int pos,
                                                         const int32_t* __restrict__ left, int rl,
@@ -841,7 +985,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, co
       y[k] = v;
     }
     const double W = (sLw[al] * sw[i]) * sRw[be];
-    out[q] = W * integrand<MAXM>(fa, y);
+    out[q] = W * integrand_fam<FAM, MAXM>(fa, y);
   }
 }
 

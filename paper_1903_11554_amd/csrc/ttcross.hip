@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "tt_kernels.hpp"
+#include "tt_launch.hpp"
 
 using namespace ttx;
 
@@ -31,7 +32,7 @@ static hipError_t& last_hip_error() {
 }
 
 // kernel kinds timed by the optional event profiler
-enum { KK_SEARCH = 0, KK_UPDATE = 1, KK_INTEGRAL = 2, KK_START = 3, KK_GL = 4, KK_EVAL_POINTS = 5,
+enum { KK_SWEEP = 0, KK_UPDATE = 1, KK_INTEGRAL = 2, KK_START = 3, KK_GL = 4, KK_EVAL_POINTS = 5,
        KK_EVAL_FIBERS = 6, KK_COUNT = 7 };
 
 struct tt_ctx {
@@ -70,10 +71,13 @@ struct tt_job {
   int2* dcore = nullptr;
   int ncore = 0;
   int maxm = 0, maxR = 1;
+  int fam = 3;            // integrand class the job's kernels are specialised for
   int launched = 0;       // sweeps enqueued so far
   int max_sweeps_all = 0;
   ProbState* dstate = nullptr;
   std::vector<char> image;   // host image of the table region (source of the async upload)
+  int32_t* done_host = nullptr;            // pinned, one flag per integral, written by the kernels
+  std::vector<hipEvent_t> ring;            // one event per queued sweep (tt_cross_run)
 };
 
 namespace {
@@ -133,6 +137,12 @@ int modes_of(const tt_problem& p) {
 
 bool is_synthetic(int f) { return f == TT_PROD_EXP || f == TT_SUM2_EXP_COS; }
 
+int fam_of(int f) {
+  if (f == TT_ISING_C || f == TT_ISING_D || f == TT_ISING_E) return FAM_PAPER;
+  if (f == TT_ISING_C_U || f == TT_ISING_D_U) return FAM_UFORM;
+  return FAM_SYNTH;
+}
+
 tt_status validate(const tt_problem* p) {
   if (!p) return TT_EINVAL;
   const int m = modes_of(*p);
@@ -162,7 +172,8 @@ struct Layout {
 };
 
 struct ProbOffsets {
-  size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, S, rank, piv, scale, log, hist, start;
+  size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, LU, S, rank, piv, scale, log, hist, start, sync,
+      phase;
   std::vector<int64_t> foff, coff;
 };
 
@@ -193,6 +204,7 @@ ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   }
   o.F = L.take((size_t)fsz * D);
   o.C = L.take((size_t)csz * D);
+  o.LU = L.take((size_t)(nb > 0 ? nb : 1) * R * R * D);
   o.S = L.take((size_t)(m > 0 ? m : 1) * R * R * D);
   o.rank = L.take((size_t)(nb > 0 ? nb : 1) * I);
   o.piv = L.take((size_t)(nb > 0 ? nb : 1) * sizeof(PivRec));
@@ -200,11 +212,13 @@ ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   o.log = L.take((size_t)ms * (nb > 0 ? nb : 1) * sizeof(PivRec));
   o.hist = L.take((size_t)(ms + 1) * D);
   o.start = L.take((size_t)(m > 0 ? m : 1) * I);
+  o.sync = L.take((size_t)(m + 1) * I);
+  o.phase = L.take((size_t)ms * (nb > 0 ? nb : 1) * kPhases * sizeof(long long));
   return o;
 }
 
-int bucket_m(int m) { return m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : 32; }
-int bucket_r(int r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : 64; }
+int bucket_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : 32; }
+int bucket_r(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : 64; }
 
 double four_over_fact(int m) {
   double f = 1.0;
@@ -212,56 +226,23 @@ double four_over_fact(int m) {
   return 4.0 / f;
 }
 
-template <int MAXM>
-void launch_search(tt_job* j) {
-  Timed tm(j->ctx, KK_SEARCH);
-  hipLaunchKernelGGL(k_search<MAXM>, dim3(j->nbond), dim3(kSearchBlock), 0, j->ctx->stream, j->ddesc,
-                     (const int2*)j->dbond);
-}
-template <int MAXM, int RMAX>
-void launch_update(tt_job* j, int init) {
-  Timed tm(j->ctx, KK_UPDATE);
-  hipLaunchKernelGGL((k_update<MAXM, RMAX>), dim3(j->ncore), dim3(kBlock), 0, j->ctx->stream,
-                     j->ddesc, (const int2*)j->dcore, init);
-}
-template <int MAXM>
-void launch_update_r(tt_job* j, int rb, int init) {
-  switch (rb) {
-    case 4: launch_update<MAXM, 4>(j, init); break;
-    case 8: launch_update<MAXM, 8>(j, init); break;
-    case 16: launch_update<MAXM, 16>(j, init); break;
-    case 32: launch_update<MAXM, 32>(j, init); break;
-    default: launch_update<MAXM, 64>(j, init); break;
+void launch(tt_job* j, int what, int rb) {
+  LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, bucket_m(j->maxm), j->ctx->stream};
+  Timed tm(j->ctx, what == LAUNCH_SWEEP ? KK_SWEEP : what == LAUNCH_START ? KK_START : KK_UPDATE);
+  switch (j->fam) {
+    case FAM_PAPER: launch_paper(a, what, rb); break;
+    case FAM_UFORM: launch_uform(a, what, rb); break;
+    case FAM_SYNTH: launch_synth(a, what, rb); break;
+    default: launch_any(a, what, rb); break;
   }
 }
-
-void enqueue_update(tt_job* j, int rb, int init) {
-  switch (bucket_m(j->maxm)) {
-    case 4: launch_update_r<4>(j, rb, init); break;
-    case 8: launch_update_r<8>(j, rb, init); break;
-    case 16: launch_update_r<16>(j, rb, init); break;
-    default: launch_update_r<32>(j, rb, init); break;
-  }
-}
-void enqueue_search(tt_job* j) {
-  switch (bucket_m(j->maxm)) {
-    case 4: launch_search<4>(j); break;
-    case 8: launch_search<8>(j); break;
-    case 16: launch_search<16>(j); break;
-    default: launch_search<32>(j); break;
-  }
-}
+void enqueue_update(tt_job* j, int, int) { launch(j, LAUNCH_INIT_UPDATE, 8); }
+void enqueue_sweep(tt_job* j, int rb) { launch(j, LAUNCH_SWEEP, rb); }
 
 tt_status enqueue_sweeps(tt_job* j, int n_sweeps) {
   for (int s = 0; s < n_sweeps; ++s) {
     if (j->launched >= j->max_sweeps_all) break;
-    if (j->nbond > 0) {
-      const int rb = bucket_r(std::min(j->maxR, j->launched + 2));
-      enqueue_search(j);
-      enqueue_update(j, rb, 0);
-      Timed tm(j->ctx, KK_INTEGRAL);
-      hipLaunchKernelGGL(k_integral, dim3(j->nprob), dim3(kIntBlock), 0, j->ctx->stream, j->ddesc, 0);
-    }
+    if (j->nbond > 0) enqueue_sweep(j, bucket_r(std::min(j->maxR, j->launched + 2)));
     ++j->launched;
   }
   TT_HIP(hipGetLastError());
@@ -451,6 +432,8 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
     j->maxm = std::max(j->maxm, m);
     j->maxR = std::max(j->maxR, problems[k].rank_cap);
     j->max_sweeps_all = std::max(j->max_sweeps_all, max_sweeps_of(problems[k]));
+    const int fk = fam_of(problems[k].integrand);
+    j->fam = (k == 0) ? fk : (j->fam == fk ? fk : FAM_ANY);
     if (m >= 2) {
       for (int b = 0; b < m - 1; ++b) bond_tasks.push_back(make_int2(k, b));
       for (int c = 0; c < m; ++c) core_tasks.push_back(make_int2(k, c));
@@ -494,6 +477,7 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   auto fail = [&](tt_status s) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(j->arena);
+    if (j->done_host) (void)hipHostFree(j->done_host);
     delete j;
     return s;
   };
@@ -505,6 +489,9 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->ncore = (int)core_tasks.size();
   j->image.assign(table_bytes, 0);
   char* img = j->image.data();
+  if (hipHostMalloc((void**)&j->done_host, sizeof(int32_t) * count, hipHostMallocDefault) != hipSuccess)
+    return fail(TT_ENOMEM);
+  for (int k = 0; k < count; ++k) j->done_host[k] = 0;
   for (int k = 0; k < count; ++k) {
     const tt_problem& p = problems[k];
     const ProbOffsets& o = offs[k];
@@ -535,6 +522,7 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
     d.F = (double*)(pb + o.F);
     d.Foff = (int64_t*)(base + foff_at[k]);
     d.C = (double*)(pb + o.C);
+    d.LU = (double*)(pb + o.LU);
     d.Coff = (int64_t*)(base + coff_at[k]);
     d.S = (double*)(pb + o.S);
     d.rank = (int32_t*)(pb + o.rank);
@@ -543,6 +531,9 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
     d.log = (PivRec*)(pb + o.log);
     d.hist = (double*)(pb + o.hist);
     d.start = (int32_t*)(pb + o.start);
+    d.sync = (int32_t*)(pb + o.sync);
+    d.done_host = j->done_host + k;
+    d.phase = ctx->profiling ? (long long*)(pb + o.phase) : nullptr;
     d.st = j->dstate + k;
     j->hdesc.push_back(d);
     if (!o.foff.empty()) std::memcpy(img + foff_at[k], o.foff.data(), o.foff.size() * sizeof(int64_t));
@@ -558,15 +549,7 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   // one table upload (the host image lives until the job is freed), then the kernels, all in stream order
   if (hipMemcpyAsync(base, img, table_bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
     return fail(TT_EDEVICE);
-  {
-    Timed tm(ctx, KK_START);
-    switch (bucket_m(j->maxm)) {
-      case 4: hipLaunchKernelGGL(k_start<4>, dim3(count), dim3(kBlock), 0, ctx->stream, j->ddesc); break;
-      case 8: hipLaunchKernelGGL(k_start<8>, dim3(count), dim3(kBlock), 0, ctx->stream, j->ddesc); break;
-      case 16: hipLaunchKernelGGL(k_start<16>, dim3(count), dim3(kBlock), 0, ctx->stream, j->ddesc); break;
-      default: hipLaunchKernelGGL(k_start<32>, dim3(count), dim3(kBlock), 0, ctx->stream, j->ddesc); break;
-    }
-  }
+  launch(j, LAUNCH_START, 8);
   if (j->ncore > 0) {
     enqueue_update(j, 4, 1);
     Timed tm(ctx, KK_INTEGRAL);
@@ -575,8 +558,10 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   if (hipGetLastError() != hipSuccess) return fail(TT_EDEVICE);
   std::vector<ProbState> st;
   if (read_states(j, st) != TT_OK) return fail(TT_EDEVICE);
-  for (int k = 0; k < count; ++k)
+  for (int k = 0; k < count; ++k) {
     if (st[k].err_flags & (1 | 4)) return fail(TT_ENUMERIC);
+    if (st[k].done) j->done_host[k] = 1;
+  }
   *out = j;
   return TT_OK;
 }
@@ -598,14 +583,51 @@ tt_status tt_cross_sweep(tt_job* j, int32_t n_sweeps, tt_info* info) {
   return all ? TT_CONVERGED : TT_NOT_CONVERGED;
 }
 
+// Sweeps are queued kQueued ahead of the last one known complete; after each
+// completed sweep the host reads the pinned done flags that the kernels write,
+// and stops queueing once every integral has stopped.  Sweeps still queued for
+// stopped integrals return at once.
+static const int kQueued = 4;
+
 tt_status tt_cross_run(tt_job* j, tt_info* info) {
   if (!j) return TT_EINVAL;
-  for (;;) {
-    const int before = j->launched;
-    tt_status s = tt_cross_sweep(j, 4, info);
-    if (s != TT_NOT_CONVERGED) return s;
-    if (j->launched == before) return TT_NOT_CONVERGED;   // max sweeps exhausted
+  {
+    std::lock_guard<std::mutex> lock(j->ctx->mu);
+    TT_HIP(hipSetDevice(j->ctx->device));
+    while ((int)j->ring.size() < kQueued) {
+      hipEvent_t e;
+      TT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      j->ring.push_back(e);
+    }
+    auto all_done = [&]() {
+      for (int k = 0; k < j->nprob; ++k)
+        if (__atomic_load_n(&j->done_host[k], __ATOMIC_ACQUIRE) == 0) return false;
+      return true;
+    };
+    int queued = 0;   // sweeps queued by this call
+    while (j->launched < j->max_sweeps_all && !all_done()) {
+      if (queued >= kQueued) {
+        TT_HIP(hipEventSynchronize(j->ring[queued % kQueued]));
+        if (all_done()) break;
+      }
+      tt_status s = enqueue_sweeps(j, 1);
+      if (s != TT_OK) return s;
+      TT_HIP(hipEventRecord(j->ring[queued % kQueued], j->ctx->stream));
+      ++queued;
+    }
   }
+  std::vector<ProbState> st;
+  {
+    std::lock_guard<std::mutex> lock(j->ctx->mu);
+    tt_status s = read_states(j, st);
+    if (s != TT_OK) return s;
+  }
+  bool all = true;
+  for (int k = 0; k < j->nprob; ++k) {
+    if (info) fill_info(st[k], &info[k]);
+    all = all && st[k].done;
+  }
+  return all ? TT_CONVERGED : TT_NOT_CONVERGED;
 }
 
 tt_status tt_cross_integrate(tt_job* j, double* values, tt_info* info) {
@@ -701,6 +723,26 @@ tt_status tt_job_index_sets(tt_job* j, int32_t k, int32_t* ranks, int32_t* nodes
   return TT_OK;
 }
 
+tt_status tt_job_phase_times(tt_job* j, int32_t k, int64_t* marks, int64_t capacity, int64_t* written,
+                             double* clock_mhz) {
+  if (!j || k < 0 || k >= j->nprob || !marks || !written || !clock_mhz) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  std::vector<ProbState> st;
+  tt_status s = read_states(j, st);
+  if (s != TT_OK) return s;
+  const ProbDesc& d = j->hdesc[k];
+  *written = 0;
+  int rate_khz = 0;
+  TT_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, j->ctx->device));
+  *clock_mhz = rate_khz / 1000.0;
+  if (!d.phase) return TT_OK;
+  const int64_t nrec = (int64_t)st[k].sweeps * d.nbonds * kPhases;
+  if (nrec > capacity) return TT_EINVAL;
+  if (nrec > 0) TT_HIP(hipMemcpy(marks, d.phase, nrec * sizeof(long long), hipMemcpyDeviceToHost));
+  *written = nrec;
+  return TT_OK;
+}
+
 tt_status tt_job_nodes(tt_job* j, int32_t k, double* t, double* w) {
   if (!j || k < 0 || k >= j->nprob || !t || !w) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(j->ctx->mu);
@@ -717,6 +759,8 @@ void tt_cross_free(tt_job* j) {
   std::lock_guard<std::mutex> lock(c->mu);
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (j->done_host) (void)hipHostFree(j->done_host);
+  for (hipEvent_t e : j->ring) (void)hipEventDestroy(e);
   if (c->arena_bytes_cached + j->bytes <= kArenaCacheBytes) {
     c->arenas.emplace(j->bytes, j->arena);
     c->arena_bytes_cached += j->bytes;
@@ -742,7 +786,6 @@ tt_status tt_eval_points(tt_ctx* ctx, const tt_problem* p, const int32_t* d_idx,
   const dim3 grid((unsigned)blocks64), block(kBlock);
   Timed tm(ctx, KK_EVAL_POINTS);
   switch (bucket_m(fa.m)) {
-    case 4: hipLaunchKernelGGL(k_eval_points<4>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
     case 8: hipLaunchKernelGGL(k_eval_points<8>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
     case 16: hipLaunchKernelGGL(k_eval_points<16>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
     default: hipLaunchKernelGGL(k_eval_points<32>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
@@ -772,12 +815,21 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
   const dim3 grid((unsigned)blocks64), block(kBlock);
   const int n = p->n_nodes;
   Timed tm(ctx, KK_EVAL_FIBERS);
-  switch (bucket_m(m)) {
-    case 4: hipLaunchKernelGGL(k_eval_fibers<4>, grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
-    case 8: hipLaunchKernelGGL(k_eval_fibers<8>, grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
-    case 16: hipLaunchKernelGGL(k_eval_fibers<16>, grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
-    default: hipLaunchKernelGGL(k_eval_fibers<32>, grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
+  const int fam = fam_of(p->integrand);
+#define TT_FIB(F, M)                                                                                   \
+  hipLaunchKernelGGL((k_eval_fibers<F, M>), grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, \
+                     d_right, r_right, d_out)
+#define TT_FIB_M(F)              \
+  switch (bucket_m(m)) {         \
+    case 8: TT_FIB(F, 8); break;   \
+    case 16: TT_FIB(F, 16); break; \
+    default: TT_FIB(F, 32); break; \
   }
+  if (fam == FAM_PAPER) { TT_FIB_M(FAM_PAPER) }
+  else if (fam == FAM_UFORM) { TT_FIB_M(FAM_UFORM) }
+  else { TT_FIB_M(FAM_SYNTH) }
+#undef TT_FIB_M
+#undef TT_FIB
   TT_HIP(hipGetLastError());
   return TT_OK;
 }

@@ -57,10 +57,10 @@ EXPORTS = [
     "tt_cross_init", "tt_cross_sweep", "tt_cross_run", "tt_cross_integrate",
     "tt_job_pivot_log", "tt_job_history", "tt_job_index_sets", "tt_job_nodes",
     "tt_cross_free", "tt_eval_points", "tt_eval_fibers", "tt_status_string",
-    "tt_ctx_profile", "tt_ctx_kernel_time",
+    "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
 ]
 
-KERNEL_KINDS = {"search": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
+KERNEL_KINDS = {"sweep": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
                 "eval_points": 5, "eval_fibers": 6}
 
 _lib = None
@@ -100,6 +100,7 @@ def load_library():
         "tt_status_string": (ctypes.c_char_p, [i32]),
         "tt_ctx_profile": (i32, [vp, i32]),
         "tt_ctx_kernel_time": (i32, [vp, i32, P(i64), P(dbl)]),
+        "tt_job_phase_times": (i32, [vp, i32, P(i64), i64, P(i64), P(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -287,6 +288,22 @@ class Job:
             pos += r * w
             out.append((left, right))
         return out
+
+    def phase_times(self, k):
+        """(marks[sweep, superblock, 16], clock MHz) of the sweep kernel, or None if not profiled."""
+        p = self.problems[k]
+        nb = max(p.modes() - 1, 0)
+        ms = p.max_sweeps if p.max_sweeps > 0 else 4 * p.rank_cap
+        cap = max(1, ms * nb * 16)
+        buf = (ctypes.c_int64 * cap)()
+        written = ctypes.c_int64()
+        mhz = ctypes.c_double()
+        _check(self._lib.tt_job_phase_times(self.handle, k, buf, cap, ctypes.byref(written),
+                                            ctypes.byref(mhz)), "tt_job_phase_times")
+        if written.value == 0:
+            return None
+        arr = np.array(buf[:written.value], dtype=np.int64).reshape(-1, nb, 16)
+        return arr, mhz.value
 
     def nodes(self, k):
         n = self.problems[k].n
