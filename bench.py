@@ -205,6 +205,19 @@ def cpu_baseline(probs, budget_s):
                 integrals_per_s=len(done) / t_used)
 
 
+def copy_calibration(mib=1024, reps=4):
+    """A plain device-to-device copy of known size, the yardstick for the HBM byte counters."""
+    import torch
+    torch.cuda.set_device(0)
+    src = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 8, "copies": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,7 +225,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (yardstick for rocprofv3 byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); integrals are independent "
               f"and shard across GPUs without communication, which this build does not run.",

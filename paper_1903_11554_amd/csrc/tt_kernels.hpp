@@ -741,6 +741,10 @@ struct IntSmem {
 __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int init, IntSmem& sm) {
   ProbState* st = p.st;
   if (st->done) return;
+  // state needed by the stopping rule, loaded now so its latency overlaps the chain
+  const int sw0 = st->sweeps;
+  const double prev = p.hist[sw0];
+  const double prev_rel = st->rel;
   double* v = sm.v;
   double* v2 = sm.v2;
   double* stage = sm.stage;
@@ -785,7 +789,7 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
       for (int e = tid; e < rl * rr; e += blockDim.x) dst[e] = S[(size_t)(e / rr) * R + e % rr];
     }
     __syncthreads();
-    for (int c = c0; c < c1; ++c) {
+    for (int c = c0; c < c1; ++c) {   // ping-pong between v and v2: one barrier per core
       const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
       const double* Sc = stage + s_off[c - c0];
       for (int k = tid; k < rr; k += blockDim.x) {
@@ -793,8 +797,9 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
         for (int a = 0; a < rl; ++a) s = fma(v[a], Sc[a * rr + k], s);
         v2[k] = s;
       }
-      __syncthreads();
-      for (int k = tid; k < rr; k += blockDim.x) v[k] = v2[k];
+      double* tmp = v;
+      v = v2;
+      v2 = tmp;
       __syncthreads();
     }
     c0 = c1;
@@ -808,30 +813,33 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
     st->value = value;
     return;
   }
-  const double prev = p.hist[st->sweeps];
   const double rel = value != 0.0 ? fabs(value - prev) / fabs(value) : __builtin_huge_val();
-  const double prev_rel = st->rel;
-  const int s = st->sweeps + 1;
+  const int s = sw0 + 1;
   st->sweeps = s;
   p.hist[s] = value;
   st->value = value;
   st->rel = rel;
   st->nacc = nacc;
+  int done = 0, reason = TT_RUNNING;
   if (rel <= p.tol && prev_rel <= p.tol) {
-    st->done = 1;
-    st->reason = TT_STOP_CONVERGED;
+    done = 1;
+    reason = TT_STOP_CONVERGED;
   } else if (nacc == 0) {
-    st->done = 1;
-    st->reason = below_cap ? TT_STOP_CONVERGED : TT_STOP_RANK_CAP;
+    done = 1;
+    reason = below_cap ? TT_STOP_CONVERGED : TT_STOP_RANK_CAP;
   } else if (s >= p.max_sweeps) {
-    st->done = 1;
-    st->reason = TT_STOP_MAX_SWEEPS;
+    done = 1;
+    reason = TT_STOP_MAX_SWEEPS;
   }
   if (st->err_flags) {
-    st->done = 1;
-    if (st->reason == TT_RUNNING) st->reason = TT_STOP_CONVERGED;
+    done = 1;
+    if (reason == TT_RUNNING) reason = TT_STOP_CONVERGED;
   }
-  if (st->done) signal_done(p);
+  if (done) {
+    st->reason = reason;
+    st->done = 1;
+    signal_done(p);
+  }
 }
 
 // ------------------------------------------------------------ kernels
@@ -934,8 +942,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(FamilyArgs fa, const dou
   }
 }
 
-// Fibre set I_left x [n] x I_right at mode `pos`: one point per lane, the
-// index rows and node tables staged in LDS, output ordered (alpha, i, beta).
+// Fibre set I_left x [n] x I_right at mode `pos`: one point per lane, the index
+// rows and node tables staged in LDS once per workgroup, output ordered
+// (alpha, i, beta) with beta fastest.  The grid is bounded and strides over the
+// points; each lane advances its (alpha, i, beta) by the fixed stride with
+// carries instead of dividing.
 template <int FAM, int MAXM>
 __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, const double* __restrict__ t,
                                                         const double* __restrict__ w, int pos,
@@ -968,12 +979,15 @@ __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, co
     sRw[a] = ww;
   }
   __syncthreads();
-  const int64_t total = (int64_t)rl * n * rr;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + tid; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int be = (int)(q % rr);
-    const int64_t rest = q / rr;
-    const int i = (int)(rest % n);
-    const int al = (int)(rest / n);
+  const uint32_t total = (uint32_t)rl * (uint32_t)n * (uint32_t)rr;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  uint32_t q = blockIdx.x * blockDim.x + tid;
+  if (q >= total) return;
+  // position of q and the stride in (alpha, i, beta)
+  int be = (int)(q % (uint32_t)rr), i = (int)((q / (uint32_t)rr) % (uint32_t)n), al = (int)(q / ((uint32_t)rr * n));
+  const int dbe = (int)(stride % (uint32_t)rr), di = (int)((stride / (uint32_t)rr) % (uint32_t)n);
+  const int dal = (int)(stride / ((uint32_t)rr * n));
+  for (; q < total; q += stride) {
     double y[MAXM];
 #pragma unroll
     for (int k = 0; k < MAXM; ++k) {
@@ -986,6 +1000,13 @@ __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, co
     }
     const double W = (sLw[al] * sw[i]) * sRw[be];
     out[q] = W * integrand_fam<FAM, MAXM>(fa, y);
+    be += dbe;
+    int ci = 0;
+    if (be >= rr) { be -= rr; ci = 1; }
+    i += di + ci;
+    int ca = 0;
+    if (i >= n) { i -= n; ca = 1; }
+    al += dal + ca;
   }
 }
 

@@ -810,8 +810,8 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
   FamilyArgs fa;
   s = family_for(ctx, p, &fa);
   if (s != TT_OK) return s;
-  const int64_t total = (int64_t)r_left * p->n_nodes * r_right;
-  const int64_t blocks64 = std::min<int64_t>((total + kBlock - 1) / kBlock, 1 << 20);
+  const int64_t total = (int64_t)r_left * p->n_nodes * r_right;   // < 2^31 by the rank and node limits
+  const int64_t blocks64 = std::min<int64_t>((total + kBlock - 1) / kBlock, 2048);
   const dim3 grid((unsigned)blocks64), block(kBlock);
   const int n = p->n_nodes;
   Timed tm(ctx, KK_EVAL_FIBERS);
