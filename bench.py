@@ -25,6 +25,31 @@ METRIC = "integrand evals/s; D_n integrals/s at 1e-10 rel err; p50/p99 solve lat
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector (FMA = 2 flops)
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per k_sweep launch on this workload from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (KiB per dispatch, mean over every launch of 4 jobs), scaled by
+# what the same counters read for a 1 GiB device copy (FETCH 2.0, WRITE 1.0).
+# Valid only for the kernel sources they were taken on (hash below); for any
+# other source the traffic is reported as null.
+SWEEP_TRAFFIC = {"source_hash": "52e6d5d5e1955bf1", "fetch_kib": 2745.5, "fetch_scale": 2.0,
+                 "write_kib": 1644.2, "write_scale": 1.0}
+KERNEL_SOURCES = ("tt_device.hpp", "tt_inst.hip", "tt_kernels.hpp", "tt_launch.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1903_11554_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def sweep_traffic_bytes():
+    t = SWEEP_TRAFFIC
+    if kernel_source_hash() != t["source_hash"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def flops_per_eval(family, m, weight_muls):
     """Algorithmic FP64 flops of one weighted integrand value (FMA = 2).
@@ -58,11 +83,16 @@ def sweep_work(job, k, prob):
     (new row: n r_c', new column: r_{c-1} n), the LU of the r x r cross
     (2 r^3 / 3) and the triangular solves of its r_{c-1}' n rows (2 r^2 each),
     and the core sum (r_{c-1}' n r_c'); the quadrature adds 2 r_{c-1} r_c per core.
+
+    Algorithmic bytes: the samples and every rook iteration read the
+    interpolation core C_b and the fibre core F_{b+1} once (8 (r_{b-1} n r_b +
+    r_b n r_{b+1})); each core update writes its new fibre entries, reads and
+    writes C_c (16 r_{c-1}' n r_c') and reads it again for the core sum.
     """
     m, n = prob.modes(), prob.n
     nb = m - 1
     ranks = [1] * nb
-    evals = flops = 0
+    evals = flops = nbytes = 0
     fs = flops_per_eval(prob.family, m, 4)
     fc = flops_per_eval(prob.family, m, 3)
     for sweep in job.pivot_log(k):
@@ -75,6 +105,7 @@ def sweep_work(job, k, prob):
             e = min(nrows + ncols, 1024) + rec["iters"] * (nrows + ncols)
             evals += e
             flops += e * (fs + 2 * ranks[b])
+            nbytes += (1 + rec["iters"]) * 8 * (rl * n * ranks[b] + ranks[b] * n * rr)
         new = [ranks[b] + (1 if sweep[b]["accepted"] else 0) for b in range(nb)]
         for c in range(m):
             rl_old = ranks[c - 1] if c > 0 else 1
@@ -84,12 +115,13 @@ def sweep_work(job, k, prob):
             e = (rl_new - rl_old) * n * rr_new + rl_old * n * (rr_new - rr_old)
             evals += e
             flops += e * fc
+            nbytes += 8 * e + 24 * rl_new * n * rr_new
             if c < nb:
                 r = rr_new
                 flops += 2 * r ** 3 // 3 + 2 * rl_new * n * r * r + rl_new * n * r
             flops += 2 * rl_new * rr_new
         ranks = new
-    return evals, flops
+    return evals, flops, nbytes
 
 
 def workload():
@@ -142,11 +174,12 @@ def run_gpu(args):
     ctx.profile(True)
     job, pinfos = step()
     kt = {k: ctx.kernel_time(k) for k in ("sweep", "update", "integral", "start", "gl")}
-    s_evals = s_flops = 0
+    s_evals = s_flops = s_bytes = 0
     for k, p in enumerate(probs):
-        e, f = sweep_work(job, k, p)
+        e, f, nb = sweep_work(job, k, p)
         s_evals += e
         s_flops += f
+        s_bytes += nb
     sweeps = max(i["sweeps"] for i in pinfos)
     job.free()
     ctx.profile(False)
@@ -180,7 +213,7 @@ def run_gpu(args):
             errs[f"{p.family}_{p.d}"] = abs(inf["value"] / refs[key] - 1)
     ctx.close()
     return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
-                s_evals=s_evals, s_flops=s_flops, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
+                s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
                 errs=errs, probs=probs)
 
 
@@ -249,7 +282,9 @@ def main():
     roof = {"kernel": "k_sweep (one launch per sweep: pivot search of every superblock, core updates, "
                       "quadrature and stopping rule; one workgroup per superblock)",
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": sweep_traffic_bytes(),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "alg_bytes_per_launch": r["s_bytes"] / max(nl_s, 1),
             "launches": nl_s, "avg_launch_ms": ms_s / max(nl_s, 1),
             "flops_per_launch": r["s_flops"] / max(nl_s, 1), "evals_per_launch": r["s_evals"] / max(nl_s, 1)}
     nl, ms, npts, ff, ft = r["fib"]
