@@ -28,7 +28,7 @@ def run_oracle(p):
                            max_sweeps=p.max_sweeps, params=p.params)
 
 
-def compare(job, k, p, ref, exact_log=True):
+def compare(job, k, p, ref, exact_log=True, value_scale=None):
     """Compare the GPU run of integral k with the oracle run `ref` of the same problem.
 
     A record where both sides accept must agree in position (it defines the next
@@ -38,6 +38,14 @@ def compare(job, k, p, ref, exact_log=True):
     noise once the superblock is resolved.  Any other difference is a decision
     taken on a tie or at the threshold; it is allowed only where rounding can
     decide it, and then the final values must agree within 10 * tol.
+
+    Quadrature values are compared relative to the values themselves, or, when
+    `value_scale` is given (the integral of |f| for integrands whose terms
+    cancel in the integral), within 64 eps kappa value_scale, where kappa, the
+    largest ratio of a bond's scale to its smallest accepted pivot error in the
+    oracle's log, bounds the condition number of the crosses: the two sides
+    compute the same interpolant from the same sets by different, stable
+    factorisations, so they may differ by rounding amplified by kappa.
     """
     info = job.values()[1][k]
     glog = job.pivot_log(k)
@@ -68,7 +76,16 @@ def compare(job, k, p, ref, exact_log=True):
         assert info["reason"] == ref.stop_reason
         if not noise_positions:
             assert info["evals"] == ref.evals
-        np.testing.assert_allclose(ghist, ref.history, rtol=1e-12, atol=0)
+        if value_scale is None:
+            np.testing.assert_allclose(ghist, ref.history, rtol=1e-12, atol=0)
+        else:
+            kappa = 1.0
+            for b in range(len(ref.scale)):
+                acc = [abs(sw[b].err) for sw in olog if sw[b].accepted]
+                if acc and min(acc) > 0:
+                    kappa = max(kappa, ref.scale[b] / min(acc))
+            np.testing.assert_allclose(ghist, ref.history, rtol=0,
+                                       atol=max(1e-12, 64 * 2.0 ** -52 * kappa) * value_scale)
         return None
     kind, s, b, g, o = divergence
     print(f"first divergence ({kind}) at sweep {s} bond {b}: gpu {g} oracle {o}")
@@ -79,7 +96,7 @@ def compare(job, k, p, ref, exact_log=True):
         thr = p.tol * ref.scale[b]     # the oracle's final scale bounds the one at the time
         e = abs(g["err"]) if g["accepted"] else abs(o.err)
         assert e <= thr * (1 + 1e-6), (divergence, thr)
-    assert abs(info["value"] - ref.history[-1]) <= 10 * p.tol * abs(ref.history[-1])
+    assert abs(info["value"] - ref.history[-1]) <= 10 * p.tol * (value_scale or abs(ref.history[-1]))
     return divergence
 
 
@@ -187,4 +204,83 @@ def test_workload_d5_d10_c4_full_size():
             assert abs(infos[k]["value"] / c4 - 1) < 1e-10
         if p.family == "ising_d" and p.d == 8:
             assert abs(infos[k]["value"] / 1.8959911856917860437277009899220e-05 - 1) < 1e-9
+    job.free()
+
+
+def l1_cos_product(b):
+    """Integral over [0,1]^d of |prod_j cos(b_j x_j)| (each factor by adaptive quadrature)."""
+    from scipy.integrate import quad
+    out = 1.0
+    for bj in b:
+        zeros = [(k + 0.5) * math.pi / bj for k in range(8) if (k + 0.5) * math.pi / bj < 1]
+        out *= quad(lambda x: abs(math.cos(bj * x)), 0, 1, points=zeros or None, epsabs=0, epsrel=1e-12)[0]
+    return out
+
+
+def test_workload_mixed_batch_64():
+    """64 mixed integrals in one job: C_n, D_n (n in 4..16) and rank-2 synthetic (d in 8..32).
+
+    64 nodes, rank <= 48, tol 1e-10.  Every synthetic integral and every Ising
+    integral up to d = 8 is compared with the oracle's own run (same decisions,
+    or final values within 10 tol).  C_4, D_8 and D_16 are checked against the
+    closed form / printed values.  The synthetic values are checked against the
+    exact integral, within 10 tol of the integral of |f|, wherever the oracle's
+    run resolves them that well: with the weights folded in, the entries of B
+    span tens of orders of magnitude at d ~ 30, and the sampled search can miss
+    the product term that carries the integral (it then misses it on both
+    sides, in the same way).  One of each family re-run alone must be bitwise
+    the same as in the mix.
+    """
+    from oracle.integrands import exact_synthetic
+    from paper_1903_11554_amd.workloads import config_batch
+
+    ctx = gpu_context()
+    probs = config_batch()
+    print(f"mixed batch of {len(probs)} integrals", flush=True)
+    job = ctx.job(probs)
+    infos = job.run()
+    with mp.workdps(30):
+        c4 = float(7 * mp.zeta(3) / 12)
+    printed = {8: 1.8959911856917860437277009899220e-05, 16: 4.2801588294649145858508255168059e-11}
+    bad, refs, l1s = [], {}, {}
+    for k, p in enumerate(probs):
+        inf = infos[k]
+        v = inf["value"]
+        line = f"batch {k} {p.family} d={p.d}: {inf}"
+        if inf["err_flags"] != 0 or inf["reason"] not in ("converged", "rank_cap"):
+            bad.append(line)
+        if p.family == "sum2_exp_cos":
+            a, b = np.asarray(p.params["a"]), np.asarray(p.params["b"])
+            l1 = np.prod((1 - np.exp(-a)) / a) + l1_cos_product(b)
+            exact = exact_synthetic(p.family, p.params, p.d)
+            err = abs(v - exact)
+            ref = refs[k] = run_oracle(p)
+            l1s[k] = l1
+            oerr = abs(ref.history[-1] - exact)
+            line += f" | err {err:.3e} oracle err {oerr:.3e} L1 {l1:.3e}"
+            if oerr <= 10 * p.tol * l1 and err > 10 * p.tol * l1:
+                bad.append(line)
+            if abs(v - ref.history[-1]) > 10 * p.tol * l1:
+                bad.append(line + " (differs from the oracle)")
+        elif p.family == "ising_c" and p.d == 4:
+            if abs(v / c4 - 1) >= 1e-10:
+                bad.append(line)
+        elif p.family == "ising_d" and p.d in printed:
+            line += f" | rel err {abs(v / printed[p.d] - 1):.3e}"
+            if abs(v / printed[p.d] - 1) >= 10 * p.tol:
+                bad.append(line)
+        print(line, flush=True)
+    assert not bad, "\n".join(bad)
+    sample = [k for k, p in enumerate(probs) if p.family == "sum2_exp_cos" or p.d <= 8]
+    for k in sample:
+        p = probs[k]
+        print(f"oracle check {k} {p.family} d={p.d}", flush=True)
+        compare(job, k, p, refs.get(k) or run_oracle(p), exact_log=False, value_scale=l1s.get(k))
+    for fam in ("ising_c", "ising_d", "sum2_exp_cos"):
+        k = next(k for k, p in enumerate(probs) if p.family == fam)
+        alone = ctx.job([probs[k]])
+        ainfo = alone.run()[0]
+        assert ainfo["value"] == infos[k]["value"] and ainfo["evals"] == infos[k]["evals"], (k, ainfo, infos[k])
+        assert alone.pivot_log(0) == job.pivot_log(k)
+        alone.free()
     job.free()
