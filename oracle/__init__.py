@@ -3,8 +3,9 @@
 This package is the slow, plain, obviously-correct reference that the GPU
 library is checked against.  It is written from the paper (Dolgov &
 Savostyanov, "Parallel cross interpolation for high-precision calculation of
-high-dimensional integrals", arXiv:1903.11554) in float64 numpy, with mpmath
-used only where a pin needs more digits.
+high-dimensional integrals", arXiv:1903.11554) in float64 numpy, with a
+double-double counterpart for the high-precision runs, and mpmath used only
+where a pin needs more digits.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import anything from here.  The product library
@@ -21,6 +22,10 @@ quadrature   Brute-force tensor-product quadrature (eq. quad_product).
 ttcross      Alg. 2 (matrix cross step: random + rook pivoting) run on every
              superblock at once with the previous sweep's index sets (Alg. 6),
              and the TT quadrature as a product of 2d-1 matrices (Sec. 4.1).
+ddarith      Double-double arithmetic on numpy arrays from the error-free
+             transformations (Knuth two-sum, Dekker/Veltkamp two-product).
+ttcross_dd   The same TT cross with every value in double-double (the
+             quadruple/multiple-precision runs of Sec. 5.2), paper form only.
 
 Parity status of every function is listed in the module headers.  Functions
 pinned by closed forms, the paper's printed values or exact-recovery theorems

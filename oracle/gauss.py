@@ -32,7 +32,8 @@ def _legendre_pair(n, x, mp):
 
 
 @functools.lru_cache(maxsize=64)
-def _gl_mp_rounded(n):
+def _gl_mp(n):
+    """Nodes and weights on [0,1] as 40-digit mpmath numbers, increasing nodes."""
     import mpmath as mp
     with mp.workdps(40):
         t, w = [], []
@@ -47,10 +48,16 @@ def _gl_mp_rounded(n):
                     break
             p, q = _legendre_pair(n, x, mp)
             dp = n * (x * p - q) / (x * x - 1)
-            t.append(float((x + 1) / 2))
-            w.append(float(1 / ((1 - x * x) * dp * dp)))
-    order = np.argsort(t)
-    return np.array(t)[order], np.array(w)[order]
+            t.append((x + 1) / 2)
+            w.append(1 / ((1 - x * x) * dp * dp))
+    order = sorted(range(n), key=lambda i: t[i])
+    return [t[i] for i in order], [w[i] for i in order]
+
+
+@functools.lru_cache(maxsize=64)
+def _gl_mp_rounded(n):
+    t, w = _gl_mp(n)
+    return np.array([float(v) for v in t]), np.array([float(v) for v in w])
 
 
 def gauss_legendre_01(n):
@@ -59,6 +66,15 @@ def gauss_legendre_01(n):
         raise ValueError("n must be >= 1")
     t, w = _gl_mp_rounded(n)
     return t.copy(), w.copy()
+
+
+def gauss_legendre_01_dd(n):
+    """Return (t, w) as double-double arrays (the 40-digit values rounded to hi + lo)."""
+    from .ddarith import DD
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    t, w = _gl_mp(n)
+    return DD.from_mp(t), DD.from_mp(w)
 
 
 def gauss_legendre_01_mp(n, dps=50):

@@ -124,6 +124,56 @@ def f_values(family, x, params=None):
     raise ValueError(family)
 
 
+def _ising_paper_dd(family, x):
+    """The paper form in double-double; x is a DD array (npts, d-1).  Same formula as above."""
+    from .ddarith import DD, dd_prod
+    npts, m = x.shape
+    d = m + 1
+
+    def prod_range(a, b):
+        return dd_prod(x[:, a - 2:b - 1], axis=1)
+
+    f = DD(np.full(npts, 2.0))
+    if family in ("ising_c", "ising_d"):
+        s_left = DD(np.ones(npts))
+        s_right = DD(np.ones(npts))
+        for k in range(2, d + 1):
+            s_left = s_left + prod_range(2, k)
+            s_right = s_right + prod_range(k, d)
+        f = f / (s_left * s_right)
+    if family in ("ising_d", "ising_e"):
+        a_d = DD(np.ones(npts))
+        for i in range(1, d):
+            for j in range(i + 1, d + 1):
+                p = prod_range(i + 1, j)
+                a_d = a_d * ((1.0 - p) / (1.0 + p)).square()
+        f = f * a_d
+    return f
+
+
+def f_values_dd(family, x):
+    """Unweighted integrand in double-double at points x (a DD array (npts, m)); paper form only."""
+    if family not in PAPER_FORM:
+        raise ValueError(f"no double-double path for {family}")
+    if len(x.shape) != 2:
+        raise ValueError("x must be 2-D (npts, m)")
+    return _ising_paper_dd(family, x)
+
+
+def weighted_values_dd(family, idx, t, w):
+    """B in double-double at integer multi-indices idx (npts, m); t, w are DD node/weight tables."""
+    from .ddarith import DD, dd_prod
+    idx = np.asarray(idx, dtype=np.int64)
+    if idx.ndim != 2:
+        raise ValueError("idx must be 2-D (npts, m)")
+    npts, m = idx.shape
+    if m == 0:
+        return f_values_dd(family, DD(np.zeros((npts, 0))))
+    x = DD(t.hi[idx], t.lo[idx])
+    wt = dd_prod(DD(w.hi[idx], w.lo[idx]), axis=1)
+    return wt * f_values_dd(family, x)
+
+
 def weighted_values(family, idx, t, w, params=None):
     """B at integer multi-indices idx (npts, m): prod_k w[idx_k] * f(t[idx])."""
     idx = np.asarray(idx, dtype=np.int64)

@@ -56,12 +56,13 @@ N_START = 1024
 
 
 class PivotRecord:
-    __slots__ = ("bond", "row", "col", "err", "value", "accepted", "iters", "searched", "_new")
+    __slots__ = ("bond", "row", "col", "err", "err_lo", "value", "accepted", "iters", "searched", "_new")
 
     def __init__(self, bond, row=-1, col=-1, err=0.0, value=0.0, accepted=False, iters=0,
                  searched=False):
         self.bond, self.row, self.col = bond, row, col
         self.err, self.value = err, value
+        self.err_lo = 0.0            # low part of err in the double-double oracle
         self.accepted, self.iters, self.searched = accepted, iters, searched
         self._new = None
 
@@ -81,7 +82,7 @@ class TTCross:
         self.params = params
         self.t_rook, self.max_samples, self.n_start = t_rook, max_samples, n_start
         self.m = n_modes(family, d)
-        self.t, self.w = gauss_legendre_01(n)
+        self.t, self.w = self._nodes(n)
         nb = max(self.m - 1, 0)
         self.left = [[] for _ in range(nb)]    # left[b]:  I_<=b, tuples (i_0..i_b)
         self.right = [[] for _ in range(nb)]   # right[b]: I_>b,  tuples (i_b+1..i_m-1)
@@ -96,6 +97,9 @@ class TTCross:
         self._start()
 
     # ----------------------------------------------------------------- tensor
+    def _nodes(self, n):
+        return gauss_legendre_01(n)
+
     def B(self, idx):
         idx = np.asarray(idx, dtype=np.int64)
         idx = idx.reshape(-1, self.m) if self.m > 0 else idx.reshape(idx.shape[0], 0)

@@ -29,7 +29,7 @@ def load_copy(tmp_path, name, file=None, old=None, new=None):
     sys.path.insert(0, str(tmp_path))
     try:
         return {m: importlib.import_module(f"{name}.{m}")
-                for m in ("rng", "gauss", "integrands", "quadrature", "ttcross")}
+                for m in ("rng", "gauss", "integrands", "quadrature", "ttcross", "ddarith", "ttcross_dd")}
     finally:
         sys.path.remove(str(tmp_path))
 
@@ -107,6 +107,48 @@ def pin_rook(o):
     return ok
 
 
+def pin_dd_ops(o):
+    DD = o["ddarith"].DD
+    r = np.random.default_rng(2)
+    a = DD(r.uniform(-2, 2, 200), r.uniform(-1, 1, 200) * 2.0 ** -56)
+    b = DD(r.uniform(0.5, 2, 200), r.uniform(-1, 1, 200) * 2.0 ** -56)
+    with mp.workdps(60):
+        am = [mp.mpf(float(h)) + mp.mpf(float(l)) for h, l in zip(a.hi, a.lo)]
+        bm = [mp.mpf(float(h)) + mp.mpf(float(l)) for h, l in zip(b.hi, b.lo)]
+        for c, f in ((a + b, lambda x, y: x + y), (a * b, lambda x, y: x * y), (a / b, lambda x, y: x / y)):
+            for i in range(200):
+                ref = f(am[i], bm[i])
+                if abs(mp.mpf(float(c.hi[i])) + mp.mpf(float(c.lo[i])) - ref) > 2.0 ** -102 * abs(ref):
+                    return False
+    return True
+
+
+def pin_dd_integrand(o):
+    from test_oracle_dd import mp_paper_form
+    DD = o["ddarith"].DD
+    r = np.random.default_rng(4)
+    x = DD(r.uniform(0, 1, (10, 5)))
+    v = o["integrands"].f_values_dd("ising_d", x)
+    with mp.workdps(60):
+        return all(abs((mp.mpf(float(v.hi[p])) + mp.mpf(float(v.lo[p])))
+                       / mp_paper_form("ising_d", [mp.mpf(float(q)) for q in x.hi[p]]) - 1) < 1e-29
+                   for p in range(10))
+
+
+def pin_dd_quad(o):
+    hi, lo = o["quadrature"].tensor_quadrature_dd("ising_d", 2, 32)
+    with mp.workdps(50):
+        L3 = (mp.zeta(2, mp.mpf(1) / 3) - mp.zeta(2, mp.mpf(2) / 3)) / 9
+        return abs((mp.mpf(hi) + mp.mpf(lo)) / (8 + 4 * mp.pi ** 2 / 3 - 27 * L3) - 1) < 1e-29
+
+
+def pin_dd_tt(o):
+    tt = o["ttcross_dd"].solve_dd("ising_d", 4, 24, 24, 1e-28, seed=4)
+    with mp.workdps(50):
+        d4 = 4 * mp.pi ** 2 / 9 - mp.mpf(1) / 6 - 7 * mp.zeta(3) / 2
+        return abs((mp.mpf(tt.history[-1]) + mp.mpf(tt.history_lo[-1])) / d4 - 1) < 1e-25
+
+
 MUTATIONS = [
     # (file, original text, planted mistake, pin that must catch it)
     ("integrands.py", "a_d = a_d * ((1.0 - p) / (1.0 + p)) ** 2", "a_d = a_d * ((1.0 - p) / (1.0 + p))",
@@ -121,10 +163,22 @@ MUTATIONS = [
      pin_rank2),                                                             # transposed operand
     ("ttcross.py", "row = argmax_abs(a_col - approx(all_rows, [col] * nrows))",
      "row = argmax_abs(a_col)", pin_rook),                                   # dropped B~ term
-    ("gauss.py", "w.append(float(1 / ((1 - x * x) * dp * dp)))",
-     "w.append(float(2 / ((1 - x * x) * dp * dp)))", pin_gl),                # interval map
+    ("gauss.py", "w.append(1 / ((1 - x * x) * dp * dp))",
+     "w.append(2 / ((1 - x * x) * dp * dp))", pin_gl),                       # interval map
     ("rng.py", "GAMMA = 0x9E3779B97F4A7C15", "GAMMA = 0x9E3779B97F4A7C13", pin_rng),
     ("rng.py", "z = ((z ^ (z >> 27)) * M2) & MASK", "z = ((z ^ (z >> 28)) * M2) & MASK", pin_rng),
+    # double-double oracle
+    ("ddarith.py", "e = e + (self.hi * y.lo + self.lo * y.hi)", "e = e + self.hi * y.lo", pin_dd_ops),
+    ("ddarith.py", "SPLITTER = 134217729.0", "SPLITTER = 67108865.0", pin_dd_ops),
+    ("ddarith.py", "        e = e + t\n", "        e = e\n", pin_dd_ops),    # dropped low-part sum
+    ("ddarith.py", "X[k, :] = s / A[k, k]", "X[k, :] = s / A[k, k].hi", pin_dd_tt),
+    ("integrands.py", "a_d = a_d * ((1.0 - p) / (1.0 + p)).square()", "a_d = a_d * ((1.0 - p) / (1.0 + p))",
+     pin_dd_integrand),
+    ("ttcross_dd.py", "v = dd_solve(M.T, v.T).T", "v = dd_solve(M, v.T).T", pin_dd_tt),
+    ("ttcross_dd.py", "return dd_sum(Fb[np.asarray(rows), :] * X.T, axis=1)",
+     "return DD(dd_sum(Fb[np.asarray(rows), :] * X.T, axis=1).hi)", pin_dd_tt),
+    ("gauss.py", "return DD.from_mp(t), DD.from_mp(w)", "return DD.from_mp(t), DD([float(v) for v in w])",
+     pin_dd_quad),
 ]
 
 
