@@ -58,7 +58,16 @@ typedef enum {
   TT_PROD_EXP = 21, TT_SUM2_EXP_COS = 22
 } tt_integrand;
 
-typedef enum { TT_FP64 = 0 } tt_precision;
+/* Number type of a job's whole computation.
+ * TT_FP64: IEEE double throughout.
+ * TT_DD: double-double (a value is an unevaluated sum hi + lo of two doubles,
+ *   about 32 significant digits), standing in for the quadruple and multiple
+ *   precision runs of Sec. 5.2: nodes, weights, integrand values, interpolation
+ *   cores, the pivot errors and the quadrature are all double-double; the pivot
+ *   choice and the acceptance test compare the leading double.  Paper-form
+ *   integrands (TT_ISING_C, TT_ISING_D, TT_ISING_E) only.
+ * All integrals of one job must use the same precision. */
+typedef enum { TT_FP64 = 0, TT_DD = 1 } tt_precision;
 
 /* Stop reasons reported in tt_info.reason. */
 enum { TT_RUNNING = 0, TT_STOP_CONVERGED = 1, TT_STOP_RANK_CAP = 2, TT_STOP_MAX_SWEEPS = 3 };
@@ -88,8 +97,9 @@ typedef struct {
   int32_t err_flags;   /* bits: non-finite value (1), singular cross (2), zero start (4),
                           internal rank bucket overflow (8)                               */
   int64_t evals;       /* integrand evaluations so far (start, samples, fibers, cores)    */
-  double  value;       /* integral estimate                                               */
+  double  value;       /* integral estimate (TT_DD: its leading double)                   */
   double  rel_change;  /* |I_s - I_{s-1}| / |I_s| of the last sweep                       */
+  double  value_lo;    /* TT_DD: the low double of the estimate (value + value_lo); else 0 */
 } tt_info;
 
 /* One accepted-or-rejected pivot search of one superblock in one sweep.
@@ -99,8 +109,8 @@ typedef struct {
   int32_t row, col;    /* pivot position in the superblock (-1: not searched)            */
   int32_t accepted;    /* 1 if appended to the index sets                                 */
   int32_t iters;       /* rook (column,row) pairs used, 1..5; 0 if not searched            */
-  double  err;         /* B - B~ at the pivot (signed)                                    */
-  double  value;       /* B at the pivot                                                  */
+  double  err;         /* B - B~ at the pivot (signed; TT_DD: leading double)             */
+  double  value;       /* B at the pivot (TT_DD: leading double)                          */
 } tt_pivot;
 
 typedef struct tt_ctx tt_ctx;
@@ -120,7 +130,8 @@ size_t tt_job_footprint(const tt_problem *problem);
  * start of each integral (largest |B| among 1024 SplitMix64 grid samples),
  * evaluates the first cores and the first quadrature value.  Synchronises.
  * Errors: TT_EINVAL (bad problem: d < 1, modes > TT_MAX_MODES, n or rank out of
- * range, tol <= 0, unknown integrand or precision, missing params),
+ * range, tol <= 0, unknown integrand or precision, TT_DD for an integrand
+ * without a double-double path, precisions mixed in one job, missing params),
  * TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC (all start samples zero or non-finite). */
 tt_status tt_cross_init(tt_ctx *ctx, const tt_problem *problems, int32_t count, tt_job **out);
 
@@ -137,27 +148,33 @@ tt_status tt_cross_integrate(tt_job *job, double *values, tt_info *info);
 
 /* Diagnostics for tests: the pivot log of integral k (sweeps x (m-1) records,
  * host buffer of `capacity` records, *written = records copied), the
- * integral after the start and after each sweep (sweeps+1 doubles), and the
+ * integral after the start and after each sweep (sweeps+1 values: leading
+ * doubles in `values`, low doubles in `values_lo` if not NULL, 0 for TT_FP64), and the
  * index sets: for bond b the left set I_<=b as rows of (b+1) node indices and
  * the right set I_>b as rows of (m-b-1) node indices, packed bond by bond
  * (left then right), each row in insertion order; ranks[m-1] receives r_b. */
 tt_status tt_job_pivot_log(tt_job *job, int32_t k, tt_pivot *log, int64_t capacity, int64_t *written);
-tt_status tt_job_history(tt_job *job, int32_t k, double *values, int64_t capacity, int64_t *written);
+tt_status tt_job_history(tt_job *job, int32_t k, double *values, double *values_lo, int64_t capacity,
+                         int64_t *written);
 tt_status tt_job_index_sets(tt_job *job, int32_t k, int32_t *ranks, int32_t *nodes,
                             int64_t capacity, int64_t *written);
-/* Gauss--Legendre nodes and weights of integral k as generated on the device (n each). */
-tt_status tt_job_nodes(tt_job *job, int32_t k, double *t, double *w);
+/* Gauss--Legendre nodes and weights of integral k as generated on the device, n
+ * each: t and w rounded to double; t_lo and w_lo (may be NULL) receive the low
+ * doubles of the double-double tables (t + t_lo, w + w_lo), for any precision. */
+tt_status tt_job_nodes(tt_job *job, int32_t k, double *t, double *w, double *t_lo, double *w_lo);
 void tt_cross_free(tt_job *job);
 
 /* Standalone batched integrand evaluation (the fiber-evaluation kernel of the
  * sweep, exposed for parity checks and roofline measurement).
  * tt_eval_points: B at npts multi-indices; d_idx is a device int32 array of
  * npts*m node indices (row-major, one row per point), d_out a device double
- * array of npts values.  Asynchronous on the context stream.
+ * array of npts values (TT_DD: 2*npts doubles, the pairs (hi, lo) of each
+ * value in turn).  Asynchronous on the context stream.
  * tt_eval_fibers: B over the fiber set I_left x [n] x I_right at mode position
  * `pos` (0 <= pos < m): d_left is device int32 [r_left * pos] node indices,
  * d_right device int32 [r_right * (m-pos-1)]; d_out receives r_left*n*r_right
- * doubles in the order (alpha, i, beta), beta fastest.  Asynchronous.
+ * values in the order (alpha, i, beta), beta fastest (TT_DD: (hi, lo) pairs,
+ * twice as many doubles).  Asynchronous.
  * Errors: TT_EINVAL (bad problem or sizes), TT_EDEVICE. */
 tt_status tt_eval_points(tt_ctx *ctx, const tt_problem *problem, const int32_t *d_idx,
                          int64_t npts, double *d_out);

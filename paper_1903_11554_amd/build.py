@@ -2,7 +2,8 @@
 
 The library is the host translation unit ``csrc/ttcross.hip`` plus one kernel
 translation unit per integrand class (``csrc/tt_inst.hip`` compiled with
--DTT_FAM=0..3), compiled in parallel for gfx950 only, with floating-point
+-DTT_FAM=0..3, and once more with -DTT_INST_DD=1 for the double-double kernels of
+the paper-form class), compiled in parallel for gfx950 only, with floating-point
 contraction off (every FMA is written in the source) and packed-FP32
 instructions disabled, then linked into ``libttcross.so``.
 """
@@ -25,7 +26,8 @@ FLAGS = [
 ]
 
 UNITS = [("ttcross.hip", [], "ttcross.o")] + [
-    ("tt_inst.hip", [f"-DTT_FAM={f}"], f"tt_inst_{f}.o") for f in range(4)]
+    ("tt_inst.hip", [f"-DTT_FAM={f}"], f"tt_inst_{f}.o") for f in range(4)] + [
+    ("tt_inst.hip", ["-DTT_FAM=0", "-DTT_INST_DD=1"], "tt_inst_dd.o")]
 
 
 def _run(cmd, verbose):

@@ -69,6 +69,43 @@ __device__ __forceinline__ dd dd_div(dd x, dd y) {
 }
 __device__ __forceinline__ dd dd_from(double a) { return {a, 0.0}; }
 
+// ------------------------------------------------------- working number type
+// The TT kernels are written once over the number type T of a job: double, or
+// dd for the double-double path.  These overloads are the only arithmetic they
+// apply to T values; for double each is the plain operation (n_mad is one FMA).
+template <class T> struct is_dd_t { static constexpr bool value = false; };
+template <> struct is_dd_t<dd> { static constexpr bool value = true; };
+
+template <class T> __device__ __forceinline__ T num(double a);
+template <> __device__ __forceinline__ double num<double>(double a) { return a; }
+template <> __device__ __forceinline__ dd num<dd>(double a) { return {a, 0.0}; }
+
+__device__ __forceinline__ double n_hi(double a) { return a; }
+__device__ __forceinline__ double n_hi(dd a) { return a.hi; }
+__device__ __forceinline__ double n_lo(double) { return 0.0; }
+__device__ __forceinline__ double n_lo(dd a) { return a.lo; }
+__device__ __forceinline__ double n_add(double a, double b) { return a + b; }
+__device__ __forceinline__ dd n_add(dd a, dd b) { return dd_add(a, b); }
+__device__ __forceinline__ double n_sub(double a, double b) { return a - b; }
+__device__ __forceinline__ dd n_sub(dd a, dd b) { return dd_sub(a, b); }
+__device__ __forceinline__ double n_mul(double a, double b) { return a * b; }
+__device__ __forceinline__ dd n_mul(dd a, dd b) { return dd_mul(a, b); }
+__device__ __forceinline__ double n_div(double a, double b) { return a / b; }
+__device__ __forceinline__ dd n_div(dd a, dd b) { return dd_div(a, b); }
+// a b + c and c - a b
+__device__ __forceinline__ double n_mad(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ dd n_mad(dd a, dd b, dd c) { return dd_add(dd_mul(a, b), c); }
+__device__ __forceinline__ double n_nmad(double a, double b, double c) { return fma(-a, b, c); }
+__device__ __forceinline__ dd n_nmad(dd a, dd b, dd c) { return dd_sub(c, dd_mul(a, b)); }
+__device__ __forceinline__ double n_shfl(double a, int lane) { return __shfl(a, lane, kWave); }
+__device__ __forceinline__ dd n_shfl(dd a, int lane) {
+  return {__shfl(a.hi, lane, kWave), __shfl(a.lo, lane, kWave)};
+}
+__device__ __forceinline__ double n_shfl_xor(double a, int off) { return __shfl_xor(a, off, kWave); }
+__device__ __forceinline__ dd n_shfl_xor(dd a, int off) {
+  return {__shfl_xor(a.hi, off, kWave), __shfl_xor(a.lo, off, kWave)};
+}
+
 // ---------------------------------------------------------------- SplitMix64
 __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -103,46 +140,47 @@ __device__ __forceinline__ uint64_t start_counter(int q, int k) {
 //   suffix sum s = sum_a y_a..y_{m-1} (all runs after the last step);
 //   B_d = 1 / ((1 + q)(1 + s)).
 // One uniform guard per b: modes beyond m are skipped in one branch each.
-template <int MAXM>
-__device__ __forceinline__ double ising_paper(int family, int m, const double (&y)[MAXM]) {
-  double z[MAXM];
+template <class T, int MAXM>
+__device__ __forceinline__ T ising_paper(int family, int m, const T (&y)[MAXM]) {
+  const T zero = num<T>(0.0), one = num<T>(1.0);
+  T z[MAXM];
 #pragma unroll
-  for (int k = 0; k < MAXM; ++k) z[k] = (k < m) ? y[k] : 0.0;
+  for (int k = 0; k < MAXM; ++k) z[k] = (k < m) ? y[k] : zero;
   const bool need_a = family != TT_ISING_C;
-  double pn = 1.0, pd = 1.0, q = 0.0;
+  T pn = one, pd = one, q = zero;
 #pragma unroll
   for (int b = 0; b < MAXM; ++b) {
     if (b < m) {
-      const double yb = z[b];
+      const T yb = z[b];
 #pragma unroll
-      for (int a = 0; a < b; ++a) z[a] *= yb;      // z[a] = y_a..y_b
-      q += z[0];
+      for (int a = 0; a < b; ++a) z[a] = n_mul(z[a], yb);   // z[a] = y_a..y_b
+      q = n_add(q, z[0]);
       if (need_a) {
 #pragma unroll
         for (int a = 0; a <= b; ++a) {
-          pn = fma(-pn, z[a], pn);                   // pn * (1 - y_a..y_b)
-          pd = fma(pd, z[a], pd);                    // pd * (1 + y_a..y_b)
+          pn = n_nmad(pn, z[a], pn);                          // pn * (1 - y_a..y_b)
+          pd = n_mad(pd, z[a], pd);                           // pd * (1 + y_a..y_b)
         }
       }
     }
   }
-  double num = 2.0, den = 1.0;
+  T nm = num<T>(2.0), den = one;
   if (family != TT_ISING_E) {
-    double s = 0.0;
+    T s = zero;
 #pragma unroll
-    for (int a = 0; a < MAXM; ++a) s += z[a];        // zero beyond m
-    den = (1.0 + q) * (1.0 + s);
+    for (int a = 0; a < MAXM; ++a) s = n_add(s, z[a]);      // zero beyond m
+    den = n_mul(n_add(one, q), n_add(one, s));
   }
   if (need_a) {
     if (m <= 31) {               // pd^2 <= 2^(m(m+1)) stays finite
-      num = num * pn * pn;
-      den = den * (pd * pd);
+      nm = n_mul(n_mul(nm, pn), pn);
+      den = n_mul(den, n_mul(pd, pd));
     } else {
-      const double r = pn / pd;
-      num = num * r * r;
+      const T r = n_div(pn, pd);
+      nm = n_mul(n_mul(nm, r), r);
     }
   }
-  return num / den;
+  return n_div(nm, den);
 }
 
 // u-form, d = m variables x_j with u_j = x_j/(1-x_j):
@@ -221,7 +259,7 @@ __device__ __forceinline__ double integrand(const FamilyArgs& fa, const double (
     case TT_ISING_C:
     case TT_ISING_D:
     case TT_ISING_E:
-      return ising_paper<MAXM>(fa.family, fa.m, y);
+      return ising_paper<double, MAXM>(fa.family, fa.m, y);
     case TT_ISING_C_U:
     case TT_ISING_D_U:
       return ising_u<MAXM>(fa.family, fa.m, y, fa.four_over_mfact);

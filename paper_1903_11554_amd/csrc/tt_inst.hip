@@ -1,30 +1,43 @@
 // Kernel instantiations for one integrand class (TT_FAM = FAM_PAPER, FAM_UFORM,
-// FAM_SYNTH or FAM_ANY), compiled once per class.
+// FAM_SYNTH or FAM_ANY) and one number type (TT_INST_DD = 0: double, 1:
+// double-double, paper form only), compiled once per combination.
 #include "tt_kernels.hpp"
 #include "tt_launch.hpp"
 
 #ifndef TT_FAM
 #error "compile with -DTT_FAM=<integrand class>"
 #endif
+#ifndef TT_INST_DD
+#define TT_INST_DD 0
+#endif
+#if TT_INST_DD && TT_FAM != 0
+#error "the double-double kernels exist for the paper-form class only"
+#endif
 
 namespace ttx {
 namespace {
 
+#if TT_INST_DD
+using Real = dd;
+#else
+using Real = double;
+#endif
+
 template <int MAXM, int RMAX>
 void sweep(const LaunchArgs& a) {
-  hipLaunchKernelGGL((k_sweep<TT_FAM, MAXM, RMAX>), dim3(a.nbond), dim3(kSweepBlock), 0, a.stream, a.desc,
-                     a.bond_tasks);
+  hipLaunchKernelGGL((k_sweep<Real, TT_FAM, MAXM, RMAX>), dim3(a.nbond), dim3(kSweepBlock), 0, a.stream,
+                     a.desc, a.bond_tasks);
 }
 
 template <int MAXM>
 void by_rank(const LaunchArgs& a, int what, int rb) {
   if (what == LAUNCH_START) {
-    hipLaunchKernelGGL((k_start<TT_FAM, MAXM>), dim3(a.nprob), dim3(kBlock), 0, a.stream, a.desc);
+    hipLaunchKernelGGL((k_start<Real, TT_FAM, MAXM>), dim3(a.nprob), dim3(kBlock), 0, a.stream, a.desc);
     return;
   }
   if (what == LAUNCH_INIT_UPDATE) {
-    hipLaunchKernelGGL((k_update<TT_FAM, MAXM, 8>), dim3(a.ncore), dim3(kSweepBlock), 0, a.stream, a.desc,
-                       a.core_tasks, 1);
+    hipLaunchKernelGGL((k_update<Real, TT_FAM, MAXM, 8>), dim3(a.ncore), dim3(kSweepBlock), 0, a.stream,
+                       a.desc, a.core_tasks, 1);
     return;
   }
   switch (rb) {
@@ -45,7 +58,9 @@ void dispatch(const LaunchArgs& a, int what, int rb) {
 
 }  // namespace
 
-#if TT_FAM == 0
+#if TT_INST_DD
+void launch_paper_dd(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }
+#elif TT_FAM == 0
 void launch_paper(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }
 #elif TT_FAM == 1
 void launch_uform(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }

@@ -19,7 +19,9 @@
 //   integral  per integral, run by the last core update: commits the ranks,
 //             multiplies the 2m-1 matrices of the TT quadrature (Sec. 4.1) and
 //             applies the stopping rule.
-// Kernels are specialised by integrand class, so each carries one integrand.
+// Kernels are specialised by integrand class, so each carries one integrand,
+// and templated on the number type T of the job (double, or dd for the
+// double-double path): the arrays marked "T" below hold T values.
 #pragma once
 
 #include "tt_device.hpp"
@@ -36,7 +38,7 @@ struct ProbState {
   int32_t sweeps, done, reason, err_flags;
   int32_t nacc, max_rank, pad0, pad1;
   unsigned long long evals;
-  double value, rel, pad2;
+  double value, rel, value_lo;   // value_lo: low part of the integral (double-double jobs)
 };
 
 struct ProbDesc {
@@ -44,21 +46,22 @@ struct ProbDesc {
   int32_t max_sweeps, nbonds, pad0, pad1;
   double tol, four_over_mfact;
   uint64_t seed;
-  const double *t, *w, *pa, *pb;
+  const double *t, *w;                   // T: nodes and weights
+  const double *pa, *pb;                 // synthetic parameters
   int32_t *Lpar, *Lnode, *Rpar, *Rnode;  // [nbonds][R]
-  double *Lx, *Rx;                       // [nbonds][R][m]
-  double *Lw, *Rw;                       // [nbonds][R]
-  double *F;                             // cores, core c at F + Foff[c]
+  double *Lx, *Rx;                       // T [nbonds][R][m]
+  double *Lw, *Rw;                       // T [nbonds][R]
+  double *F;                             // T cores, core c at F + Foff[c] (in T elements)
   int64_t *Foff;
-  double *C;                             // interpolation cores (transposed), bond b at C + Coff[b]
+  double *C;                             // T interpolation cores (transposed), bond b at C + Coff[b]
   int64_t *Coff;
-  double *LU;                            // [nbonds][R*R] LU of M_b in insertion order (no pivoting)
-  double *S;                             // [m][R*R] core sums over the mode index
+  double *LU;                            // T [nbonds][R*R] LU of M_b in insertion order (no pivoting)
+  double *S;                             // T [m][R*R] core sums over the mode index
   int32_t *rank;                         // [nbonds]
   PivRec *piv;                           // [nbonds] current sweep's pivots
   double *scale;                         // [nbonds] largest |B| seen per bond
   PivRec *log;                           // [max_sweeps][nbonds]
-  double *hist;                          // [max_sweeps+1]
+  double *hist;                          // T [max_sweeps+1]
   int32_t *start;                        // [m] start multi-index
   int32_t *sync;                         // [m+1] per-sweep dataflow counters (cores ready, cores done)
   int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
@@ -95,13 +98,25 @@ constexpr int kRook = 5;
 // integrand classes a kernel can be specialised for
 enum { FAM_PAPER = 0, FAM_UFORM = 1, FAM_SYNTH = 2, FAM_ANY = 3 };
 
-template <int FAM, int MAXM>
-__device__ __forceinline__ double integrand_fam(const FamilyArgs& fa, const double (&y)[MAXM]) {
-  if constexpr (FAM == FAM_PAPER) return ising_paper<MAXM>(fa.family, fa.m, y);
-  else if constexpr (FAM == FAM_UFORM) return ising_u<MAXM>(fa.family, fa.m, y, fa.four_over_mfact);
-  else if constexpr (FAM == FAM_SYNTH) return synthetic<MAXM>(fa.family, fa.m, y, fa.a, fa.b);
-  else return integrand<MAXM>(fa, y);
+template <class T, int FAM, int MAXM>
+__device__ __forceinline__ T integrand_fam(const FamilyArgs& fa, const T (&y)[MAXM]) {
+  if constexpr (is_dd_t<T>::value) {
+    static_assert(FAM == FAM_PAPER, "the double-double path covers the paper-form integrands");
+    return ising_paper<dd, MAXM>(fa.family, fa.m, y);
+  } else if constexpr (FAM == FAM_PAPER) {
+    return ising_paper<double, MAXM>(fa.family, fa.m, y);
+  } else if constexpr (FAM == FAM_UFORM) {
+    return ising_u<MAXM>(fa.family, fa.m, y, fa.four_over_mfact);
+  } else if constexpr (FAM == FAM_SYNTH) {
+    return synthetic<MAXM>(fa.family, fa.m, y, fa.a, fa.b);
+  } else {
+    return integrand<MAXM>(fa, y);
+  }
 }
+
+// The arrays of a job hold T values; the descriptor carries them as double*.
+template <class T> __device__ __forceinline__ T* tp(double* p) { return reinterpret_cast<T*>(p); }
+template <class T> __device__ __forceinline__ const T* tp(const double* p) { return reinterpret_cast<const T*>(p); }
 
 __device__ __forceinline__ int rowcap(const ProbDesc& p, int c) { return c == 0 ? 1 : p.R; }
 __device__ __forceinline__ int colcap(const ProbDesc& p, int c) { return c == p.m - 1 ? 1 : p.R; }
@@ -113,7 +128,8 @@ __device__ __forceinline__ FamilyArgs family_args(const ProbDesc& p) {
 // ------------------------------------------------------------------ GL rule
 // Nodes on [0,1] = (x+1)/2 for the roots x of P_n; weights 1/((1-x^2) P_n'(x)^2).
 // Newton in double from the classical initial guess, then two Newton steps in
-// double-double; the dd results are rounded once to double.
+// double-double; the dd results are kept for the double-double path and
+// rounded once to double for the double path.
 __device__ inline void legendre_dd(int n, dd x, dd& pn, dd& pn1) {
   dd p0 = dd_from(1.0), p1 = x;
   if (n == 0) { pn = p0; pn1 = dd_from(0.0); return; }
@@ -128,7 +144,7 @@ __device__ inline void legendre_dd(int n, dd x, dd& pn, dd& pn1) {
   pn1 = p0;
 }
 
-__device__ inline void gl_node(int n, int k, double& t_out, double& w_out) {
+__device__ inline void gl_node(int n, int k, dd& t_out, dd& w_out) {
   // k-th root in decreasing order of x
   double x = cos(M_PI * ((double)k + 0.75) / ((double)n + 0.5));
   for (int it = 0; it < 100; ++it) {
@@ -155,61 +171,66 @@ __device__ inline void gl_node(int n, int k, double& t_out, double& w_out) {
   dp = dd_div(dd_mul_d(dd_sub(dd_mul(X, pn), pn1), (double)n), x2m1);
   dd one_m_x2 = dd_neg(x2m1);
   dd wk = dd_div(dd_from(1.0), dd_mul(one_m_x2, dd_mul(dp, dp)));   // = w_x / 2
-  dd tk = dd_mul_d(dd_add(X, dd_from(1.0)), 0.5);
-  t_out = tk.hi + tk.lo;
-  w_out = wk.hi + wk.lo;
+  t_out = dd_mul_d(dd_add(X, dd_from(1.0)), 0.5);
+  w_out = wk;
 }
 
-static __global__ void k_gl(int n, double* __restrict__ t, double* __restrict__ w) {
+static __global__ void k_gl(int n, double* __restrict__ t, double* __restrict__ w, dd* __restrict__ t2,
+                            dd* __restrict__ w2) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    double tk, wk;
+    dd tk, wk;
     gl_node(n, k, tk, wk);
-    t[n - 1 - k] = tk;   // increasing order
-    w[n - 1 - k] = wk;
+    t[n - 1 - k] = tk.hi + tk.lo;   // increasing order
+    w[n - 1 - k] = wk.hi + wk.lo;
+    t2[n - 1 - k] = tk;
+    w2[n - 1 - k] = wk;
   }
 }
 
 
 // ----------------------------------------------------- rank-1 start (m >= 0)
-template <int FAM, int MAXM>
+template <class T, int FAM, int MAXM>
 __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   const ProbDesc p = P[blockIdx.x];
   const int m = p.m, n = p.n, tid = threadIdx.x;
   const FamilyArgs fa = family_args(p);
+  const T* __restrict__ tt = tp<T>(p.t);
+  const T* __restrict__ ww = tp<T>(p.w);
   __shared__ double sv[kBlock / kWave + 1];
   __shared__ int si[kBlock / kWave + 1];
   __shared__ int s_i0[MAXM];
-  __shared__ double s_buf[TT_MAX_NODES];
+  __shared__ T s_buf[TT_MAX_NODES];
   ProbState* st = p.st;
 
   if (m <= 1) {   // no bond: the tensor is a vector (or a scalar for m = 0)
-    double val = 0.0;
+    T val = num<T>(0.0);
     if (m == 0) {
-      double y[MAXM];
+      T y[MAXM];
 #pragma unroll
-      for (int k = 0; k < MAXM; ++k) y[k] = 0.0;
-      val = integrand_fam<FAM, MAXM>(fa, y);
+      for (int k = 0; k < MAXM; ++k) y[k] = num<T>(0.0);
+      val = integrand_fam<T, FAM, MAXM>(fa, y);
     } else {
       for (int i = tid; i < n; i += blockDim.x) {
-        double y[MAXM];
+        T y[MAXM];
 #pragma unroll
-        for (int k = 0; k < MAXM; ++k) y[k] = 0.0;
-        y[0] = p.t[i];
-        s_buf[i] = p.w[i] * integrand_fam<FAM, MAXM>(fa, y);
+        for (int k = 0; k < MAXM; ++k) y[k] = num<T>(0.0);
+        y[0] = tt[i];
+        s_buf[i] = n_mul(ww[i], integrand_fam<T, FAM, MAXM>(fa, y));
       }
       __syncthreads();
       if (tid == 0)
-        for (int i = 0; i < n; ++i) val += s_buf[i];
+        for (int i = 0; i < n; ++i) val = n_add(val, s_buf[i]);
     }
     if (tid == 0) {
-      p.hist[0] = val;
-      st->value = val;
+      tp<T>(p.hist)[0] = val;
+      st->value = n_hi(val);
+      st->value_lo = n_lo(val);
       st->rel = 0.0;
       st->sweeps = 0;
       st->done = 1;
       st->reason = TT_STOP_CONVERGED;
       st->evals = (m == 1) ? (unsigned long long)n : 0ull;
-      st->err_flags = isfinite(val) ? 0 : 1;
+      st->err_flags = isfinite(n_hi(val)) ? 0 : 1;
       st->max_rank = 1;
     }
     return;
@@ -218,19 +239,19 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   ArgMax best{-1.0, 0x7fffffff};
   bool bad = false;
   for (int q = tid; q < kStart; q += blockDim.x) {
-    double y[MAXM];
-    double W = 1.0;
+    T y[MAXM];
+    T W = num<T>(1.0);
 #pragma unroll
     for (int k = 0; k < MAXM; ++k) {
       if (k < m) {
         int ik = (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n);
-        y[k] = p.t[ik];
-        W = W * p.w[ik];
+        y[k] = tt[ik];
+        W = n_mul(W, ww[ik]);
       } else {
-        y[k] = 0.0;
+        y[k] = num<T>(0.0);
       }
     }
-    double v = W * integrand_fam<FAM, MAXM>(fa, y);
+    const double v = n_hi(n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y)));
     if (!isfinite(v)) bad = true;
     if (better(fabs(v), q, best.v, best.idx)) { best.v = fabs(v); best.idx = q; }
   }
@@ -248,30 +269,35 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       st->sweeps = 0;
       st->max_rank = 0;
       st->value = 0.0;
+      st->value_lo = 0.0;
       st->rel = __builtin_huge_val();
     }
     return;
   }
   const int nb = m - 1, R = p.R;
+  T* __restrict__ Lx = tp<T>(p.Lx);
+  T* __restrict__ Rx = tp<T>(p.Rx);
+  T* __restrict__ Lw = tp<T>(p.Lw);
+  T* __restrict__ Rw = tp<T>(p.Rw);
   // left sets I_<=b = {(i0_0..i0_b)}, right sets I_>b = {(i0_b+1..i0_m-1)}
   for (int e = tid; e < nb * m; e += blockDim.x) {
     int b = e / m, k = e % m;
-    double tk = p.t[s_i0[k]];
-    if (k <= b) p.Lx[((size_t)b * R) * m + k] = tk;
-    else p.Rx[((size_t)b * R) * m + k] = tk;
+    const T tk = tt[s_i0[k]];
+    if (k <= b) Lx[((size_t)b * R) * m + k] = tk;
+    else Rx[((size_t)b * R) * m + k] = tk;
   }
   if (tid == 0) {
-    double lw = 1.0;
+    T lw = num<T>(1.0);
     for (int b = 0; b < nb; ++b) {
-      lw = lw * p.w[s_i0[b]];
-      p.Lw[(size_t)b * R] = lw;
+      lw = n_mul(lw, ww[s_i0[b]]);
+      Lw[(size_t)b * R] = lw;
       p.Lpar[(size_t)b * R] = 0;
       p.Lnode[(size_t)b * R] = s_i0[b];
     }
-    double rw = 1.0;
+    T rw = num<T>(1.0);
     for (int b = nb - 1; b >= 0; --b) {
-      rw = p.w[s_i0[b + 1]] * rw;
-      p.Rw[(size_t)b * R] = rw;
+      rw = n_mul(ww[s_i0[b + 1]], rw);
+      Rw[(size_t)b * R] = rw;
       p.Rpar[(size_t)b * R] = 0;
       p.Rnode[(size_t)b * R] = s_i0[b + 1];
     }
@@ -292,22 +318,23 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
 }
 
 // ------------------------------------------------------------ search (Alg. 2)
-template <int MAXM>
+template <class T, int MAXM>
 struct SearchSmem {
-  double Lx[TT_MAX_RANK * (MAXM + 1)];
-  double Rx[TT_MAX_RANK * (MAXM + 1)];
-  double Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
-  double t[TT_MAX_NODES], w[TT_MAX_NODES];
-  double vec[TT_MAX_RANK];
+  T Lx[TT_MAX_RANK * (MAXM + 1)];
+  T Rx[TT_MAX_RANK * (MAXM + 1)];
+  T Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
+  T t[TT_MAX_NODES], w[TT_MAX_NODES];
+  T vec[TT_MAX_RANK];
   double red_v[kSweepBlock / kWave + 1];
   int red_i[kSweepBlock / kWave + 1];
-  double e_star, a_star;
+  T e_star, a_star;
 };
 
 // One step of Alg. 2 on superblock b.  The random samples, every column step and
 // every row step run through the same evaluation loop (one inlined integrand).
-template <int FAM, int MAXM>
-__device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, SearchSmem<MAXM>& sm) {
+// Decisions (argmax, acceptance) are taken on the leading double of |error|.
+template <class T, int FAM, int MAXM>
+__device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, SearchSmem<T, MAXM>& sm) {
   constexpr int LD = MAXM + 1;
   const int tid = threadIdx.x;
   ProbState* st = p.st;
@@ -325,29 +352,35 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
     return;
   }
   const FamilyArgs fa = family_args(p);
+  const T* __restrict__ gLx = tp<T>(p.Lx);
+  const T* __restrict__ gRx = tp<T>(p.Rx);
+  const T* __restrict__ gLw = tp<T>(p.Lw);
+  const T* __restrict__ gRw = tp<T>(p.Rw);
+  const T* __restrict__ gt = tp<T>(p.t);
+  const T* __restrict__ gw = tp<T>(p.w);
   mark(p, sweep, b, 0);
   // stage index-set coordinates, node table and weights in LDS
   for (int e = tid; e < rL * b; e += blockDim.x) {
     const int a = e / b, k = e % b;
-    sm.Lx[a * LD + k] = p.Lx[((size_t)(b - 1) * R + a) * m + k];
+    sm.Lx[a * LD + k] = gLx[((size_t)(b - 1) * R + a) * m + k];
   }
   const int nright = m - b - 2;
   for (int e = tid; e < rR * nright; e += blockDim.x) {
     const int a = e / nright, k = b + 2 + e % nright;
-    sm.Rx[a * LD + k] = p.Rx[((size_t)(b + 1) * R + a) * m + k];
+    sm.Rx[a * LD + k] = gRx[((size_t)(b + 1) * R + a) * m + k];
   }
-  for (int a = tid; a < rL; a += blockDim.x) sm.Lw[a] = b > 0 ? p.Lw[(size_t)(b - 1) * R + a] : 1.0;
+  for (int a = tid; a < rL; a += blockDim.x) sm.Lw[a] = b > 0 ? gLw[(size_t)(b - 1) * R + a] : num<T>(1.0);
   for (int a = tid; a < rR; a += blockDim.x)
-    sm.Rw[a] = (b + 1 <= m - 2) ? p.Rw[(size_t)(b + 1) * R + a] : 1.0;
-  for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = p.t[i]; sm.w[i] = p.w[i]; }
-  if (tid == 0) { sm.e_star = 0.0; sm.a_star = 0.0; }
+    sm.Rw[a] = (b + 1 <= m - 2) ? gRw[(size_t)(b + 1) * R + a] : num<T>(1.0);
+  for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = gt[i]; sm.w[i] = gw[i]; }
+  if (tid == 0) { sm.e_star = num<T>(0.0); sm.a_star = num<T>(0.0); }
   __syncthreads();
   mark(p, sweep, b, 1);
 
   const int nrows = rL * n, ncols = n * rR;
-  const double* __restrict__ F1 = p.F + p.Foff[b + 1];
+  const T* __restrict__ F1 = tp<T>(p.F) + p.Foff[b + 1];
   const int cc1 = colcap(p, b + 1);
-  const double* __restrict__ Cb = p.C + p.Coff[b];
+  const T* __restrict__ Cb = tp<T>(p.C) + p.Coff[b];
   const size_t ldC = (size_t)rowcap(p, b) * n;
   const int nsamp = min(nrows + ncols, kMaxSamples);
   const uint32_t total = (uint32_t)nrows * (uint32_t)ncols;
@@ -366,7 +399,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
     __syncthreads();
     const int count = mode == 0 ? nsamp : (mode == 1 ? nrows : ncols);
     ArgMax best{-1.0, 0x7fffffff};
-    double my_e = 0.0, my_a = 0.0;
+    T my_e = num<T>(0.0), my_a = num<T>(0.0);
     for (int q = tid; q < count; q += blockDim.x) {
       int pr, pc;
       if (mode == 0) {
@@ -383,10 +416,10 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
       // B at (alpha, i, j, beta): coordinates of I_<=b-1[alpha], t_i, t_j, I_>b+1[beta]
       const int al = pr / n, i = pr - al * n;
       const int j = pc / rR, be = pc - j * rR;
-      double y[MAXM];
+      T y[MAXM];
 #pragma unroll
       for (int k = 0; k < MAXM; ++k) {
-        double v = 0.0;
+        T v = num<T>(0.0);
         if (k < m) {
           v = (k < b) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
           v = (k == b) ? sm.t[i] : v;
@@ -394,23 +427,24 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
         }
         y[k] = v;
       }
-      const double W = ((sm.Lw[al] * sm.w[i]) * sm.w[j]) * sm.Rw[be];
-      const double a = W * integrand_fam<FAM, MAXM>(fa, y);
-      double s = 0.0;
+      const T W = n_mul(n_mul(n_mul(sm.Lw[al], sm.w[i]), sm.w[j]), sm.Rw[be]);
+      const T a = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
+      T s = num<T>(0.0);
       if (mode == 0) {
 #pragma unroll 8
-        for (int k = 0; k < rb; ++k) s = fma(Cb[(size_t)k * ldC + pr], F1[((size_t)k * n + j) * cc1 + be], s);
+        for (int k = 0; k < rb; ++k) s = n_mad(Cb[(size_t)k * ldC + pr], F1[((size_t)k * n + j) * cc1 + be], s);
       } else if (mode == 1) {
 #pragma unroll 8
-        for (int k = 0; k < rb; ++k) s = fma(Cb[(size_t)k * ldC + pr], sm.vec[k], s);
+        for (int k = 0; k < rb; ++k) s = n_mad(Cb[(size_t)k * ldC + pr], sm.vec[k], s);
       } else {
 #pragma unroll 8
-        for (int k = 0; k < rb; ++k) s = fma(sm.vec[k], F1[((size_t)k * n + j) * cc1 + be], s);
+        for (int k = 0; k < rb; ++k) s = n_mad(sm.vec[k], F1[((size_t)k * n + j) * cc1 + be], s);
       }
-      const double e = a - s;
-      bad |= !isfinite(e);
-      seen = fmax(seen, fabs(a));
-      if (better(fabs(e), q, best.v, best.idx)) { best.v = fabs(e); best.idx = q; my_e = e; my_a = a; }
+      const T e = n_sub(a, s);
+      const double ae = fabs(n_hi(e));
+      bad |= !isfinite(n_hi(e));
+      seen = fmax(seen, fabs(n_hi(a)));
+      if (better(ae, q, best.v, best.idx)) { best.v = ae; best.idx = q; my_e = e; my_a = a; }
     }
     best = block_argmax(best, sm.red_v, sm.red_i);
     if (!(best.v >= 0.0)) { invalid = true; break; }   // every error non-finite
@@ -451,7 +485,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   }
   const int dup = __syncthreads_or(mine);
   if (tid == 0) {
-    const double e_star = sm.e_star, a_star = sm.a_star;
+    const double e_star = n_hi(sm.e_star), a_star = n_hi(sm.a_star);
     const double scale = fmax(p.scale[b], seen);
     p.scale[b] = scale;
     const int acc = (fabs(e_star) > p.tol * scale) && !dup && !any_bad && !invalid;
@@ -465,32 +499,41 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
 }
 
 // ------------------------------------------------------------ core update
-template <int MAXM, int RMAX>
+template <class T, int MAXM, int RMAX>
 struct UpdateSmem {
   union {
     struct {                       // fibre evaluation stage
-      double Lx[TT_MAX_RANK * (MAXM + 1)];
-      double Rx[TT_MAX_RANK * (MAXM + 1)];
-      double Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
-      double t[TT_MAX_NODES], w[TT_MAX_NODES];
+      T Lx[TT_MAX_RANK * (MAXM + 1)];
+      T Rx[TT_MAX_RANK * (MAXM + 1)];
+      T Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
+      T t[TT_MAX_NODES], w[TT_MAX_NODES];
     };
-    double A[RMAX * (RMAX + 1)];   // the stored LU of the cross, zero-padded to RMAX
+    T A[RMAX * (RMAX + 1)];        // the stored LU of the cross, zero-padded to RMAX
   };
-  double u[RMAX], cp[RMAX];
+  T u[RMAX], cp[RMAX];
   int rowidx[RMAX];
-  double delta;
+  T delta;
 };
 
-template <int FAM, int MAXM, int RMAX>
+template <class T, int FAM, int MAXM, int RMAX>
 __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, const int init,
-                                            UpdateSmem<MAXM, RMAX>& sm, const int mb = -1) {
+                                            UpdateSmem<T, MAXM, RMAX>& sm, const int mb = -1) {
   constexpr int LD = MAXM + 1;
   constexpr int LA = RMAX + 1;
+  // a row of C_c is kept in registers while it is updated when it is small
+  // enough; otherwise it is worked on in place in memory
+  constexpr bool kRowInRegs = sizeof(T) * RMAX <= 256;
   const int tid = threadIdx.x;
   ProbState* st = p.st;
   if (st->done) return;
   const int m = p.m, n = p.n, R = p.R;
   const FamilyArgs fa = family_args(p);
+  T* __restrict__ gLx = tp<T>(p.Lx);
+  T* __restrict__ gRx = tp<T>(p.Rx);
+  T* __restrict__ gLw = tp<T>(p.Lw);
+  T* __restrict__ gRw = tp<T>(p.Rw);
+  const T* __restrict__ gt = tp<T>(p.t);
+  const T* __restrict__ gw = tp<T>(p.w);
   const bool hasL = c >= 1, hasR = c <= m - 2;
   const int accL = (!init && hasL) ? p.piv[c - 1].acc : 0;
   const int accR = (!init && hasR) ? p.piv[c].acc : 0;
@@ -506,12 +549,12 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     const int row = p.piv[bl].row;
     const int al = row / n, i = row - al * n;
     const size_t dst = (size_t)bl * R + rL_old;
-    for (int k = tid; k < bl; k += blockDim.x) p.Lx[dst * m + k] = p.Lx[((size_t)(bl - 1) * R + al) * m + k];
+    for (int k = tid; k < bl; k += blockDim.x) gLx[dst * m + k] = gLx[((size_t)(bl - 1) * R + al) * m + k];
     if (tid == 0) {
       p.Lpar[dst] = al;
       p.Lnode[dst] = i;
-      p.Lx[dst * m + bl] = p.t[i];
-      p.Lw[dst] = (bl >= 1 ? p.Lw[(size_t)(bl - 1) * R + al] : 1.0) * p.w[i];
+      gLx[dst * m + bl] = gt[i];
+      gLw[dst] = n_mul(bl >= 1 ? gLw[(size_t)(bl - 1) * R + al] : num<T>(1.0), gw[i]);
     }
   }
   if (accR) {   // new element of I_>c: (j*, beta*) with beta* in I_>c+1
@@ -520,33 +563,33 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     const int j = col / rRR, be = col - j * rRR;
     const size_t dst = (size_t)c * R + rR_old;
     for (int k = c + 2 + tid; k < m; k += blockDim.x)
-      p.Rx[dst * m + k] = p.Rx[((size_t)(c + 1) * R + be) * m + k];
+      gRx[dst * m + k] = gRx[((size_t)(c + 1) * R + be) * m + k];
     if (tid == 0) {
       p.Rnode[dst] = j;
       p.Rpar[dst] = be;
-      p.Rx[dst * m + c + 1] = p.t[j];
-      p.Rw[dst] = p.w[j] * ((c + 1 <= m - 2) ? p.Rw[(size_t)(c + 1) * R + be] : 1.0);
+      gRx[dst * m + c + 1] = gt[j];
+      gRw[dst] = n_mul(gw[j], (c + 1 <= m - 2) ? gRw[(size_t)(c + 1) * R + be] : num<T>(1.0));
     }
   }
   __syncthreads();
   // ---- stage I_<=c-1 and I_>c coordinates
   for (int e = tid; e < rL_new * c; e += blockDim.x) {
     const int a = e / c, k = e % c;
-    sm.Lx[a * LD + k] = p.Lx[((size_t)(c - 1) * R + a) * m + k];
+    sm.Lx[a * LD + k] = gLx[((size_t)(c - 1) * R + a) * m + k];
   }
   const int nright = m - c - 1;
   for (int e = tid; e < rR_new * nright; e += blockDim.x) {
     const int a = e / nright, k = c + 1 + e % nright;
-    sm.Rx[a * LD + k] = p.Rx[((size_t)c * R + a) * m + k];
+    sm.Rx[a * LD + k] = gRx[((size_t)c * R + a) * m + k];
   }
-  for (int a = tid; a < rL_new; a += blockDim.x) sm.Lw[a] = hasL ? p.Lw[(size_t)(c - 1) * R + a] : 1.0;
-  for (int a = tid; a < rR_new; a += blockDim.x) sm.Rw[a] = hasR ? p.Rw[(size_t)c * R + a] : 1.0;
-  for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = p.t[i]; sm.w[i] = p.w[i]; }
+  for (int a = tid; a < rL_new; a += blockDim.x) sm.Lw[a] = hasL ? gLw[(size_t)(c - 1) * R + a] : num<T>(1.0);
+  for (int a = tid; a < rR_new; a += blockDim.x) sm.Rw[a] = hasR ? gRw[(size_t)c * R + a] : num<T>(1.0);
+  for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = gt[i]; sm.w[i] = gw[i]; }
   __syncthreads();
   if (mb >= 0) mark(p, msw, mb, 9);
 
   // ---- evaluate the new entries of F_c = B(I_<=c-1, i_c, I_>c)
-  double* __restrict__ Fc = p.F + p.Foff[c];
+  T* __restrict__ Fc = tp<T>(p.F) + p.Foff[c];
   const int cc = colcap(p, c);
   const int nA = (rL_new - rL_old) * n * rR_new;            // new rows (all columns)
   const int nBc = rR_new - rR_old;
@@ -566,19 +609,19 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
       i = rem / nBc;
       be = rR_old + rem % nBc;
     }
-    double y[MAXM];
+    T y[MAXM];
 #pragma unroll
     for (int k = 0; k < MAXM; ++k) {
-      double v = 0.0;
+      T v = num<T>(0.0);
       if (k < m) {
         v = (k < c) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
         v = (k == c) ? sm.t[i] : v;
       }
       y[k] = v;
     }
-    const double W = (sm.Lw[al] * sm.w[i]) * sm.Rw[be];
-    const double v = W * integrand_fam<FAM, MAXM>(fa, y);
-    bad |= !isfinite(v);
+    const T W = n_mul(n_mul(sm.Lw[al], sm.w[i]), sm.Rw[be]);
+    const T v = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
+    bad |= !isfinite(n_hi(v));
     Fc[((size_t)al * n + i) * cc + be] = v;
   }
   const int any_bad = __syncthreads_or(bad);
@@ -588,12 +631,12 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     if (any_bad) atomicOr(&st->err_flags, 1);
   }
 
-  double* __restrict__ S = p.S + (size_t)c * R * R;
+  T* __restrict__ S = tp<T>(p.S) + (size_t)c * R * R;
   if (!hasR) {   // last core: S(alpha) = sum_i F(alpha, i)
     for (int al = tid; al < rL_new; al += blockDim.x) {
-      double s = 0.0;
+      T s = num<T>(0.0);
 #pragma unroll 16
-      for (int i = 0; i < n; ++i) s += Fc[(size_t)al * n + i];
+      for (int i = 0; i < n; ++i) s = n_add(s, Fc[(size_t)al * n + i]);
       S[(size_t)al * R] = s;
     }
     return;
@@ -607,22 +650,22 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     if (tid == 0) atomicOr(&st->err_flags, 8);
     return;
   }
-  double* __restrict__ LU = p.LU + (size_t)c * R * R;
-  double* __restrict__ Cc = p.C + p.Coff[c];
+  T* __restrict__ LU = tp<T>(p.LU) + (size_t)c * R * R;
+  T* __restrict__ Cc = tp<T>(p.C) + p.Coff[c];
   const size_t ldC = (size_t)rowcap(p, c) * n;
   __syncthreads();   // the evaluation stage's LDS is reused below
   if (init) {        // rank 1: M_c = (B(i0)), C_c = F_c / M_c
     const int row0 = p.Lpar[(size_t)c * R] * n + p.Lnode[(size_t)c * R];
-    const double m00 = Fc[(size_t)row0 * cc];
+    const T m00 = Fc[(size_t)row0 * cc];
     if (tid == 0) {
       LU[0] = m00;
-      if (m00 == 0.0) atomicOr(&st->err_flags, 2);
+      if (n_hi(m00) == 0.0) atomicOr(&st->err_flags, 2);
     }
-    for (int row = tid; row < N; row += blockDim.x) Cc[row] = Fc[(size_t)row * cc] / m00;
+    for (int row = tid; row < N; row += blockDim.x) Cc[row] = n_div(Fc[(size_t)row * cc], m00);
   } else {
     for (int e = tid; e < RMAX * RMAX; e += blockDim.x) {
       const int a = e / RMAX, q = e % RMAX;
-      sm.A[a * LA + q] = (a < r0 && q < r0) ? LU[(size_t)a * R + q] : 0.0;
+      sm.A[a * LA + q] = (a < r0 && q < r0) ? LU[(size_t)a * R + q] : num<T>(0.0);
     }
     if (tid < r0) sm.rowidx[tid] = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
     __syncthreads();
@@ -631,30 +674,43 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     if (accL) {
       for (int i = tid; i < n; i += blockDim.x) {
         const int row = rL_old * n + i;
-        double x[RMAX];
+        if constexpr (kRowInRegs) {
+          T x[RMAX];
 #pragma unroll
-        for (int q = 0; q < RMAX; ++q) x[q] = (q < r0) ? Fc[(size_t)row * cc + q] : 0.0;
+          for (int q = 0; q < RMAX; ++q) x[q] = (q < r0) ? Fc[(size_t)row * cc + q] : num<T>(0.0);
 #pragma unroll
-        for (int q = 0; q < RMAX; ++q) {
-          if (q < r0) {
-            double s = x[q];
+          for (int q = 0; q < RMAX; ++q) {
+            if (q < r0) {
+              T s = x[q];
 #pragma unroll
-            for (int pp = 0; pp < q; ++pp) s = fma(-x[pp], sm.A[pp * LA + q], s);
-            x[q] = s / sm.A[q * LA + q];
+              for (int pp = 0; pp < q; ++pp) s = n_nmad(x[pp], sm.A[pp * LA + q], s);
+              x[q] = n_div(s, sm.A[q * LA + q]);
+            }
+          }
+#pragma unroll
+          for (int a = RMAX - 1; a >= 0; --a) {
+            if (a < r0) {
+              T s = x[a];
+#pragma unroll
+              for (int bb = a + 1; bb < RMAX; ++bb) s = n_nmad(x[bb], sm.A[bb * LA + a], s);
+              x[a] = s;
+            }
+          }
+#pragma unroll
+          for (int a = 0; a < RMAX; ++a)
+            if (a < r0) Cc[(size_t)a * ldC + row] = x[a];
+        } else {   // the same solves with the row of C_c as the working storage
+          for (int q = 0; q < r0; ++q) {
+            T s = Fc[(size_t)row * cc + q];
+            for (int pp = 0; pp < q; ++pp) s = n_nmad(Cc[(size_t)pp * ldC + row], sm.A[pp * LA + q], s);
+            Cc[(size_t)q * ldC + row] = n_div(s, sm.A[q * LA + q]);
+          }
+          for (int a = r0 - 1; a >= 0; --a) {
+            T s = Cc[(size_t)a * ldC + row];
+            for (int bb = a + 1; bb < r0; ++bb) s = n_nmad(Cc[(size_t)bb * ldC + row], sm.A[bb * LA + a], s);
+            Cc[(size_t)a * ldC + row] = s;
           }
         }
-#pragma unroll
-        for (int a = RMAX - 1; a >= 0; --a) {
-          if (a < r0) {
-            double s = x[a];
-#pragma unroll
-            for (int bb = a + 1; bb < RMAX; ++bb) s = fma(-x[bb], sm.A[bb * LA + a], s);
-            x[a] = s;
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < RMAX; ++a)
-          if (a < r0) Cc[(size_t)a * ldC + row] = x[a];
       }
     }
     if (mb >= 0) mark(p, msw, mb, 11);
@@ -663,22 +719,22 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
       // (c) border the LU: w = L^-1 u, l = v U^-1, delta = F_c(prow, r0) - l . w, with
       //     u = F_c(I_<=c, r0) the new column at the old cross rows and v = F_c(prow, :r0)
       if (tid < kWave) {
-        double wa = (tid < r0) ? Fc[(size_t)sm.rowidx[tid] * cc + r0] : 0.0;
-        double lq = (tid < r0) ? Fc[(size_t)prow * cc + tid] : 0.0;
+        T wa = (tid < r0) ? Fc[(size_t)sm.rowidx[tid] * cc + r0] : num<T>(0.0);
+        T lq = (tid < r0) ? Fc[(size_t)prow * cc + tid] : num<T>(0.0);
         if (tid < r0) sm.u[tid] = wa;
         for (int k2 = 0; k2 < r0; ++k2) {
-          const double wk = __shfl(wa, k2, kWave);
-          if (tid > k2 && tid < r0) wa = fma(-sm.A[tid * LA + k2], wk, wa);
+          const T wk = n_shfl(wa, k2);
+          if (tid > k2 && tid < r0) wa = n_nmad(sm.A[tid * LA + k2], wk, wa);
         }
         for (int k2 = 0; k2 < r0; ++k2) {
-          const double lk = __shfl(lq, k2, kWave) / sm.A[k2 * LA + k2];
+          const T lk = n_div(n_shfl(lq, k2), sm.A[k2 * LA + k2]);
           if (tid == k2) lq = lk;
-          else if (tid > k2 && tid < r0) lq = fma(-lk, sm.A[k2 * LA + tid], lq);
+          else if (tid > k2 && tid < r0) lq = n_nmad(lk, sm.A[k2 * LA + tid], lq);
         }
-        double prod = (tid < r0) ? lq * wa : 0.0;
+        T prod = (tid < r0) ? n_mul(lq, wa) : num<T>(0.0);
 #pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) prod += __shfl_xor(prod, off, kWave);
-        const double delta = Fc[(size_t)prow * cc + r0] - prod;
+        for (int off = kWave / 2; off > 0; off >>= 1) prod = n_add(prod, n_shfl_xor(prod, off));
+        const T delta = n_sub(Fc[(size_t)prow * cc + r0], prod);
         if (tid < r0) {
           LU[(size_t)r0 * R + tid] = lq;
           LU[(size_t)tid * R + r0] = wa;
@@ -686,27 +742,36 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
         if (tid == 0) {
           LU[(size_t)r0 * R + r0] = delta;
           sm.delta = delta;
-          if (delta == 0.0) atomicOr(&st->err_flags, 2);
+          if (n_hi(delta) == 0.0) atomicOr(&st->err_flags, 2);
         }
       }
       if (tid < r0) sm.cp[tid] = Cc[(size_t)tid * ldC + prow];   // C_c(prow, :) before the update
       __syncthreads();
       if (mb >= 0) mark(p, msw, mb, 12);
       // (b) rank-1 update of every row: e = F_c(:, r0) - C_c u, C_c <- [C_c - (e/delta) c_piv, e/delta]
-      const double delta = sm.delta;
+      const T delta = sm.delta;
       for (int row = tid; row < N; row += blockDim.x) {
-        double x[RMAX];
+        if constexpr (kRowInRegs) {
+          T x[RMAX];
 #pragma unroll
-        for (int k = 0; k < RMAX; ++k) x[k] = (k < r0) ? Cc[(size_t)k * ldC + row] : 0.0;
-        double e = Fc[(size_t)row * cc + r0];
+          for (int k = 0; k < RMAX; ++k) x[k] = (k < r0) ? Cc[(size_t)k * ldC + row] : num<T>(0.0);
+          T e = Fc[(size_t)row * cc + r0];
 #pragma unroll
-        for (int k = 0; k < RMAX; ++k)
-          if (k < r0) e = fma(-x[k], sm.u[k], e);
-        const double f = e / delta;
+          for (int k = 0; k < RMAX; ++k)
+            if (k < r0) e = n_nmad(x[k], sm.u[k], e);
+          const T f = n_div(e, delta);
 #pragma unroll
-        for (int k = 0; k < RMAX; ++k)
-          if (k < r0) Cc[(size_t)k * ldC + row] = fma(-f, sm.cp[k], x[k]);
-        Cc[(size_t)r0 * ldC + row] = f;
+          for (int k = 0; k < RMAX; ++k)
+            if (k < r0) Cc[(size_t)k * ldC + row] = n_nmad(f, sm.cp[k], x[k]);
+          Cc[(size_t)r0 * ldC + row] = f;
+        } else {
+          T e = Fc[(size_t)row * cc + r0];
+          for (int k = 0; k < r0; ++k) e = n_nmad(Cc[(size_t)k * ldC + row], sm.u[k], e);
+          const T f = n_div(e, delta);
+          for (int k = 0; k < r0; ++k)
+            Cc[(size_t)k * ldC + row] = n_nmad(f, sm.cp[k], Cc[(size_t)k * ldC + row]);
+          Cc[(size_t)r0 * ldC + row] = f;
+        }
       }
     }
     if (mb >= 0) mark(p, msw, mb, 13);
@@ -715,10 +780,10 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   // ---- S_c(alpha, k) = sum_i C_c(alpha, i, k)
   for (int e = tid; e < rL_new * r; e += blockDim.x) {
     const int al = e / r, k = e % r;
-    const double* __restrict__ src = Cc + (size_t)k * ldC + (size_t)al * n;
-    double s = 0.0;
+    const T* __restrict__ src = Cc + (size_t)k * ldC + (size_t)al * n;
+    T s = num<T>(0.0);
 #pragma unroll 16
-    for (int i = 0; i < n; ++i) s += src[i];
+    for (int i = 0; i < n; ++i) s = n_add(s, src[i]);
     S[(size_t)al * R + k] = s;
   }
   if (mb >= 0) {
@@ -729,25 +794,31 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
 
 // ------------------------------------------------------------ k_integral
 constexpr int kIntBlock = 512;
-constexpr int kIntStage = 6144;   // doubles of S staged in LDS at once (48 KiB)
+constexpr int kIntStageBytes = 49152;   // S staged in LDS at once
 
+template <class T>
 struct IntSmem {
-  double v[TT_MAX_RANK], v2[TT_MAX_RANK];
-  double stage[kIntStage];
+  static constexpr int kStage = kIntStageBytes / (int)sizeof(T);
+  T v[TT_MAX_RANK], v2[TT_MAX_RANK];
+  T stage[kStage];
   int s_rank[TT_MAX_MODES];
   int s_off[TT_MAX_MODES + 1];
 };
 
-__device__ __forceinline__ void integral_problem(const ProbDesc& p, const int init, IntSmem& sm) {
+template <class T>
+__device__ __forceinline__ void integral_problem(const ProbDesc& p, const int init, IntSmem<T>& sm) {
+  constexpr int kStage = IntSmem<T>::kStage;
   ProbState* st = p.st;
   if (st->done) return;
+  T* __restrict__ hist = tp<T>(p.hist);
+  const T* __restrict__ gS = tp<T>(p.S);
   // state needed by the stopping rule, loaded now so its latency overlaps the chain
   const int sw0 = st->sweeps;
-  const double prev = p.hist[sw0];
+  const T prev = hist[sw0];
   const double prev_rel = st->rel;
-  double* v = sm.v;
-  double* v2 = sm.v2;
-  double* stage = sm.stage;
+  T* v = sm.v;
+  T* v2 = sm.v2;
+  T* stage = sm.stage;
   int* s_rank = sm.s_rank;
   int* s_off = sm.s_off;
   const int m = p.m, R = p.R, nb = p.nbonds, tid = threadIdx.x;
@@ -764,16 +835,17 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
   int maxr = 1;
   for (int b = 0; b < nb; ++b) maxr = max(maxr, s_rank[b]);
   // v = S_0 (1 x r_0), then v <- v S_c for c = 1..m-1 (2m-1 matrices, inverses in C)
-  for (int k = tid; k < s_rank[0]; k += blockDim.x) v[k] = p.S[k];
+  for (int k = tid; k < s_rank[0]; k += blockDim.x) v[k] = gS[k];
   int c0 = 1;
   while (c0 < m) {
-    // stage as many consecutive S_c as fit, all loads in flight together
+    // stage as many consecutive S_c as fit, all loads in flight together; a core
+    // whose S_c alone exceeds the stage is multiplied straight from memory
     if (tid == 0) {
       int off = 0, c = c0;
       s_off[0] = 0;
       while (c < m) {
         const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
-        if (off + rl * rr > kIntStage && c > c0) break;
+        if (off + rl * rr > kStage) break;
         off += rl * rr;
         s_off[c - c0 + 1] = off;
         ++c;
@@ -781,23 +853,28 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
       s_off[TT_MAX_MODES] = c;
     }
     __syncthreads();
-    const int c1 = s_off[TT_MAX_MODES];
-    for (int c = c0; c < c1; ++c) {
-      const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
-      const double* __restrict__ S = p.S + (size_t)c * R * R;
-      double* dst = stage + s_off[c - c0];
-      for (int e = tid; e < rl * rr; e += blockDim.x) dst[e] = S[(size_t)(e / rr) * R + e % rr];
+    int c1 = s_off[TT_MAX_MODES];
+    const bool direct = (c1 == c0);
+    if (direct) c1 = c0 + 1;
+    if (!direct) {
+      for (int c = c0; c < c1; ++c) {
+        const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
+        const T* __restrict__ S = gS + (size_t)c * R * R;
+        T* dst = stage + s_off[c - c0];
+        for (int e = tid; e < rl * rr; e += blockDim.x) dst[e] = S[(size_t)(e / rr) * R + e % rr];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (int c = c0; c < c1; ++c) {   // ping-pong between v and v2: one barrier per core
       const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
-      const double* Sc = stage + s_off[c - c0];
+      const T* Sc = direct ? gS + (size_t)c * R * R : stage + s_off[c - c0];
+      const int ldS = direct ? R : rr;
       for (int k = tid; k < rr; k += blockDim.x) {
-        double s = 0.0;
-        for (int a = 0; a < rl; ++a) s = fma(v[a], Sc[a * rr + k], s);
+        T s = num<T>(0.0);
+        for (int a = 0; a < rl; ++a) s = n_mad(v[a], Sc[a * ldS + k], s);
         v2[k] = s;
       }
-      double* tmp = v;
+      T* tmp = v;
       v = v2;
       v2 = tmp;
       __syncthreads();
@@ -805,19 +882,21 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
     c0 = c1;
   }
   if (tid != 0) return;
-  const double value = v[0];
+  const T value = v[0];
   st->max_rank = maxr;
-  if (!isfinite(value)) st->err_flags |= 1;
+  if (!isfinite(n_hi(value))) st->err_flags |= 1;
   if (init) {
-    p.hist[0] = value;
-    st->value = value;
+    hist[0] = value;
+    st->value = n_hi(value);
+    st->value_lo = n_lo(value);
     return;
   }
-  const double rel = value != 0.0 ? fabs(value - prev) / fabs(value) : __builtin_huge_val();
+  const double rel = n_hi(value) != 0.0 ? fabs(n_hi(n_div(n_sub(value, prev), value))) : __builtin_huge_val();
   const int s = sw0 + 1;
   st->sweeps = s;
-  p.hist[s] = value;
-  st->value = value;
+  hist[s] = value;
+  st->value = n_hi(value);
+  st->value_lo = n_lo(value);
   st->rel = rel;
   st->nacc = nacc;
   int done = 0, reason = TT_RUNNING;
@@ -843,24 +922,25 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
 }
 
 // ------------------------------------------------------------ kernels
-template <int FAM, int MAXM, int RMAX>
+template <class T, int FAM, int MAXM, int RMAX>
 __global__ __launch_bounds__(kSweepBlock) void k_update(ProbDesc* __restrict__ P,
                                                         const int2* __restrict__ tasks, int init) {
-  __shared__ UpdateSmem<MAXM, RMAX> sm;
+  __shared__ UpdateSmem<T, MAXM, RMAX> sm;
   const int2 tk = tasks[blockIdx.x];
-  update_core<FAM, MAXM, RMAX>(P[tk.x], tk.y, init, sm);
+  update_core<T, FAM, MAXM, RMAX>(P[tk.x], tk.y, init, sm);
 }
 
-static __global__ __launch_bounds__(kIntBlock) void k_integral(ProbDesc* __restrict__ P, int init) {
-  __shared__ IntSmem sm;
-  integral_problem(P[blockIdx.x], init, sm);
+template <class T>
+__global__ __launch_bounds__(kIntBlock) void k_integral(ProbDesc* __restrict__ P, int init) {
+  __shared__ IntSmem<T> sm;
+  integral_problem<T>(P[blockIdx.x], init, sm);
 }
 
-template <int MAXM, int RMAX>
+template <class T, int MAXM, int RMAX>
 union SweepSmem {
-  SearchSmem<MAXM> s;
-  UpdateSmem<MAXM, RMAX> u;
-  IntSmem i;
+  SearchSmem<T, MAXM> s;
+  UpdateSmem<T, MAXM, RMAX> u;
+  IntSmem<T> i;
 };
 
 // One sweep of Alg. 6 in one launch, one workgroup per superblock.  Every
@@ -869,10 +949,10 @@ union SweepSmem {
 // finishes last.  Each hand-over is a release fence plus an atomic increment,
 // observed by the arriving workgroup after an acquire fence; no workgroup waits
 // for another, so any subset of workgroups may be resident at a time.
-template <int FAM, int MAXM, int RMAX>
+template <class T, int FAM, int MAXM, int RMAX>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
                                                        const int2* __restrict__ tasks) {
-  __shared__ SweepSmem<MAXM, RMAX> sm;
+  __shared__ SweepSmem<T, MAXM, RMAX> sm;
   __shared__ int s_todo[3];
   __shared__ int s_last;
   const int2 tk = tasks[blockIdx.x];
@@ -880,7 +960,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
   const int b = tk.y, tid = threadIdx.x, m = p.m;
   if (p.st->done) return;
   const int sweep = p.st->sweeps;
-  search_bond<FAM, MAXM>(p, b, sm.s);
+  search_bond<T, FAM, MAXM>(p, b, sm.s);
   __syncthreads();
   mark(p, sweep, b, 4);
   if (tid == 0) {
@@ -898,7 +978,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
   mark(p, sweep, b, 8);
   for (int q = 0; q < nt; ++q) {
     const int c = s_todo[q];
-    update_core<FAM, MAXM, RMAX>(p, c, 0, sm.u, b);
+    update_core<T, FAM, MAXM, RMAX>(p, c, 0, sm.u, b);
     __syncthreads();
     mark(p, sweep, b, 5);
     if (tid == 0) {
@@ -908,7 +988,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
     }
     __syncthreads();
     if (s_last) {
-      integral_problem(p, 0, sm.i);
+      integral_problem<T>(p, 0, sm.i);
       __syncthreads();
       for (int k = tid; k <= m; k += blockDim.x) p.sync[k] = 0;   // every hand-over of this sweep is done
       mark(p, sweep, b, 6);
@@ -919,26 +999,26 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
 }
 
 // ------------------------------------------------------- standalone eval
-template <int MAXM>
-__global__ __launch_bounds__(kBlock) void k_eval_points(FamilyArgs fa, const double* __restrict__ t,
-                                                        const double* __restrict__ w,
+template <class T, int FAM, int MAXM>
+__global__ __launch_bounds__(kBlock) void k_eval_points(FamilyArgs fa, const T* __restrict__ t,
+                                                        const T* __restrict__ w,
                                                         const int32_t* __restrict__ idx,
-                                                        int64_t npts, double* __restrict__ out) {
+                                                        int64_t npts, T* __restrict__ out) {
   const int m = fa.m;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < npts;
        q += (int64_t)gridDim.x * blockDim.x) {
-    double y[MAXM];
-    double W = 1.0;
+    T y[MAXM];
+    T W = num<T>(1.0);
 #pragma unroll
     for (int k = 0; k < MAXM; ++k) {
-      y[k] = 0.0;
+      y[k] = num<T>(0.0);
       if (k < m) {
         const int ik = idx[q * m + k];
         y[k] = t[ik];
-        W = W * w[ik];
+        W = n_mul(W, w[ik]);
       }
     }
-    out[q] = W * integrand<MAXM>(fa, y);
+    out[q] = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
   }
 }
 
@@ -947,34 +1027,34 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(FamilyArgs fa, const dou
 // (alpha, i, beta) with beta fastest.  The grid is bounded and strides over the
 // points; each lane advances its (alpha, i, beta) by the fixed stride with
 // carries instead of dividing.
-template <int FAM, int MAXM>
-__global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, const double* __restrict__ t,
-                                                        const double* __restrict__ w, int pos,
+template <class T, int FAM, int MAXM>
+__global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, const T* __restrict__ t,
+                                                        const T* __restrict__ w, int pos,
                                                         const int32_t* __restrict__ left, int rl,
                                                         const int32_t* __restrict__ right, int rr,
-                                                        double* __restrict__ out) {
+                                                        T* __restrict__ out) {
   constexpr int LD = MAXM + 1;
-  __shared__ double sLx[TT_MAX_RANK * LD], sRx[TT_MAX_RANK * LD];
-  __shared__ double sLw[TT_MAX_RANK], sRw[TT_MAX_RANK];
-  __shared__ double st[TT_MAX_NODES], sw[TT_MAX_NODES];
+  __shared__ T sLx[TT_MAX_RANK * LD], sRx[TT_MAX_RANK * LD];
+  __shared__ T sLw[TT_MAX_RANK], sRw[TT_MAX_RANK];
+  __shared__ T st[TT_MAX_NODES], sw[TT_MAX_NODES];
   const int m = fa.m, tid = threadIdx.x, nr = m - pos - 1;
   for (int i = tid; i < n; i += blockDim.x) { st[i] = t[i]; sw[i] = w[i]; }
   __syncthreads();
   for (int a = tid; a < rl; a += blockDim.x) {
-    double ww = 1.0;
+    T ww = num<T>(1.0);
     for (int k = 0; k < pos; ++k) {
       const int ik = left[a * pos + k];
       sLx[a * LD + k] = st[ik];
-      ww = ww * sw[ik];
+      ww = n_mul(ww, sw[ik]);
     }
     sLw[a] = ww;
   }
   for (int a = tid; a < rr; a += blockDim.x) {
-    double ww = 1.0;
+    T ww = num<T>(1.0);
     for (int k = nr - 1; k >= 0; --k) {
       const int ik = right[a * nr + k];
       sRx[a * LD + pos + 1 + k] = st[ik];
-      ww = sw[ik] * ww;
+      ww = n_mul(sw[ik], ww);
     }
     sRw[a] = ww;
   }
@@ -988,18 +1068,18 @@ __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, co
   const int dbe = (int)(stride % (uint32_t)rr), di = (int)((stride / (uint32_t)rr) % (uint32_t)n);
   const int dal = (int)(stride / ((uint32_t)rr * n));
   for (; q < total; q += stride) {
-    double y[MAXM];
+    T y[MAXM];
 #pragma unroll
     for (int k = 0; k < MAXM; ++k) {
-      double v = 0.0;
+      T v = num<T>(0.0);
       if (k < m) {
         v = (k < pos) ? sLx[al * LD + k] : sRx[be * LD + k];
         v = (k == pos) ? st[i] : v;
       }
       y[k] = v;
     }
-    const double W = (sLw[al] * sw[i]) * sRw[be];
-    out[q] = W * integrand_fam<FAM, MAXM>(fa, y);
+    const T W = n_mul(n_mul(sLw[al], sw[i]), sRw[be]);
+    out[q] = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
     be += dbe;
     int ci = 0;
     if (be >= rr) { be -= rr; ci = 1; }

@@ -45,7 +45,11 @@ struct tt_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::mutex mu;
-  std::map<int, std::pair<double*, double*>> gl;   // n -> device (t, w)
+  struct GL {
+    double *t, *w;     // nodes and weights rounded to double
+    dd *t2, *w2;       // the same in double-double
+  };
+  std::map<int, GL> gl;                            // n -> device tables
   double* params = nullptr;                        // device scratch for synthetic params
   size_t params_cap = 0;
   std::multimap<size_t, void*> arenas;             // freed job arenas kept for reuse
@@ -72,6 +76,8 @@ struct tt_job {
   int ncore = 0;
   int maxm = 0, maxR = 1;
   int fam = 3;            // integrand class the job's kernels are specialised for
+  bool dd = false;        // double-double job
+  std::vector<std::pair<double*, double*>> gl64;   // per integral: the double node tables
   int launched = 0;       // sweeps enqueued so far
   int max_sweeps_all = 0;
   ProbState* dstate = nullptr;
@@ -150,7 +156,8 @@ tt_status validate(const tt_problem* p) {
   if (p->n_nodes < 1 || p->n_nodes > TT_MAX_NODES) return TT_EINVAL;
   if (p->rank_cap < 1 || p->rank_cap > TT_MAX_RANK) return TT_EINVAL;
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return TT_EINVAL;
-  if (p->precision != TT_FP64) return TT_EINVAL;
+  if (p->precision != TT_FP64 && p->precision != TT_DD) return TT_EINVAL;
+  if (p->precision == TT_DD && fam_of(p->integrand) != FAM_PAPER) return TT_EINVAL;
   if (p->max_sweeps < 0 || p->max_sweeps > 1024) return TT_EINVAL;
   if (is_synthetic(p->integrand) && !p->params) return TT_EINVAL;
   // the superblock size r n n r must fit a 32-bit sample index
@@ -182,7 +189,8 @@ ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   const int m = modes_of(p), n = p.n_nodes, R = p.rank_cap;
   const int nb = m > 1 ? m - 1 : 0;
   const int ms = max_sweeps_of(p);
-  const size_t D = sizeof(double), I = sizeof(int32_t);
+  // D: bytes of one value of the job's number type; plain doubles use sizeof(double)
+  const size_t D = p.precision == TT_DD ? sizeof(dd) : sizeof(double), I = sizeof(int32_t);
   o.Lpar = L.take((size_t)nb * R * I);
   o.Lnode = L.take((size_t)nb * R * I);
   o.Rpar = L.take((size_t)nb * R * I);
@@ -208,7 +216,7 @@ ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   o.S = L.take((size_t)(m > 0 ? m : 1) * R * R * D);
   o.rank = L.take((size_t)(nb > 0 ? nb : 1) * I);
   o.piv = L.take((size_t)(nb > 0 ? nb : 1) * sizeof(PivRec));
-  o.scale = L.take((size_t)(nb > 0 ? nb : 1) * D);
+  o.scale = L.take((size_t)(nb > 0 ? nb : 1) * sizeof(double));
   o.log = L.take((size_t)ms * (nb > 0 ? nb : 1) * sizeof(PivRec));
   o.hist = L.take((size_t)(ms + 1) * D);
   o.start = L.take((size_t)(m > 0 ? m : 1) * I);
@@ -229,6 +237,10 @@ double four_over_fact(int m) {
 void launch(tt_job* j, int what, int rb) {
   LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, bucket_m(j->maxm), j->ctx->stream};
   Timed tm(j->ctx, what == LAUNCH_SWEEP ? KK_SWEEP : what == LAUNCH_START ? KK_START : KK_UPDATE);
+  if (j->dd) {
+    launch_paper_dd(a, what, rb);
+    return;
+  }
   switch (j->fam) {
     case FAM_PAPER: launch_paper(a, what, rb); break;
     case FAM_UFORM: launch_uform(a, what, rb); break;
@@ -265,23 +277,28 @@ void fill_info(const ProbState& s, tt_info* out) {
   out->evals = (int64_t)s.evals;
   out->value = s.value;
   out->rel_change = s.rel;
+  out->value_lo = s.value_lo;
 }
 
-tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w) {
+// Node tables for n, generated on first use.  With want_dd the returned
+// pointers are the double-double tables (reinterpreted as double*).
+tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd = false) {
   auto it = ctx->gl.find(n);
   if (it == ctx->gl.end()) {
-    double *dt = nullptr, *dw = nullptr;
-    TT_HIP(hipMalloc(&dt, n * sizeof(double)));
-    TT_HIP(hipMalloc(&dw, n * sizeof(double)));
+    tt_ctx::GL g{nullptr, nullptr, nullptr, nullptr};
+    TT_HIP(hipMalloc(&g.t, n * sizeof(double)));
+    TT_HIP(hipMalloc(&g.w, n * sizeof(double)));
+    TT_HIP(hipMalloc(&g.t2, n * sizeof(dd)));
+    TT_HIP(hipMalloc(&g.w2, n * sizeof(dd)));
     {
       Timed tm(ctx, KK_GL);
-      hipLaunchKernelGGL(k_gl, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, dt, dw);
+      hipLaunchKernelGGL(k_gl, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, g.t, g.w, g.t2, g.w2);
     }
     TT_HIP(hipGetLastError());
-    it = ctx->gl.emplace(n, std::make_pair(dt, dw)).first;
+    it = ctx->gl.emplace(n, g).first;
   }
-  *t = it->second.first;
-  *w = it->second.second;
+  *t = want_dd ? reinterpret_cast<double*>(it->second.t2) : it->second.t;
+  *w = want_dd ? reinterpret_cast<double*>(it->second.w2) : it->second.w;
   return TT_OK;
 }
 
@@ -310,6 +327,40 @@ tt_status family_for(tt_ctx* ctx, const tt_problem* p, FamilyArgs* fa) {
   return TT_OK;
 }
 
+}  // namespace
+
+namespace {
+template <int MAXM>
+void eval_points_m(tt_ctx* ctx, bool use_dd, dim3 grid, dim3 block, const FamilyArgs& fa, const double* t,
+                   const double* w, const int32_t* d_idx, int64_t npts, double* d_out) {
+  if (use_dd)
+    hipLaunchKernelGGL((k_eval_points<dd, FAM_PAPER, MAXM>), grid, block, 0, ctx->stream, fa,
+                       reinterpret_cast<const dd*>(t), reinterpret_cast<const dd*>(w), d_idx, npts,
+                       reinterpret_cast<dd*>(d_out));
+  else
+    hipLaunchKernelGGL((k_eval_points<double, FAM_ANY, MAXM>), grid, block, 0, ctx->stream, fa, t, w, d_idx,
+                       npts, d_out);
+}
+
+template <class T, int FAM, int MAXM>
+void eval_fibers_k(tt_ctx* ctx, dim3 grid, dim3 block, const FamilyArgs& fa, int n, const double* t,
+                   const double* w, int pos, const int32_t* d_left, int r_left, const int32_t* d_right,
+                   int r_right, double* d_out) {
+  hipLaunchKernelGGL((k_eval_fibers<T, FAM, MAXM>), grid, block, 0, ctx->stream, fa, n,
+                     reinterpret_cast<const T*>(t), reinterpret_cast<const T*>(w), pos, d_left, r_left,
+                     d_right, r_right, reinterpret_cast<T*>(d_out));
+}
+
+template <class T, int FAM>
+void eval_fibers_f(tt_ctx* ctx, int mb, dim3 grid, dim3 block, const FamilyArgs& fa, int n, const double* t,
+                   const double* w, int pos, const int32_t* d_left, int r_left, const int32_t* d_right,
+                   int r_right, double* d_out) {
+  switch (mb) {
+    case 8: eval_fibers_k<T, FAM, 8>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
+    case 16: eval_fibers_k<T, FAM, 16>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
+    default: eval_fibers_k<T, FAM, 32>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
+  }
+}
 }  // namespace
 
 extern "C" {
@@ -354,8 +405,10 @@ void tt_ctx_destroy(tt_ctx* c) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   for (auto& kv : c->gl) {
-    hipFree(kv.second.first);
-    hipFree(kv.second.second);
+    hipFree(kv.second.t);
+    hipFree(kv.second.w);
+    hipFree(kv.second.t2);
+    hipFree(kv.second.w2);
   }
   if (c->params) hipFree(c->params);
   for (auto& kv : c->arenas) hipFree(kv.second);
@@ -406,8 +459,10 @@ size_t tt_job_footprint(const tt_problem* p) {
 
 tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, tt_job** out) {
   if (!ctx || !problems || count < 1 || !out) return TT_EINVAL;
-  for (int k = 0; k < count; ++k)
+  for (int k = 0; k < count; ++k) {
     if (validate(&problems[k]) != TT_OK) return TT_EINVAL;
+    if (problems[k].precision != problems[0].precision) return TT_EINVAL;
+  }
   std::lock_guard<std::mutex> lock(ctx->mu);
   TT_HIP(hipSetDevice(ctx->device));
   tt_job* j = new (std::nothrow) tt_job;
@@ -415,10 +470,13 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->ctx = ctx;
   j->nprob = count;
   j->probs.assign(problems, problems + count);
+  j->dd = problems[0].precision == TT_DD;
   // Gauss--Legendre tables are computed once per node count and shared by all jobs of the context
   std::vector<std::pair<double*, double*>> gl(count);
+  j->gl64.resize(count);
   for (int k = 0; k < count; ++k) {
-    tt_status s = gl_table(ctx, problems[k].n_nodes, &gl[k].first, &gl[k].second);
+    tt_status s = gl_table(ctx, problems[k].n_nodes, &j->gl64[k].first, &j->gl64[k].second);
+    if (s == TT_OK) s = gl_table(ctx, problems[k].n_nodes, &gl[k].first, &gl[k].second, j->dd);
     if (s != TT_OK) {
       delete j;
       return s;
@@ -553,7 +611,10 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   if (j->ncore > 0) {
     enqueue_update(j, 4, 1);
     Timed tm(ctx, KK_INTEGRAL);
-    hipLaunchKernelGGL(k_integral, dim3(count), dim3(kIntBlock), 0, ctx->stream, j->ddesc, 1);
+    if (j->dd)
+      hipLaunchKernelGGL(k_integral<dd>, dim3(count), dim3(kIntBlock), 0, ctx->stream, j->ddesc, 1);
+    else
+      hipLaunchKernelGGL(k_integral<double>, dim3(count), dim3(kIntBlock), 0, ctx->stream, j->ddesc, 1);
   }
   if (hipGetLastError() != hipSuccess) return fail(TT_EDEVICE);
   std::vector<ProbState> st;
@@ -658,7 +719,8 @@ tt_status tt_job_pivot_log(tt_job* j, int32_t k, tt_pivot* log, int64_t capacity
   return TT_OK;
 }
 
-tt_status tt_job_history(tt_job* j, int32_t k, double* values, int64_t capacity, int64_t* written) {
+tt_status tt_job_history(tt_job* j, int32_t k, double* values, double* values_lo, int64_t capacity,
+                         int64_t* written) {
   if (!j || k < 0 || k >= j->nprob || !values || !written) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(j->ctx->mu);
   std::vector<ProbState> st;
@@ -666,7 +728,18 @@ tt_status tt_job_history(tt_job* j, int32_t k, double* values, int64_t capacity,
   if (s != TT_OK) return s;
   const int64_t nv = st[k].sweeps + 1;
   if (nv > capacity) return TT_EINVAL;
-  TT_HIP(hipMemcpy(values, j->hdesc[k].hist, nv * sizeof(double), hipMemcpyDeviceToHost));
+  if (j->dd) {
+    std::vector<dd> h(nv);
+    TT_HIP(hipMemcpy(h.data(), j->hdesc[k].hist, nv * sizeof(dd), hipMemcpyDeviceToHost));
+    for (int64_t q = 0; q < nv; ++q) {
+      values[q] = h[q].hi;
+      if (values_lo) values_lo[q] = h[q].lo;
+    }
+  } else {
+    TT_HIP(hipMemcpy(values, j->hdesc[k].hist, nv * sizeof(double), hipMemcpyDeviceToHost));
+    if (values_lo)
+      for (int64_t q = 0; q < nv; ++q) values_lo[q] = 0.0;
+  }
   *written = nv;
   return TT_OK;
 }
@@ -743,13 +816,25 @@ tt_status tt_job_phase_times(tt_job* j, int32_t k, int64_t* marks, int64_t capac
   return TT_OK;
 }
 
-tt_status tt_job_nodes(tt_job* j, int32_t k, double* t, double* w) {
+tt_status tt_job_nodes(tt_job* j, int32_t k, double* t, double* w, double* t_lo, double* w_lo) {
   if (!j || k < 0 || k >= j->nprob || !t || !w) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(j->ctx->mu);
   TT_HIP(hipStreamSynchronize(j->ctx->stream));
   const ProbDesc& d = j->hdesc[k];
-  TT_HIP(hipMemcpy(t, d.t, d.n * sizeof(double), hipMemcpyDeviceToHost));
-  TT_HIP(hipMemcpy(w, d.w, d.n * sizeof(double), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(t, j->gl64[k].first, d.n * sizeof(double), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(w, j->gl64[k].second, d.n * sizeof(double), hipMemcpyDeviceToHost));
+  if (t_lo || w_lo) {
+    const tt_ctx::GL& g = j->ctx->gl.at(d.n);
+    std::vector<dd> h(d.n);
+    if (t_lo) {
+      TT_HIP(hipMemcpy(h.data(), g.t2, d.n * sizeof(dd), hipMemcpyDeviceToHost));
+      for (int i = 0; i < d.n; ++i) t_lo[i] = h[i].lo;
+    }
+    if (w_lo) {
+      TT_HIP(hipMemcpy(h.data(), g.w2, d.n * sizeof(dd), hipMemcpyDeviceToHost));
+      for (int i = 0; i < d.n; ++i) w_lo[i] = h[i].lo;
+    }
+  }
   return TT_OK;
 }
 
@@ -770,14 +855,16 @@ void tt_cross_free(tt_job* j) {
   delete j;
 }
 
+
 tt_status tt_eval_points(tt_ctx* ctx, const tt_problem* p, const int32_t* d_idx, int64_t npts,
                          double* d_out) {
   if (!ctx || validate(p) != TT_OK || npts < 0 || (npts > 0 && (!d_idx || !d_out))) return TT_EINVAL;
   if (npts == 0) return TT_OK;
   std::lock_guard<std::mutex> lock(ctx->mu);
   TT_HIP(hipSetDevice(ctx->device));
+  const bool use_dd = p->precision == TT_DD;
   double *t, *w;
-  tt_status s = gl_table(ctx, p->n_nodes, &t, &w);
+  tt_status s = gl_table(ctx, p->n_nodes, &t, &w, use_dd);
   if (s != TT_OK) return s;
   FamilyArgs fa;
   s = family_for(ctx, p, &fa);
@@ -786,9 +873,9 @@ tt_status tt_eval_points(tt_ctx* ctx, const tt_problem* p, const int32_t* d_idx,
   const dim3 grid((unsigned)blocks64), block(kBlock);
   Timed tm(ctx, KK_EVAL_POINTS);
   switch (bucket_m(fa.m)) {
-    case 8: hipLaunchKernelGGL(k_eval_points<8>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
-    case 16: hipLaunchKernelGGL(k_eval_points<16>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
-    default: hipLaunchKernelGGL(k_eval_points<32>, grid, block, 0, ctx->stream, fa, t, w, d_idx, npts, d_out); break;
+    case 8: eval_points_m<8>(ctx, use_dd, grid, block, fa, t, w, d_idx, npts, d_out); break;
+    case 16: eval_points_m<16>(ctx, use_dd, grid, block, fa, t, w, d_idx, npts, d_out); break;
+    default: eval_points_m<32>(ctx, use_dd, grid, block, fa, t, w, d_idx, npts, d_out); break;
   }
   TT_HIP(hipGetLastError());
   return TT_OK;
@@ -804,8 +891,9 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
   if ((pos == 0 && r_left != 1) || (pos == m - 1 && r_right != 1)) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   TT_HIP(hipSetDevice(ctx->device));
+  const bool use_dd = p->precision == TT_DD;
   double *t, *w;
-  tt_status s = gl_table(ctx, p->n_nodes, &t, &w);
+  tt_status s = gl_table(ctx, p->n_nodes, &t, &w, use_dd);
   if (s != TT_OK) return s;
   FamilyArgs fa;
   s = family_for(ctx, p, &fa);
@@ -813,23 +901,20 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
   const int64_t total = (int64_t)r_left * p->n_nodes * r_right;   // < 2^31 by the rank and node limits
   const int64_t blocks64 = std::min<int64_t>((total + kBlock - 1) / kBlock, 2048);
   const dim3 grid((unsigned)blocks64), block(kBlock);
-  const int n = p->n_nodes;
+  const int n = p->n_nodes, mb = bucket_m(m);
   Timed tm(ctx, KK_EVAL_FIBERS);
   const int fam = fam_of(p->integrand);
-#define TT_FIB(F, M)                                                                                   \
-  hipLaunchKernelGGL((k_eval_fibers<F, M>), grid, block, 0, ctx->stream, fa, n, t, w, pos, d_left, r_left, \
-                     d_right, r_right, d_out)
-#define TT_FIB_M(F)              \
-  switch (bucket_m(m)) {         \
-    case 8: TT_FIB(F, 8); break;   \
-    case 16: TT_FIB(F, 16); break; \
-    default: TT_FIB(F, 32); break; \
-  }
-  if (fam == FAM_PAPER) { TT_FIB_M(FAM_PAPER) }
-  else if (fam == FAM_UFORM) { TT_FIB_M(FAM_UFORM) }
-  else { TT_FIB_M(FAM_SYNTH) }
-#undef TT_FIB_M
-#undef TT_FIB
+  if (use_dd)
+    eval_fibers_f<dd, FAM_PAPER>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out);
+  else if (fam == FAM_PAPER)
+    eval_fibers_f<double, FAM_PAPER>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right,
+                                     d_out);
+  else if (fam == FAM_UFORM)
+    eval_fibers_f<double, FAM_UFORM>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right,
+                                     d_out);
+  else
+    eval_fibers_f<double, FAM_SYNTH>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right,
+                                     d_out);
   TT_HIP(hipGetLastError());
   return TT_OK;
 }

@@ -20,6 +20,7 @@ FAMILY_IDS = {
     "prod_exp": 21, "sum2_exp_cos": 22,
 }
 STOP_REASONS = {0: "running", 1: "converged", 2: "rank_cap", 3: "max_sweeps"}
+PRECISION_IDS = {"fp64": 0, "dd": 1}
 
 TT_OK, TT_CONVERGED, TT_NOT_CONVERGED = 0, 1, 2
 TT_EINVAL, TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC = -1, -2, -3, -4
@@ -43,7 +44,7 @@ class _Info(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("reason", ctypes.c_int32), ("err_flags", ctypes.c_int32),
                 ("evals", ctypes.c_int64), ("value", ctypes.c_double),
-                ("rel_change", ctypes.c_double)]
+                ("rel_change", ctypes.c_double), ("value_lo", ctypes.c_double)]
 
 
 class _Pivot(ctypes.Structure):
@@ -91,9 +92,9 @@ def load_library():
         "tt_cross_run": (i32, [vp, P(_Info)]),
         "tt_cross_integrate": (i32, [vp, P(dbl), P(_Info)]),
         "tt_job_pivot_log": (i32, [vp, i32, P(_Pivot), i64, P(i64)]),
-        "tt_job_history": (i32, [vp, i32, P(dbl), i64, P(i64)]),
+        "tt_job_history": (i32, [vp, i32, P(dbl), P(dbl), i64, P(i64)]),
         "tt_job_index_sets": (i32, [vp, i32, P(i32), P(i32), i64, P(i64)]),
-        "tt_job_nodes": (i32, [vp, i32, P(dbl), P(dbl)]),
+        "tt_job_nodes": (i32, [vp, i32, P(dbl), P(dbl), P(dbl), P(dbl)]),
         "tt_cross_free": (None, [vp]),
         "tt_eval_points": (i32, [vp, P(_Problem), vp, i64, vp]),
         "tt_eval_fibers": (i32, [vp, P(_Problem), i32, vp, i32, vp, i32, vp]),
@@ -130,7 +131,7 @@ def _c_problem(p: Problem, keep):
                                                    np.asarray(p.params["b"], np.float64)[:p.d]]))
         keep.append(arr)
         params = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    return _Problem(FAMILY_IDS[p.family], p.d, p.n, p.rank_cap, float(p.tol), 0,
+    return _Problem(FAMILY_IDS[p.family], p.d, p.n, p.rank_cap, float(p.tol), PRECISION_IDS[p.precision],
                     int(p.max_sweeps), int(p.seed) & ((1 << 64) - 1), params)
 
 
@@ -180,7 +181,9 @@ class Context:
         return Job(self, problems)
 
     def eval_points(self, p: Problem, idx_dev, out_dev, npts):
-        """B at npts multi-indices; idx_dev / out_dev are device pointers (ints)."""
+        """B at npts multi-indices; idx_dev / out_dev are device pointers (ints).
+
+        out_dev holds npts doubles, or 2*npts ((hi, lo) pairs) for precision "dd"."""
         keep = []
         _check(self._lib.tt_eval_points(self.handle, ctypes.byref(_c_problem(p, keep)),
                                         ctypes.c_void_p(idx_dev), npts, ctypes.c_void_p(out_dev)),
@@ -226,7 +229,8 @@ class Job:
     @staticmethod
     def _info_dicts(infos):
         return [dict(sweeps=i.sweeps, max_rank=i.max_rank, reason=STOP_REASONS.get(i.reason, i.reason),
-                     err_flags=i.err_flags, evals=i.evals, value=i.value, rel_change=i.rel_change)
+                     err_flags=i.err_flags, evals=i.evals, value=i.value, rel_change=i.rel_change,
+                     value_lo=i.value_lo)
                 for i in infos]
 
     def sweep(self, n=1):
@@ -258,12 +262,17 @@ class Job:
         return [recs[s * nb:(s + 1) * nb] for s in range(written.value // nb)] if nb else []
 
     def history(self, k):
+        return self.history_dd(k)[0]
+
+    def history_dd(self, k):
+        """(leading doubles, low doubles) of the integral after the start and every sweep."""
         p = self.problems[k]
         cap = (p.max_sweeps if p.max_sweeps > 0 else 4 * p.rank_cap) + 1
         buf = (ctypes.c_double * cap)()
+        lo = (ctypes.c_double * cap)()
         written = ctypes.c_int64()
-        _check(self._lib.tt_job_history(self.handle, k, buf, cap, ctypes.byref(written)), "tt_job_history")
-        return list(buf[:written.value])
+        _check(self._lib.tt_job_history(self.handle, k, buf, lo, cap, ctypes.byref(written)), "tt_job_history")
+        return list(buf[:written.value]), list(lo[:written.value])
 
     def index_sets(self, k):
         """[(left rows, right rows)] per bond, each a list of tuples of node indices."""
@@ -306,8 +315,12 @@ class Job:
         return arr, mhz.value
 
     def nodes(self, k):
+        """(t, w) rounded to double."""
+        return self.nodes_dd(k)[:2]
+
+    def nodes_dd(self, k):
+        """(t, w, t_lo, w_lo): the device's double-double node and weight tables."""
         n = self.problems[k].n
-        t = (ctypes.c_double * n)()
-        w = (ctypes.c_double * n)()
-        _check(self._lib.tt_job_nodes(self.handle, k, t, w), "tt_job_nodes")
-        return np.array(t[:]), np.array(w[:])
+        t, w, tl, wl = [(ctypes.c_double * n)() for _ in range(4)]
+        _check(self._lib.tt_job_nodes(self.handle, k, t, w, tl, wl), "tt_job_nodes")
+        return np.array(t[:]), np.array(w[:]), np.array(tl[:]), np.array(wl[:])

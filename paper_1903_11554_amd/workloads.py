@@ -27,6 +27,7 @@ class Problem:
     seed: int = 1
     max_sweeps: int = 0
     params: Optional[dict] = None   # synthetic: {"a": [...], "b": [...]}, d entries each
+    precision: str = "fp64"         # "fp64" or "dd" (double-double, paper-form integrands)
 
     def modes(self):
         return self.d - 1 if self.family in ("ising_c", "ising_d", "ising_e") else self.d
