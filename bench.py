@@ -206,6 +206,7 @@ def run_gpu(args):
     fib_tflops = fib_flops / (ms / nl * 1e-3) / 1e12
 
     batch = run_batch(ctx)
+    dd = run_dd(ctx)
 
     refs = reference_values()
     errs = {}
@@ -216,7 +217,41 @@ def run_gpu(args):
     ctx.close()
     return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
                 s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
-                errs=errs, probs=probs, batch=batch)
+                errs=errs, probs=probs, batch=batch, dd=dd)
+
+
+def run_dd(ctx, reps=2):
+    """D_8..D_12 in double-double (128 nodes, rank <= 64, tol 1e-21) and the same in double."""
+    import mpmath as mp
+    import torch
+
+    from paper_1903_11554_amd.workloads import Problem
+    probs = [Problem("ising_d", d, 128, 64, 1e-21, seed=d, precision="dd") for d in range(8, 13)]
+    fp = [Problem("ising_d", d, 128, 64, 1e-13, seed=d) for d in range(8, 13)]
+
+    def timed(ps):
+        t = time.perf_counter()
+        job = ctx.job(ps)
+        infos = job.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        job.free()
+        return dt, infos
+
+    timed(probs)
+    runs = [timed(probs) for _ in range(reps)]
+    t_dd, infos = min(runs, key=lambda r: r[0])
+    t_64, infos64 = timed(fp)
+    with mp.workdps(40):
+        ref = mp.mpf("1.8959911856917860437277009899220e-05")
+        e_dd = float(abs(mp.mpf(infos[0]["value"]) + mp.mpf(infos[0]["value_lo"]) - ref) / ref)
+        e_64 = float(abs(mp.mpf(infos64[0]["value"]) - ref) / ref)
+    ev = sum(i["evals"] for i in infos)
+    return {"workload": "D_8..D_12 paper form, double-double, 128 nodes, rank <= 64, tol 1e-21, one job",
+            "ms_per_job": t_dd * 1e3, "integrals_per_s": len(probs) / t_dd, "dd_evals_per_s": ev / t_dd,
+            "sweeps": max(i["sweeps"] for i in infos), "max_rank": max(i["max_rank"] for i in infos),
+            "d8_rel_err_vs_printed": e_dd,
+            "fp64_same_config": {"tol": 1e-13, "ms_per_job": t_64 * 1e3, "d8_rel_err_vs_printed": e_64}}
 
 
 def run_batch(ctx, reps=5):
@@ -360,6 +395,7 @@ def main():
                                  "evals_per_s": npts / (ms / nl * 1e-3),
                                  "workload": "D_10 (9 modes) fibre set 64 x 256 x 64 at mode 4"},
         "batch_mixed64": r["batch"],
+        "precision_dd": r["dd"],
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(r["probs"], args.cpu_budget)
