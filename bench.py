@@ -207,6 +207,7 @@ def run_gpu(args):
 
     batch = run_batch(ctx)
     dd = run_dd(ctx)
+    serving = run_serving(ctx, args.serve_seconds)
 
     refs = reference_values()
     errs = {}
@@ -217,7 +218,72 @@ def run_gpu(args):
     ctx.close()
     return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
                 s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
-                errs=errs, probs=probs, batch=batch, dd=dd)
+                errs=errs, probs=probs, batch=batch, dd=dd, serving=serving)
+
+
+def run_serving(ctx, seconds, warm_s=1.0, plain_sample=100):
+    """Poisson stream of single-integral requests through the serving loop (continuous batching).
+
+    The trace (200 requests/s; C_d, D_d, rank-2 exp/cos with d ~ U{4..32}, tol
+    log-uniform in [1e-12, 1e-6], rank cap ~ U{16..64}, 64 nodes) is submitted at
+    its arrival times; latency is submission to completion as the server
+    measures it, over the requests arriving after the first warm_s seconds.
+    Beside it: the same requests solved one job at a time (the plain sweep),
+    and the whole trace submitted at once (the server's capacity).
+    """
+    import torch
+
+    from paper_1903_11554_amd.workloads import serving_trace
+    trace = serving_trace(duration_s=warm_s + seconds, rate=200.0, seed=5)
+    srv = ctx.server(max_bytes=32 << 30, max_active=1024)
+    t0 = time.perf_counter()
+    tickets = []
+    for at, p in trace:
+        while time.perf_counter() - t0 < at:
+            time.sleep(0.0002)
+        tickets.append((at, srv.submit(p)))
+    res = [(at, srv.wait(t)) for at, t in tickets]
+    t_end = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lats = sorted(r[1] for at, r in res if at >= warm_s)
+    n_meas = len(lats)
+    first = next(at for at, _ in res if at >= warm_s)
+
+    def pct(q):
+        return lats[min(len(lats) - 1, int(math.ceil(q * len(lats))) - 1)] * 1e3
+
+    # plain: one job per request, back to back
+    sample = [p for _, p in trace[:plain_sample]]
+    for p in sample[:5]:
+        j = ctx.job([p])
+        j.run()
+        j.free()
+    tp = time.perf_counter()
+    for p in sample:
+        j = ctx.job([p])
+        j.run()
+        j.free()
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - tp) / len(sample)
+    # capacity: everything submitted at once
+    srv = ctx.server(max_bytes=32 << 30, max_active=1024)
+    tb = time.perf_counter()
+    ts = [srv.submit(p) for _, p in trace]
+    for t in ts:
+        srv.wait(t)
+    burst_s = time.perf_counter() - tb
+    srv.close()
+    return {"workload": f"Poisson stream, 200 requests/s for {seconds:.0f} s after {warm_s:.0f} s warm-up "
+                        "({} requests); C_d, D_d, rank-2 exp/cos, d ~ U{{4..32}}, tol log-uniform "
+                        "[1e-12, 1e-6], rank cap ~ U{{16..64}}, 64 nodes".format(len(trace)),
+            "requests_measured": n_meas, "latency_ms_p50": pct(0.5), "latency_ms_p99": pct(0.99),
+            "integrals_per_s": n_meas / max(t_end - first, 1e-9),
+            "max_running": st["max_running"], "sweep_launches": st["sweep_launches"],
+            "admissions": st["admissions"],
+            "plain_ms_per_integral": plain_s * 1e3, "plain_integrals_per_s": 1.0 / plain_s,
+            "burst_integrals_per_s": len(trace) / burst_s,
+            "burst_vs_plain": (len(trace) / burst_s) * plain_s}
 
 
 def run_dd(ctx, reps=2):
@@ -343,6 +409,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="measured length of the serving stream (after a 1 s warm-up)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (yardstick for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -396,6 +464,7 @@ def main():
                                  "workload": "D_10 (9 modes) fibre set 64 x 256 x 64 at mode 4"},
         "batch_mixed64": r["batch"],
         "precision_dd": r["dd"],
+        "serving": r["serving"],
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(r["probs"], args.cpu_budget)

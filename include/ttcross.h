@@ -40,6 +40,7 @@ typedef enum {
   TT_OK = 0,
   TT_CONVERGED = 1,      /* every integral of the job met its stopping rule            */
   TT_NOT_CONVERGED = 2,  /* work remains (more sweeps needed)                          */
+  TT_PENDING = 3,        /* a served request has not finished yet                      */
   TT_EINVAL = -1,        /* invalid argument (see each function)                       */
   TT_ENOMEM = -2,        /* device allocation failed or footprint over the limit       */
   TT_EDEVICE = -3,       /* a HIP runtime call failed                                  */
@@ -198,12 +199,50 @@ tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, doubl
  * superblock, 16 wall-clock marks (0 start, 1 sets staged, 2 samples done,
  * 3 rook pivoting done, 4 search done, 5 core updates done, 6 quadrature done,
  * 7 end, then inside the workgroup's last core update: 8 hand-over done,
- * 9 sets staged, 10 new entries evaluated, 11 cross factorised, 12 interpolation
- * core solved, 13 core summed; 0 where the workgroup skipped a phase), in ticks
+ * 9 pivots appended and sets staged, 10 new entries evaluated, 11 new rows of
+ * the interpolation core solved, 12 cross LU bordered, 13 rank-1 update done,
+ * 14 core summed; 0 where the workgroup skipped a phase), in ticks
  * of *clock_mhz MHz.  marks is a host buffer of `capacity` int64;
  * sweeps x (m-1) x 16 values are written. */
 tt_status tt_job_phase_times(tt_job *job, int32_t k, int64_t *marks, int64_t capacity, int64_t *written,
                              double *clock_mhz);
+
+/* ---- Serving loop (continuous batching) --------------------------------------
+ * For callers that submit integrals one at a time, as they arrive.  A server
+ * owns a worker thread, one device arena of max_bytes and up to max_active
+ * running integrals.  tt_server_submit queues one problem (any host thread)
+ * and returns a ticket.  The worker admits queued problems in arrival order
+ * while the arena has room for their footprint (tt_job_footprint) and fewer
+ * than max_active run, initialises them, and launches sweeps in which every
+ * running integral advances by one sweep of Alg. 6: one launch serves all of
+ * them, whatever their d, tolerance, rank cap or age.  An integral that stops
+ * leaves the running set at once and its memory and slot go to the next
+ * request; the kernels publish its result to pinned host memory, so the loop
+ * never waits for the device except to bound the sweeps in flight.  Every
+ * result is bitwise the one tt_cross_run gives for the same problem alone.
+ * Double precision only (TT_FP64).
+ * tt_server_submit: TT_EINVAL (invalid problem, TT_DD), TT_ENOMEM (footprint
+ *   above max_bytes: it could never be admitted).
+ * tt_server_poll: TT_PENDING until the result exists, then TT_OK with info and
+ *   the time from submission to completion in seconds (latency_s may be NULL);
+ *   the ticket is then released.  TT_EINVAL for an unknown ticket.
+ * tt_server_wait: as poll, blocking until the result exists.
+ * tt_server_destroy: lets running integrals finish, drops queued ones. */
+typedef struct tt_server tt_server;
+typedef struct {
+  int64_t submitted, completed;   /* requests so far                                         */
+  int64_t queued, running;        /* now                                                     */
+  int64_t max_running;            /* largest running set seen                                */
+  int64_t sweep_launches;         /* sweep kernels launched                                  */
+  int64_t admissions;             /* admission rounds (each initialises one group of requests) */
+  double  busy_s;                 /* wall time with at least one integral running            */
+} tt_server_stats;
+tt_status tt_server_create(tt_ctx *ctx, size_t max_bytes, int32_t max_active, tt_server **out);
+tt_status tt_server_submit(tt_server *server, const tt_problem *problem, uint64_t *ticket);
+tt_status tt_server_poll(tt_server *server, uint64_t ticket, tt_info *info, double *latency_s);
+tt_status tt_server_wait(tt_server *server, uint64_t ticket, tt_info *info, double *latency_s);
+tt_status tt_server_get_stats(tt_server *server, tt_server_stats *out);
+void tt_server_destroy(tt_server *server);
 
 /* Synchronise the context stream. */
 tt_status tt_ctx_synchronize(tt_ctx *ctx);

@@ -6,8 +6,8 @@ step of the method runs in the library's kernels.  Importing this package does
 not need a GPU; creating a context does, and fails loudly without one or
 without the built library.
 """
-from .ttcross import (Context, Job, Problem, TTError, FAMILY_IDS, STOP_REASONS,  # noqa: F401
+from .ttcross import (Context, Job, Problem, Server, TTError, FAMILY_IDS, STOP_REASONS,  # noqa: F401
                       library_path, load_library)
 
-__all__ = ["Context", "Job", "Problem", "TTError", "FAMILY_IDS", "STOP_REASONS",
+__all__ = ["Context", "Job", "Problem", "Server", "TTError", "FAMILY_IDS", "STOP_REASONS",
            "library_path", "load_library"]

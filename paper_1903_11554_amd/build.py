@@ -1,6 +1,7 @@
 """Build the gfx950 HIP library in-tree (hipcc, no JIT cache).
 
-The library is the host translation unit ``csrc/ttcross.hip`` plus one kernel
+The library is the host translation units ``csrc/ttcross.hip`` (job API) and
+``csrc/tt_server.hip`` (serving loop) plus one kernel
 translation unit per integrand class (``csrc/tt_inst.hip`` compiled with
 -DTT_FAM=0..3, and once more with -DTT_INST_DD=1 for the double-double kernels of
 the paper-form class), compiled in parallel for gfx950 only, with floating-point
@@ -25,7 +26,7 @@ FLAGS = [
     "-Wno-unused-result", "-Wno-unused-value", "-Wno-pass-failed",
 ]
 
-UNITS = [("ttcross.hip", [], "ttcross.o")] + [
+UNITS = [("ttcross.hip", [], "ttcross.o"), ("tt_server.hip", [], "tt_server.o")] + [
     ("tt_inst.hip", [f"-DTT_FAM={f}"], f"tt_inst_{f}.o") for f in range(4)] + [
     ("tt_inst.hip", ["-DTT_FAM=0", "-DTT_INST_DD=1"], "tt_inst_dd.o")]
 

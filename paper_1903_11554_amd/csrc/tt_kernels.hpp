@@ -65,6 +65,7 @@ struct ProbDesc {
   int32_t *start;                        // [m] start multi-index
   int32_t *sync;                         // [m+1] per-sweep dataflow counters (cores ready, cores done)
   int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
+  ProbState *st_host;                    // pinned host copy of the final state (may be null)
   long long *phase;                      // [max_sweeps][nbonds][kPhases] wall-clock marks, or null
   ProbState *st;
 };
@@ -81,8 +82,25 @@ __device__ __forceinline__ void mark(const ProbDesc& p, int sweep, int b, int sl
 }
 
 // Mirror "this integral has stopped" into pinned host memory so the host can
-// stop queueing sweeps without copying the device state back.
+// stop queueing sweeps (and read the result) without copying device state
+// back: the final state first, then a system-scope fence, then the flag.
+// Called by one thread, after every field of the state has its final value.
 __device__ __forceinline__ void signal_done(const ProbDesc& p) {
+  if (p.st_host) {
+    const volatile ProbState* src = p.st;
+    volatile ProbState* dst = p.st_host;
+    dst->sweeps = src->sweeps;
+    dst->done = src->done;
+    dst->reason = src->reason;
+    dst->err_flags = src->err_flags;
+    dst->nacc = src->nacc;
+    dst->max_rank = src->max_rank;
+    dst->evals = src->evals;
+    dst->value = src->value;
+    dst->rel = src->rel;
+    dst->value_lo = src->value_lo;
+    __threadfence_system();
+  }
   if (p.done_host) {
     __hip_atomic_store(p.done_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __threadfence_system();
@@ -232,6 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       st->evals = (m == 1) ? (unsigned long long)n : 0ull;
       st->err_flags = isfinite(n_hi(val)) ? 0 : 1;
       st->max_rank = 1;
+      signal_done(p);
     }
     return;
   }
@@ -271,6 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       st->value = 0.0;
       st->value_lo = 0.0;
       st->rel = __builtin_huge_val();
+      signal_done(p);
     }
     return;
   }

@@ -12,54 +12,10 @@
 #include <new>
 #include <vector>
 
-#include "tt_kernels.hpp"
-#include "tt_launch.hpp"
+#include "tt_host.hpp"
 
 using namespace ttx;
-
-#define TT_HIP(call)                                    \
-  do {                                                  \
-    hipError_t e_ = (call);                             \
-    if (e_ != hipSuccess) {                             \
-      last_hip_error() = e_;                            \
-      return TT_EDEVICE;                                \
-    }                                                   \
-  } while (0)
-
-static hipError_t& last_hip_error() {
-  static thread_local hipError_t e = hipSuccess;
-  return e;
-}
-
-// kernel kinds timed by the optional event profiler
-enum { KK_SWEEP = 0, KK_UPDATE = 1, KK_INTEGRAL = 2, KK_START = 3, KK_GL = 4, KK_EVAL_POINTS = 5,
-       KK_EVAL_FIBERS = 6, KK_COUNT = 7 };
-
-struct tt_ctx {
-  int device = 0;
-  bool profiling = false;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;   // kind, (start, stop)
-  std::vector<hipEvent_t> pool;
-  double kernel_ms[KK_COUNT] = {0};
-  long long kernel_launches[KK_COUNT] = {0};
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::mutex mu;
-  struct GL {
-    double *t, *w;     // nodes and weights rounded to double
-    dd *t2, *w2;       // the same in double-double
-  };
-  std::map<int, GL> gl;                            // n -> device tables
-  double* params = nullptr;                        // device scratch for synthetic params
-  size_t params_cap = 0;
-  std::multimap<size_t, void*> arenas;             // freed job arenas kept for reuse
-  size_t arena_bytes_cached = 0;
-};
-
-// Arenas of freed jobs are kept by the context (up to this many bytes) and
-// handed to later jobs of the same or smaller size, so a stream of jobs does
-// not call hipMalloc/hipFree every time.
-static const size_t kArenaCacheBytes = size_t(4) << 30;
+using namespace ttx_host;
 
 struct tt_job {
   tt_ctx* ctx = nullptr;
@@ -86,153 +42,32 @@ struct tt_job {
   std::vector<hipEvent_t> ring;            // one event per queued sweep (tt_cross_run)
 };
 
-namespace {
-
-// Bracket one kernel launch with a pair of events on the context stream.
-struct Timed {
-  tt_ctx* c;
-  int kind;
-  hipEvent_t a = nullptr, b = nullptr;
-  hipEvent_t take() {
-    hipEvent_t e = nullptr;
-    if (!c->pool.empty()) {
-      e = c->pool.back();
-      c->pool.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-      e = nullptr;
+namespace ttx_host {
+// Node tables for n, generated on first use.  With want_dd the returned
+// pointers are the double-double tables (reinterpreted as double*).
+tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd) {
+  auto it = ctx->gl.find(n);
+  if (it == ctx->gl.end()) {
+    tt_ctx::GL g{nullptr, nullptr, nullptr, nullptr};
+    TT_HIP(hipMalloc(&g.t, n * sizeof(double)));
+    TT_HIP(hipMalloc(&g.w, n * sizeof(double)));
+    TT_HIP(hipMalloc(&g.t2, n * sizeof(dd)));
+    TT_HIP(hipMalloc(&g.w2, n * sizeof(dd)));
+    {
+      Timed tm(ctx, KK_GL);
+      hipLaunchKernelGGL(k_gl, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, g.t, g.w, g.t2, g.w2);
     }
-    return e;
+    TT_HIP(hipGetLastError());
+    it = ctx->gl.emplace(n, g).first;
   }
-  Timed(tt_ctx* ctx, int k) : c(ctx), kind(k) {
-    if (c->profiling) {
-      a = take();
-      b = take();
-      if (a && b) (void)hipEventRecord(a, c->stream);
-    }
-  }
-  ~Timed() {
-    if (c->profiling && a && b) {
-      (void)hipEventRecord(b, c->stream);
-      c->pending.push_back({kind, {a, b}});
-    }
-  }
-};
-
-void drain_profile(tt_ctx* c) {
-  if (c->pending.empty()) return;
-  (void)hipStreamSynchronize(c->stream);
-  for (auto& pe : c->pending) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
-      c->kernel_ms[pe.first] += ms;
-      c->kernel_launches[pe.first] += 1;
-    }
-    c->pool.push_back(pe.second.first);
-    c->pool.push_back(pe.second.second);
-  }
-  c->pending.clear();
-}
-
-int modes_of(const tt_problem& p) {
-  switch (p.integrand) {
-    case TT_ISING_C: case TT_ISING_D: case TT_ISING_E: return p.d - 1;
-    case TT_ISING_C_U: case TT_ISING_D_U: case TT_PROD_EXP: case TT_SUM2_EXP_COS: return p.d;
-    default: return -1;
-  }
-}
-
-bool is_synthetic(int f) { return f == TT_PROD_EXP || f == TT_SUM2_EXP_COS; }
-
-int fam_of(int f) {
-  if (f == TT_ISING_C || f == TT_ISING_D || f == TT_ISING_E) return FAM_PAPER;
-  if (f == TT_ISING_C_U || f == TT_ISING_D_U) return FAM_UFORM;
-  return FAM_SYNTH;
-}
-
-tt_status validate(const tt_problem* p) {
-  if (!p) return TT_EINVAL;
-  const int m = modes_of(*p);
-  if (m < 0 || p->d < 1 || m > TT_MAX_MODES) return TT_EINVAL;
-  if (p->n_nodes < 1 || p->n_nodes > TT_MAX_NODES) return TT_EINVAL;
-  if (p->rank_cap < 1 || p->rank_cap > TT_MAX_RANK) return TT_EINVAL;
-  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return TT_EINVAL;
-  if (p->precision != TT_FP64 && p->precision != TT_DD) return TT_EINVAL;
-  if (p->precision == TT_DD && fam_of(p->integrand) != FAM_PAPER) return TT_EINVAL;
-  if (p->max_sweeps < 0 || p->max_sweeps > 1024) return TT_EINVAL;
-  if (is_synthetic(p->integrand) && !p->params) return TT_EINVAL;
-  // the superblock size r n n r must fit a 32-bit sample index
-  const double sb = (double)p->rank_cap * p->n_nodes * p->n_nodes * p->rank_cap;
-  if (sb >= 4294967296.0) return TT_EINVAL;
+  *t = want_dd ? reinterpret_cast<double*>(it->second.t2) : it->second.t;
+  *w = want_dd ? reinterpret_cast<double*>(it->second.w2) : it->second.w;
   return TT_OK;
 }
 
-int max_sweeps_of(const tt_problem& p) { return p.max_sweeps > 0 ? p.max_sweeps : 4 * p.rank_cap; }
+}  // namespace ttx_host
 
-// byte layout of one problem inside a job arena
-struct Layout {
-  size_t off = 0;
-  size_t take(size_t bytes) {
-    size_t o = (off + 255) & ~size_t(255);
-    off = o + bytes;
-    return o;
-  }
-};
-
-struct ProbOffsets {
-  size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, LU, S, rank, piv, scale, log, hist, start, sync,
-      phase;
-  std::vector<int64_t> foff, coff;
-};
-
-ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
-  ProbOffsets o;
-  const int m = modes_of(p), n = p.n_nodes, R = p.rank_cap;
-  const int nb = m > 1 ? m - 1 : 0;
-  const int ms = max_sweeps_of(p);
-  // D: bytes of one value of the job's number type; plain doubles use sizeof(double)
-  const size_t D = p.precision == TT_DD ? sizeof(dd) : sizeof(double), I = sizeof(int32_t);
-  o.Lpar = L.take((size_t)nb * R * I);
-  o.Lnode = L.take((size_t)nb * R * I);
-  o.Rpar = L.take((size_t)nb * R * I);
-  o.Rnode = L.take((size_t)nb * R * I);
-  o.Lx = L.take((size_t)nb * R * m * D);
-  o.Rx = L.take((size_t)nb * R * m * D);
-  o.Lw = L.take((size_t)nb * R * D);
-  o.Rw = L.take((size_t)nb * R * D);
-  int64_t fsz = 0, csz = 0;
-  for (int c = 0; c < m; ++c) {
-    const int rc = c == 0 ? 1 : R, cc = c == m - 1 ? 1 : R;
-    o.foff.push_back(fsz);
-    fsz += (int64_t)rc * n * cc;
-  }
-  for (int b = 0; b < nb; ++b) {
-    const int rc = b == 0 ? 1 : R;
-    o.coff.push_back(csz);
-    csz += (int64_t)R * rc * n;
-  }
-  o.F = L.take((size_t)fsz * D);
-  o.C = L.take((size_t)csz * D);
-  o.LU = L.take((size_t)(nb > 0 ? nb : 1) * R * R * D);
-  o.S = L.take((size_t)(m > 0 ? m : 1) * R * R * D);
-  o.rank = L.take((size_t)(nb > 0 ? nb : 1) * I);
-  o.piv = L.take((size_t)(nb > 0 ? nb : 1) * sizeof(PivRec));
-  o.scale = L.take((size_t)(nb > 0 ? nb : 1) * sizeof(double));
-  o.log = L.take((size_t)ms * (nb > 0 ? nb : 1) * sizeof(PivRec));
-  o.hist = L.take((size_t)(ms + 1) * D);
-  o.start = L.take((size_t)(m > 0 ? m : 1) * I);
-  o.sync = L.take((size_t)(m + 1) * I);
-  o.phase = L.take((size_t)ms * (nb > 0 ? nb : 1) * kPhases * sizeof(long long));
-  return o;
-}
-
-int bucket_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : 32; }
-int bucket_r(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : 64; }
-
-double four_over_fact(int m) {
-  double f = 1.0;
-  for (int k = 2; k <= m; ++k) f *= k;
-  return 4.0 / f;
-}
+namespace {
 
 void launch(tt_job* j, int what, int rb) {
   LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, bucket_m(j->maxm), j->ctx->stream};
@@ -269,63 +104,6 @@ tt_status read_states(tt_job* j, std::vector<ProbState>& st) {
   return TT_OK;
 }
 
-void fill_info(const ProbState& s, tt_info* out) {
-  out->sweeps = s.sweeps;
-  out->max_rank = s.max_rank;
-  out->reason = s.done ? s.reason : TT_RUNNING;
-  out->err_flags = s.err_flags;
-  out->evals = (int64_t)s.evals;
-  out->value = s.value;
-  out->rel_change = s.rel;
-  out->value_lo = s.value_lo;
-}
-
-// Node tables for n, generated on first use.  With want_dd the returned
-// pointers are the double-double tables (reinterpreted as double*).
-tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd = false) {
-  auto it = ctx->gl.find(n);
-  if (it == ctx->gl.end()) {
-    tt_ctx::GL g{nullptr, nullptr, nullptr, nullptr};
-    TT_HIP(hipMalloc(&g.t, n * sizeof(double)));
-    TT_HIP(hipMalloc(&g.w, n * sizeof(double)));
-    TT_HIP(hipMalloc(&g.t2, n * sizeof(dd)));
-    TT_HIP(hipMalloc(&g.w2, n * sizeof(dd)));
-    {
-      Timed tm(ctx, KK_GL);
-      hipLaunchKernelGGL(k_gl, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, g.t, g.w, g.t2, g.w2);
-    }
-    TT_HIP(hipGetLastError());
-    it = ctx->gl.emplace(n, g).first;
-  }
-  *t = want_dd ? reinterpret_cast<double*>(it->second.t2) : it->second.t;
-  *w = want_dd ? reinterpret_cast<double*>(it->second.w2) : it->second.w;
-  return TT_OK;
-}
-
-tt_status family_for(tt_ctx* ctx, const tt_problem* p, FamilyArgs* fa) {
-  const int m = modes_of(*p);
-  fa->family = p->integrand;
-  fa->m = m;
-  fa->four_over_mfact = four_over_fact(m);
-  fa->a = fa->b = nullptr;
-  if (is_synthetic(p->integrand)) {
-    const size_t need = 2 * (size_t)m * sizeof(double);
-    if (need > ctx->params_cap) {
-      TT_HIP(hipStreamSynchronize(ctx->stream));
-      if (ctx->params) TT_HIP(hipFree(ctx->params));
-      ctx->params = nullptr;
-      ctx->params_cap = 0;
-      TT_HIP(hipMalloc(&ctx->params, need));
-      ctx->params_cap = need;
-    }
-    // synchronous copy: earlier kernels may still read the old parameters
-    TT_HIP(hipStreamSynchronize(ctx->stream));
-    TT_HIP(hipMemcpy(ctx->params, p->params, need, hipMemcpyHostToDevice));
-    fa->a = ctx->params;
-    fa->b = ctx->params + m;
-  }
-  return TT_OK;
-}
 
 }  // namespace
 
@@ -370,6 +148,7 @@ const char* tt_status_string(tt_status s) {
     case TT_OK: return "TT_OK";
     case TT_CONVERGED: return "TT_CONVERGED";
     case TT_NOT_CONVERGED: return "TT_NOT_CONVERGED";
+    case TT_PENDING: return "TT_PENDING";
     case TT_EINVAL: return "TT_EINVAL: invalid argument";
     case TT_ENOMEM: return "TT_ENOMEM: out of device memory";
     case TT_EDEVICE: return "TT_EDEVICE: HIP runtime error";
@@ -503,14 +282,11 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   const size_t bond_off = L.take(sizeof(int2) * (bond_tasks.size() + 1));
   const size_t core_off = L.take(sizeof(int2) * (core_tasks.size() + 1));
   std::vector<ProbOffsets> offs;
-  std::vector<size_t> foff_at(count), coff_at(count), par_at(count);
+  std::vector<ProbTables> tabs;
   for (int k = 0; k < count; ++k) {
     Layout pl;
     offs.push_back(layout_problem(problems[k], pl));
-    const int m = modes_of(problems[k]);
-    foff_at[k] = L.take(sizeof(int64_t) * std::max(m, 1));
-    coff_at[k] = L.take(sizeof(int64_t) * std::max(m - 1, 1));
-    par_at[k] = L.take(sizeof(double) * 2 * std::max(m, 1));
+    tabs.push_back(take_tables(problems[k], L));
   }
   const size_t table_bytes = L.take(0);
   std::vector<size_t> bases;
@@ -552,54 +328,9 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   for (int k = 0; k < count; ++k) j->done_host[k] = 0;
   for (int k = 0; k < count; ++k) {
     const tt_problem& p = problems[k];
-    const ProbOffsets& o = offs[k];
-    char* pb = base + bases[k];
-    ProbDesc d;
-    std::memset(&d, 0, sizeof(d));
-    d.family = p.integrand;
-    d.m = modes_of(p);
-    d.n = p.n_nodes;
-    d.R = p.rank_cap;
-    d.max_sweeps = max_sweeps_of(p);
-    d.nbonds = d.m > 1 ? d.m - 1 : 0;
-    d.tol = p.tol;
-    d.four_over_mfact = four_over_fact(d.m);
-    d.seed = p.seed;
-    d.t = gl[k].first;
-    d.w = gl[k].second;
-    d.pa = (double*)(base + par_at[k]);
-    d.pb = d.pa + std::max(d.m, 1);
-    d.Lpar = (int32_t*)(pb + o.Lpar);
-    d.Lnode = (int32_t*)(pb + o.Lnode);
-    d.Rpar = (int32_t*)(pb + o.Rpar);
-    d.Rnode = (int32_t*)(pb + o.Rnode);
-    d.Lx = (double*)(pb + o.Lx);
-    d.Rx = (double*)(pb + o.Rx);
-    d.Lw = (double*)(pb + o.Lw);
-    d.Rw = (double*)(pb + o.Rw);
-    d.F = (double*)(pb + o.F);
-    d.Foff = (int64_t*)(base + foff_at[k]);
-    d.C = (double*)(pb + o.C);
-    d.LU = (double*)(pb + o.LU);
-    d.Coff = (int64_t*)(base + coff_at[k]);
-    d.S = (double*)(pb + o.S);
-    d.rank = (int32_t*)(pb + o.rank);
-    d.piv = (PivRec*)(pb + o.piv);
-    d.scale = (double*)(pb + o.scale);
-    d.log = (PivRec*)(pb + o.log);
-    d.hist = (double*)(pb + o.hist);
-    d.start = (int32_t*)(pb + o.start);
-    d.sync = (int32_t*)(pb + o.sync);
-    d.done_host = j->done_host + k;
-    d.phase = ctx->profiling ? (long long*)(pb + o.phase) : nullptr;
-    d.st = j->dstate + k;
-    j->hdesc.push_back(d);
-    if (!o.foff.empty()) std::memcpy(img + foff_at[k], o.foff.data(), o.foff.size() * sizeof(int64_t));
-    if (!o.coff.empty()) std::memcpy(img + coff_at[k], o.coff.data(), o.coff.size() * sizeof(int64_t));
-    if (is_synthetic(p.integrand)) {
-      std::memcpy(img + par_at[k], p.params, d.m * sizeof(double));
-      std::memcpy(img + par_at[k] + std::max(d.m, 1) * sizeof(double), p.params + d.m, d.m * sizeof(double));
-    }
+    j->hdesc.push_back(make_desc(p, offs[k], base + bases[k], base, tabs[k], gl[k].first, gl[k].second,
+                                 j->done_host + k, j->dstate + k, nullptr, ctx->profiling));
+    write_tables(p, offs[k], tabs[k], img);
   }
   std::memcpy(img + desc_off, j->hdesc.data(), sizeof(ProbDesc) * count);
   if (!bond_tasks.empty()) std::memcpy(img + bond_off, bond_tasks.data(), sizeof(int2) * bond_tasks.size());

@@ -22,7 +22,7 @@ FAMILY_IDS = {
 STOP_REASONS = {0: "running", 1: "converged", 2: "rank_cap", 3: "max_sweeps"}
 PRECISION_IDS = {"fp64": 0, "dd": 1}
 
-TT_OK, TT_CONVERGED, TT_NOT_CONVERGED = 0, 1, 2
+TT_OK, TT_CONVERGED, TT_NOT_CONVERGED, TT_PENDING = 0, 1, 2, 3
 TT_EINVAL, TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC = -1, -2, -3, -4
 
 
@@ -47,6 +47,13 @@ class _Info(ctypes.Structure):
                 ("rel_change", ctypes.c_double), ("value_lo", ctypes.c_double)]
 
 
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("max_running", ctypes.c_int64), ("sweep_launches", ctypes.c_int64),
+                ("admissions", ctypes.c_int64), ("busy_s", ctypes.c_double)]
+
+
 class _Pivot(ctypes.Structure):
     _fields_ = [("row", ctypes.c_int32), ("col", ctypes.c_int32),
                 ("accepted", ctypes.c_int32), ("iters", ctypes.c_int32),
@@ -59,6 +66,8 @@ EXPORTS = [
     "tt_job_pivot_log", "tt_job_history", "tt_job_index_sets", "tt_job_nodes",
     "tt_cross_free", "tt_eval_points", "tt_eval_fibers", "tt_status_string",
     "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
+    "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
+    "tt_server_get_stats", "tt_server_destroy",
 ]
 
 KERNEL_KINDS = {"sweep": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
@@ -102,6 +111,12 @@ def load_library():
         "tt_ctx_profile": (i32, [vp, i32]),
         "tt_ctx_kernel_time": (i32, [vp, i32, P(i64), P(dbl)]),
         "tt_job_phase_times": (i32, [vp, i32, P(i64), i64, P(i64), P(dbl)]),
+        "tt_server_create": (i32, [vp, ctypes.c_size_t, i32, P(vp)]),
+        "tt_server_submit": (i32, [vp, P(_Problem), P(ctypes.c_uint64)]),
+        "tt_server_poll": (i32, [vp, ctypes.c_uint64, P(_Info), P(dbl)]),
+        "tt_server_wait": (i32, [vp, ctypes.c_uint64, P(_Info), P(dbl)]),
+        "tt_server_get_stats": (i32, [vp, P(_ServerStats)]),
+        "tt_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -179,6 +194,9 @@ class Context:
 
     def job(self, problems):
         return Job(self, problems)
+
+    def server(self, max_bytes=1 << 30, max_active=256):
+        return Server(self, max_bytes, max_active)
 
     def eval_points(self, p: Problem, idx_dev, out_dev, npts):
         """B at npts multi-indices; idx_dev / out_dev are device pointers (ints).
@@ -324,3 +342,52 @@ class Job:
         t, w, tl, wl = [(ctypes.c_double * n)() for _ in range(4)]
         _check(self._lib.tt_job_nodes(self.handle, k, t, w, tl, wl), "tt_job_nodes")
         return np.array(t[:]), np.array(w[:]), np.array(tl[:]), np.array(wl[:])
+
+
+class Server:
+    """Continuous-batching serving loop (tt_server_*): submit integrals as they arrive."""
+
+    def __init__(self, ctx: Context, max_bytes=1 << 30, max_active=256):
+        self.ctx, self._lib = ctx, ctx._lib
+        handle = ctypes.c_void_p()
+        _check(self._lib.tt_server_create(ctx.handle, max_bytes, max_active, ctypes.byref(handle)),
+               "tt_server_create")
+        self.handle = handle
+
+    def submit(self, p: Problem):
+        keep = []
+        t = ctypes.c_uint64()
+        _check(self._lib.tt_server_submit(self.handle, ctypes.byref(_c_problem(p, keep)), ctypes.byref(t)),
+               "tt_server_submit")
+        return t.value
+
+    def _result(self, fn, ticket):
+        info = _Info()
+        lat = ctypes.c_double()
+        st = _check(fn(self.handle, ticket, ctypes.byref(info), ctypes.byref(lat)), "tt_server result")
+        if st == TT_PENDING:
+            return None
+        return Job._info_dicts([info])[0], lat.value
+
+    def poll(self, ticket):
+        """(info, latency_s) once done, else None."""
+        return self._result(self._lib.tt_server_poll, ticket)
+
+    def wait(self, ticket):
+        return self._result(self._lib.tt_server_wait, ticket)
+
+    def stats(self):
+        st = _ServerStats()
+        _check(self._lib.tt_server_get_stats(self.handle, ctypes.byref(st)), "tt_server_get_stats")
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            self._lib.tt_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass

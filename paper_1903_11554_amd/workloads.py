@@ -89,3 +89,27 @@ def config_batch(count=64, seed=4):
             d = int(g.integers(4, 17))
             probs.append(Problem(fam, d, 64, 48, 1e-10, seed=1000 + k))
     return probs
+
+
+def serving_trace(duration_s=30.0, rate=200.0, seed=5, n=64):
+    """Poisson arrivals of single-integral requests: [(arrival time in s, Problem)].
+
+    Families as in the mixed batch (C_d, D_d paper form, rank-2 exp/cos
+    products) with d ~ U{4..32}, tolerance log-uniform in [1e-12, 1e-6], rank
+    cap ~ U{16..64}, n nodes; inter-arrival times exponential with the given
+    rate (seeded numpy PCG64).
+    """
+    g = np.random.default_rng(seed)
+    out, t, k = [], 0.0, 0
+    while True:
+        t += float(g.exponential(1.0 / rate))
+        if t >= duration_s:
+            break
+        fam = ["ising_c", "ising_d", "sum2_exp_cos"][int(g.integers(0, 3))]
+        d = int(g.integers(4, 33))
+        tol = float(10.0 ** g.uniform(-12, -6))
+        rank = int(g.integers(16, 65))
+        params = synthetic_params(d, 50000 + k) if fam == "sum2_exp_cos" else None
+        out.append((t, Problem(fam, d, n, rank, tol, seed=10000 + k, params=params)))
+        k += 1
+    return out
