@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # what the same counters read for a 1 GiB device copy (FETCH 2.0, WRITE 1.0).
 # Valid only for the kernel sources they were taken on (hash below); for any
 # other source the traffic is reported as null.
-SWEEP_TRAFFIC = {"source_hash": "52e6d5d5e1955bf1", "fetch_kib": 2745.5, "fetch_scale": 2.0,
-                 "write_kib": 1644.2, "write_scale": 1.0}
+SWEEP_TRAFFIC = {"source_hash": "74fdf4c8c2c63fce", "fetch_kib": 2737.4, "fetch_scale": 2.0,
+                 "write_kib": 1645.9, "write_scale": 1.0}
 KERNEL_SOURCES = ("tt_device.hpp", "tt_inst.hip", "tt_kernels.hpp", "tt_launch.hpp")
 
 
@@ -183,6 +183,12 @@ def run_gpu(args):
     sweeps = max(i["sweeps"] for i in pinfos)
     job.free()
     ctx.profile(False)
+
+    if args.main_only:
+        ctx.close()
+        return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
+                    s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=None,
+                    errs={}, probs=probs, batch=None, dd=None, serving=None)
 
     # the fibre-evaluation kernel alone on a large fibre set (D_10, middle mode)
     import numpy as np
@@ -409,6 +415,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="run only the D_5..D_10 + C_4 steps (for profiler runs of the sweep kernel)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="measured length of the serving stream (after a 1 s warm-up)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -440,7 +448,12 @@ def main():
             "alg_bytes_per_launch": r["s_bytes"] / max(nl_s, 1),
             "launches": nl_s, "avg_launch_ms": ms_s / max(nl_s, 1),
             "flops_per_launch": r["s_flops"] / max(nl_s, 1), "evals_per_launch": r["s_evals"] / max(nl_s, 1)}
-    nl, ms, npts, ff, ft = r["fib"]
+    fib = None
+    if r["fib"] is not None:
+        nl, ms, npts, ff, ft = r["fib"]
+        fib = {"kernel": "k_eval_fibers", "points": npts, "avg_launch_ms": ms / nl,
+               "tflops": ft, "frac": ft / FP64_PEAK_TFLOPS, "evals_per_s": npts / (ms / nl * 1e-3),
+               "workload": "D_10 (9 modes) fibre set 64 x 256 x 64 at mode 4"}
     line = {
         "metric": METRIC,
         "value": r["total_evals"] / r["elapsed"],
@@ -458,10 +471,7 @@ def main():
                                "start": r["kt"]["start"][1], "gl": r["kt"]["gl"][1]},
         "sweeps": r["sweeps"],
         "roofline": roof,
-        "fibre_eval_saturated": {"kernel": "k_eval_fibers", "points": npts, "avg_launch_ms": ms / nl,
-                                 "tflops": ft, "frac": ft / FP64_PEAK_TFLOPS,
-                                 "evals_per_s": npts / (ms / nl * 1e-3),
-                                 "workload": "D_10 (9 modes) fibre set 64 x 256 x 64 at mode 4"},
+        "fibre_eval_saturated": fib,
         "batch_mixed64": r["batch"],
         "precision_dd": r["dd"],
         "serving": r["serving"],
