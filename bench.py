@@ -201,12 +201,29 @@ def run_gpu(args):
     out = torch.empty(rl * pe.n * rr, dtype=torch.float64, device="cuda")
     for _ in range(3):
         ctx.eval_fibers(pe, pos, left.data_ptr(), rl, right.data_ptr(), rr, out.data_ptr())
-    ctx.profile(True)
-    reps = 20
-    for _ in range(reps):
-        ctx.eval_fibers(pe, pos, left.data_ptr(), rl, right.data_ptr(), rr, out.data_ptr())
-    nl, ms = ctx.kernel_time("eval_fibers")
-    ctx.profile(False)
+    # 50 launches captured in a HIP graph on a side stream (a second context
+    # bound to it), replayed back to back: kernel time without host overhead
+    reps = 50
+    side = torch.cuda.Stream()
+    gctx = Context(0, stream=side)
+    with torch.cuda.stream(side):
+        gctx.eval_fibers(pe, pos, left.data_ptr(), rl, right.data_ptr(), rr, out.data_ptr())
+    side.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for _ in range(reps):
+            gctx.eval_fibers(pe, pos, left.data_ptr(), rl, right.data_ptr(), rr, out.data_ptr())
+    graph.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(3):
+        graph.replay()
+    ev1.record(stream)
+    ev1.synchronize()
+    nl, ms = 3 * reps, ev0.elapsed_time(ev1)
+    del graph
+    gctx.close()
     npts = rl * pe.n * rr
     fib_flops = npts * flops_per_eval("ising_d", m, 3)
     fib_tflops = fib_flops / (ms / nl * 1e-3) / 1e12

@@ -202,6 +202,12 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
 }
 
 inline int bucket_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : 32; }
+// Mode bucket of the sweep kernels of one integrand class and number type
+// (must match the instantiations in tt_inst.hip).
+inline int bucket_m_for(int fam, bool dd, int m) {
+  if (fam == FAM_PAPER && !dd) return m <= 4 ? 4 : m <= 8 ? 8 : m <= 10 ? 10 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 24 ? 24 : 32;
+  return bucket_m(m);
+}
 inline int bucket_r(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : 64; }
 
 inline double four_over_fact(int m) {

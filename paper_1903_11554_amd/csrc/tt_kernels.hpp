@@ -1046,14 +1046,19 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(FamilyArgs fa, const T* 
 // rows and node tables staged in LDS once per workgroup, output ordered
 // (alpha, i, beta) with beta fastest.  The grid is bounded and strides over the
 // points; each lane advances its (alpha, i, beta) by the fixed stride with
-// carries instead of dividing.
-template <class T, int FAM, int MAXM>
-__global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa, int n, const T* __restrict__ t,
+// carries instead of dividing.  EXACT = true compiles the kernel for exactly
+// MAXM modes: every guard on the number of modes folds away, and the
+// integrand is straight-line code (the same operations in the same order, so
+// the same bits as the bucketed kernel).
+template <class T, int FAM, int MAXM, bool EXACT = false>
+__global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa_in, int n, const T* __restrict__ t,
                                                         const T* __restrict__ w, int pos,
                                                         const int32_t* __restrict__ left, int rl,
                                                         const int32_t* __restrict__ right, int rr,
                                                         T* __restrict__ out) {
   constexpr int LD = MAXM + 1;
+  FamilyArgs fa = fa_in;
+  if constexpr (EXACT) fa.m = MAXM;
   __shared__ T sLx[TT_MAX_RANK * LD], sRx[TT_MAX_RANK * LD];
   __shared__ T sLw[TT_MAX_RANK], sRw[TT_MAX_RANK];
   __shared__ T st[TT_MAX_NODES], sw[TT_MAX_NODES];

@@ -206,7 +206,7 @@ tt_status start_requests(tt_server* s, std::vector<Running>& fresh) {
   }
   TT_HIP(hipEventRecord(s->stage_ev[si], ctx->stream));
   LaunchArgs a{(ProbDesc*)(s->dtable + s->off_idesc), nullptr, 0, (const int2*)(s->dtable + s->off_itask),
-               (int)itask.size(), (int)fresh.size(), bucket_m(maxm), ctx->stream};
+               (int)itask.size(), (int)fresh.size(), bucket_m_for(fam, false, maxm), ctx->stream};
   auto go = [&](int what) {
     switch (fam) {
       case FAM_PAPER: launch_paper(a, what, 8); break;
@@ -338,7 +338,7 @@ void worker_main(tt_server* s) {
           r.launched += 1;
         }
         LaunchArgs a{(ProbDesc*)(s->dtable + s->off_sdesc), (const int2*)(s->dtable + s->off_stask), nbond,
-                     nullptr, 0, (int)s->running.size(), bucket_m(maxm), ctx->stream};
+                     nullptr, 0, (int)s->running.size(), bucket_m_for(fam, false, maxm), ctx->stream};
         {
           Timed tm(ctx, KK_SWEEP);
           switch (fam) {

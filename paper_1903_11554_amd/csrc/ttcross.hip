@@ -70,7 +70,8 @@ tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd) {
 namespace {
 
 void launch(tt_job* j, int what, int rb) {
-  LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, bucket_m(j->maxm), j->ctx->stream};
+  LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, bucket_m_for(j->fam, j->dd, j->maxm),
+               j->ctx->stream};
   Timed tm(j->ctx, what == LAUNCH_SWEEP ? KK_SWEEP : what == LAUNCH_START ? KK_START : KK_UPDATE);
   if (j->dd) {
     launch_paper_dd(a, what, rb);
@@ -120,13 +121,27 @@ void eval_points_m(tt_ctx* ctx, bool use_dd, dim3 grid, dim3 block, const Family
                        npts, d_out);
 }
 
-template <class T, int FAM, int MAXM>
+template <class T, int FAM, int MAXM, bool EXACT = false>
 void eval_fibers_k(tt_ctx* ctx, dim3 grid, dim3 block, const FamilyArgs& fa, int n, const double* t,
                    const double* w, int pos, const int32_t* d_left, int r_left, const int32_t* d_right,
                    int r_right, double* d_out) {
-  hipLaunchKernelGGL((k_eval_fibers<T, FAM, MAXM>), grid, block, 0, ctx->stream, fa, n,
+  hipLaunchKernelGGL((k_eval_fibers<T, FAM, MAXM, EXACT>), grid, block, 0, ctx->stream, fa, n,
                      reinterpret_cast<const T*>(t), reinterpret_cast<const T*>(w), pos, d_left, r_left,
                      d_right, r_right, reinterpret_cast<T*>(d_out));
+}
+
+// Paper form in double: one kernel per exact number of modes (1..TT_MAX_MODES).
+template <int M>
+void eval_fibers_exact(tt_ctx* ctx, int m, dim3 grid, dim3 block, const FamilyArgs& fa, int n, const double* t,
+                       const double* w, int pos, const int32_t* d_left, int r_left, const int32_t* d_right,
+                       int r_right, double* d_out) {
+  if constexpr (M <= TT_MAX_MODES) {
+    if (m == M)
+      eval_fibers_k<double, FAM_PAPER, M, true>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right,
+                                                r_right, d_out);
+    else
+      eval_fibers_exact<M + 1>(ctx, m, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out);
+  }
 }
 
 template <class T, int FAM>
@@ -630,7 +645,7 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
   s = family_for(ctx, p, &fa);
   if (s != TT_OK) return s;
   const int64_t total = (int64_t)r_left * p->n_nodes * r_right;   // < 2^31 by the rank and node limits
-  const int64_t blocks64 = std::min<int64_t>((total + kBlock - 1) / kBlock, 2048);
+  const int64_t blocks64 = std::min<int64_t>((total + kBlock - 1) / kBlock, 1024);
   const dim3 grid((unsigned)blocks64), block(kBlock);
   const int n = p->n_nodes, mb = bucket_m(m);
   Timed tm(ctx, KK_EVAL_FIBERS);
@@ -638,8 +653,7 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
   if (use_dd)
     eval_fibers_f<dd, FAM_PAPER>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out);
   else if (fam == FAM_PAPER)
-    eval_fibers_f<double, FAM_PAPER>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right,
-                                     d_out);
+    eval_fibers_exact<1>(ctx, m, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out);
   else if (fam == FAM_UFORM)
     eval_fibers_f<double, FAM_UFORM>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right,
                                      d_out);

@@ -96,3 +96,31 @@ def test_eval_fibers_matches_oracle(family, d, n, pos, rl, rr):
     want = weighted_values(family, idx, t, w, params).reshape(rl, n, rr)
     np.testing.assert_allclose(got, want, rtol=eps_bound(op_count(family, m)),
                                atol=np.abs(want).max() * 1e-290)
+
+
+def test_eval_fibers_graph_replay_matches_eager():
+    """Library launches captured in a HIP graph replay to the eager result, replay after replay."""
+    torch = require_gpu()
+    from paper_1903_11554_amd import Context
+    p = Problem("ising_d", 8, 32, 8, 1e-10)
+    m, pos, rl, rr = p.modes(), 3, 16, 16
+    left = torch.from_numpy(random_index_set(rl, pos, p.n, 21)).cuda()
+    right = torch.from_numpy(random_index_set(rr, m - pos - 1, p.n, 22)).cuda()
+    side = torch.cuda.Stream()
+    ctx = Context(0, stream=side)
+    eager = torch.empty(rl * p.n * rr, dtype=torch.float64, device="cuda")
+    out = torch.zeros_like(eager)
+    with torch.cuda.stream(side):
+        ctx.eval_fibers(p, pos, left.data_ptr(), rl, right.data_ptr(), rr, eager.data_ptr())
+    side.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        ctx.eval_fibers(p, pos, left.data_ptr(), rl, right.data_ptr(), rr, out.data_ptr())
+    for k in range(4):
+        out.zero_()                      # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), k
+    del graph
+    ctx.close()
