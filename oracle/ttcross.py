@@ -56,13 +56,16 @@ N_START = 1024
 
 
 class PivotRecord:
-    __slots__ = ("bond", "row", "col", "err", "err_lo", "value", "accepted", "iters", "searched", "_new")
+    __slots__ = ("bond", "row", "col", "err", "err_lo", "value", "accepted", "iters", "searched", "_new",
+                 "col_fresh", "n_rows", "n_cols")
 
     def __init__(self, bond, row=-1, col=-1, err=0.0, value=0.0, accepted=False, iters=0,
                  searched=False):
         self.bond, self.row, self.col = bond, row, col
         self.err, self.value = err, value
         self.err_lo = 0.0            # low part of err in the double-double oracle
+        self.col_fresh = False       # the last column step was at the final column
+        self.n_rows = self.n_cols = 0   # superblock size at the time of the search
         self.accepted, self.iters, self.searched = accepted, iters, searched
         self._new = None
 
@@ -155,11 +158,24 @@ class TTCross:
         self._count_new_core_entries()
         self.history.append(self.integral())
 
-    def _count_new_core_entries(self):
+    def _count_new_core_entries(self, recs=()):
+        """Count the entries the core updates evaluate after the sets grew.
+
+        Reading: the last row step of an accepted search at bond b evaluated
+        the new row of F_{b+1} at its old columns, and the last column step,
+        when it was taken at the final column, the new column of F_b at its
+        old rows (these are the same tensor entries); the updates reuse them,
+        so only the remaining new entries are evaluated again.
+        """
+        reused = 0
+        for rec in recs:
+            if rec.accepted:
+                reused += rec.n_cols + (rec.n_rows if rec.col_fresh else 0)
         for c in range(self.m):
             size = len(self.left_set(c - 1)) * self.n * len(self.right_set(c))
             self.evals += size - self._core_sizes[c]
             self._core_sizes[c] = size
+        self.evals -= reused
 
     # ------------------------------------------------------------ quadrature
     def integral(self):
@@ -238,6 +254,7 @@ class TTCross:
             if done:
                 break
         rec.row, rec.col = row, col
+        rec.col_fresh, rec.n_rows, rec.n_cols = done, nrows, ncols
         rec.err, rec.value = float(e_row[col]), float(a_row[col])
         self.scale[b] = max(self.scale[b], seen)
         alpha, i = divmod(row, n)
@@ -264,7 +281,7 @@ class TTCross:
             rec._new = None
         self.pivot_log.append(recs)
         self.sweeps += 1
-        self._count_new_core_entries()
+        self._count_new_core_entries(recs)
         value = self.integral()
         prev = self.history[-1]
         rel = abs(value - prev) / abs(value) if value != 0.0 else math.inf

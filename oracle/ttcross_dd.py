@@ -179,6 +179,7 @@ class TTCrossDD(TTCross):
             if done:
                 break
         rec.row, rec.col = row, col
+        rec.col_fresh, rec.n_rows, rec.n_cols = done, nrows, ncols
         rec.err, rec.value = float(e_row.hi[col]), float(a_row.hi[col])
         rec.err_lo = float(e_row.lo[col])
         self.scale[b] = max(self.scale[b], seen)
@@ -206,7 +207,7 @@ class TTCrossDD(TTCross):
             rec._new = None
         self.pivot_log.append(recs)
         self.sweeps += 1
-        self._count_new_core_entries()
+        self._count_new_core_entries(recs)
         value = self.integral_dd()
         prev = DD(self.history[-1], self.history_lo[-1])
         rel = float(abs((value - prev) / value).hi) if value.hi != 0.0 else math.inf

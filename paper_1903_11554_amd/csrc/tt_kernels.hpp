@@ -64,6 +64,7 @@ struct ProbDesc {
   double *hist;                          // T [max_sweeps+1]
   int32_t *start;                        // [m] start multi-index
   int32_t *sync;                         // [m+1] per-sweep dataflow counters (cores ready, cores done)
+  int32_t *colok;                        // [nbonds] the search's last column step was at its final column
   int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
   ProbState *st_host;                    // pinned host copy of the final state (may be null)
   long long *phase;                      // [max_sweeps][nbonds][kPhases] wall-clock marks, or null
@@ -400,6 +401,14 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   const int nrows = rL * n, ncols = n * rR;
   const T* __restrict__ F1 = tp<T>(p.F) + p.Foff[b + 1];
   const int cc1 = colcap(p, b + 1);
+  // The column step at col = (j, beta) evaluates F_b(alpha, i, (j, beta)) for every old
+  // row: the new column of F_b if this pivot is accepted; the row step at row = (alpha,
+  // i) evaluates F_{b+1}((alpha, i), j, beta) for every old column: its new row.  Both
+  // are written into the free slot (column r_b of F_b, row r_b of F_{b+1}) as they are
+  // evaluated, so the core updates need not evaluate them again.
+  T* Fb_new = tp<T>(p.F) + p.Foff[b] + rb;
+  const int ccb = colcap(p, b);
+  T* F1_new = tp<T>(p.F) + p.Foff[b + 1] + (size_t)rb * n * cc1;
   const T* __restrict__ Cb = tp<T>(p.C) + p.Coff[b];
   const size_t ldC = (size_t)rowcap(p, b) * n;
   const int nsamp = min(nrows + ncols, kMaxSamples);
@@ -409,6 +418,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   bool bad = false, invalid = false;
   int mode = 0;            // 0: random samples, 1: column step, 2: row step
   int row = 0, col = 0, iters = 0;
+  bool col_fresh = false;  // the last column step was taken at the final column
   for (;;) {
     if (mode == 1) {          // B~(:, col) = C_b F_{b+1}(:, col)
       const int j = col / rR, be = col - j * rR;
@@ -447,8 +457,12 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
         }
         y[k] = v;
       }
-      const T W = n_mul(n_mul(n_mul(sm.Lw[al], sm.w[i]), sm.w[j]), sm.Rw[be]);
+      // weights multiplied in the order the core update uses for the same entry
+      const T W = (mode == 1) ? n_mul(n_mul(sm.Lw[al], sm.w[i]), n_mul(sm.w[j], sm.Rw[be]))
+                              : n_mul(n_mul(n_mul(sm.Lw[al], sm.w[i]), sm.w[j]), sm.Rw[be]);
       const T a = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
+      if (mode == 1) Fb_new[(size_t)pr * ccb] = a;
+      else if (mode == 2) F1_new[(size_t)j * cc1 + be] = a;
       T s = num<T>(0.0);
       if (mode == 0) {
 #pragma unroll 8
@@ -489,6 +503,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
     ++iters;
     const bool same = (best.idx == col);   // rook condition: the row step kept the column
     col = best.idx;
+    col_fresh = same;
     if (same || iters == kRook) break;
     mode = 1;
   }
@@ -512,6 +527,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
     PivRec rec{row, col, acc, iters, e_star, a_star};
     p.piv[b] = rec;
     p.log[(size_t)sweep * nb + b] = rec;
+    p.colok[b] = col_fresh ? 1 : 0;
     if (any_bad || invalid) atomicOr(&st->err_flags, 1);
     const int per_step = nrows + ncols;
     atomicAdd(&st->evals, (unsigned long long)(nsamp + iters * per_step));
@@ -608,20 +624,25 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   __syncthreads();
   if (mb >= 0) mark(p, msw, mb, 9);
 
-  // ---- evaluate the new entries of F_c = B(I_<=c-1, i_c, I_>c)
+  // ---- evaluate the new entries of F_c = B(I_<=c-1, i_c, I_>c) that no search evaluated:
+  //      the new row at the old columns came from bond c-1's last row step and the new
+  //      column at the old rows from bond c's last column step (when taken at the final
+  //      column); what remains is the corner (new row, new column), or the new column
+  //      at every row.  At init every entry is new.
   T* __restrict__ Fc = tp<T>(p.F) + p.Foff[c];
   const int cc = colcap(p, c);
-  const int nA = (rL_new - rL_old) * n * rR_new;            // new rows (all columns)
   const int nBc = rR_new - rR_old;
-  const int nB = rL_old * n * nBc;                          // new column (old rows)
+  const int nA = (rL_new - rL_old) * n * nBc;               // new rows x new columns
+  const bool col_done = !init && accR && p.colok[c];
+  const int nB = col_done ? 0 : rL_old * n * nBc;           // new column (old rows)
   bool bad = false;
   for (int e = tid; e < nA + nB; e += blockDim.x) {
     int al, i, be;
     if (e < nA) {
-      al = rL_old + e / (n * rR_new);
-      const int rem = e % (n * rR_new);
-      i = rem / rR_new;
-      be = rem % rR_new;
+      al = rL_old + e / (n * nBc);
+      const int rem = e % (n * nBc);
+      i = rem / nBc;
+      be = rR_old + rem % nBc;
     } else {
       const int e2 = e - nA;
       al = e2 / (n * nBc);

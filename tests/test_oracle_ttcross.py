@@ -171,3 +171,49 @@ def test_degenerate_mode_counts(d):
     assert tt.stop_reason == "converged"
     want = 2.0 if d == 1 else 1.0 / 3.0
     assert abs(tt.history[-1] - want) < 1e-15
+
+
+def test_update_evaluations_exclude_the_reused_rook_fibres():
+    """The core updates evaluate exactly the new core entries that no final rook step evaluated.
+
+    Checked with explicit point sets: per core, the entries added by a sweep;
+    the final row step of an accepted search at bond b covers the new row of
+    core b+1 at its old columns, and its final column step (when taken at the
+    final column) the new column of core b at its old rows.
+    """
+    tt = ttcross.TTCross("ising_d", 6, 10, 8, 1e-14, seed=3, max_sweeps=8)
+    n = tt.n
+
+    def core_points():
+        return [{l + (i,) + r for l in tt.left_set(c - 1) for i in range(n) for r in tt.right_set(c)}
+                for c in range(tt.m)]
+
+    checked = 0
+    for _ in range(6):
+        if tt.stop_reason:
+            break
+        before = core_points()
+        L = [list(tt.left_set(b - 1)) for b in range(tt.m - 1)]
+        R = [list(tt.right_set(b + 1)) for b in range(tt.m - 1)]
+        ev0 = tt.evals
+        tt.sweep()
+        recs = tt.pivot_log[-1]
+        search = sum(min(r.n_rows + r.n_cols, ttcross.MAX_SAMPLES) + r.iters * (r.n_rows + r.n_cols)
+                     for r in recs if r.searched)
+        after = core_points()
+        new = [after[c] - before[c] for c in range(tt.m)]
+        reused = [set() for _ in range(tt.m)]
+        for b, r in enumerate(recs):
+            if not r.accepted:
+                continue
+            rR = len(R[b])
+            al, i = divmod(r.row, n)
+            j, be = divmod(r.col, rR)
+            reused[b + 1] |= {L[b][al] + (i, jj) + rr for jj in range(n) for rr in R[b]}
+            if r.col_fresh:
+                reused[b] |= {ll + (ii, j) + R[b][be] for ll in L[b] for ii in range(n)}
+        for c in range(tt.m):
+            assert reused[c] <= new[c]
+        assert tt.evals - ev0 - search == sum(len(new[c]) - len(reused[c]) for c in range(tt.m))
+        checked += sum(len(x) for x in reused)
+    assert checked > 0
