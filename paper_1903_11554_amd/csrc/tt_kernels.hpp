@@ -906,20 +906,33 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
       }
       __syncthreads();
     }
-    for (int c = c0; c < c1; ++c) {   // ping-pong between v and v2: one barrier per core
-      const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
-      const T* Sc = direct ? gS + (size_t)c * R * R : stage + s_off[c - c0];
-      const int ldS = direct ? R : rr;
-      for (int k = tid; k < rr; k += blockDim.x) {
-        T s = num<T>(0.0);
-        for (int a = 0; a < rl; ++a) s = n_mad(v[a], Sc[a * ldS + k], s);
-        v2[k] = s;
+    // the chain itself runs in wave 0 alone (lane k owns column k of every S_c,
+    // r <= 64), ping-ponging v and v2 in LDS with wave-level ordering only
+    if (tid < kWave) {
+      for (int c = c0; c < c1; ++c) {
+        const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
+        const T* Sc = direct ? gS + (size_t)c * R * R : stage + s_off[c - c0];
+        const int ldS = direct ? R : rr;
+        if (tid < rr) {
+          T s = num<T>(0.0);
+          for (int a = 0; a < rl; ++a) s = n_mad(v[a], Sc[a * ldS + tid], s);
+          v2[tid] = s;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        T* tmp = v;
+        v = v2;
+        v2 = tmp;
       }
-      T* tmp = v;
-      v = v2;
-      v2 = tmp;
-      __syncthreads();
+    } else {
+      for (int c = c0; c < c1; ++c) {   // the other waves track which buffer holds v
+        T* tmp = v;
+        v = v2;
+        v2 = tmp;
+      }
     }
+    __syncthreads();
     c0 = c1;
   }
   if (tid != 0) return;
