@@ -220,3 +220,17 @@ def test_dd_workload_d8_d12_full_size():
     assert d8 < 1e-15 and d8 < d8_64 / 10
     job.free()
     job64.free()
+
+
+def test_dd_d32_against_printed_value():
+    """D_32 (31 modes) in double-double, 128 nodes, rank <= 64: closer to the printed value than double can be."""
+    ctx = gpu_context()
+    p = Problem("ising_d", 32, 128, 64, 1e-21, seed=32, precision="dd")
+    job = ctx.job([p])
+    info = job.run()[0]
+    job.free()
+    with mp.workdps(60):
+        rel = dd_rel(info["value"], info["value_lo"], mp.mpf("2.1812588849921849857069379650793e-22"), 0)
+    print(f"D_32 double-double: {info} rel err {rel:.3e}", flush=True)
+    assert info["err_flags"] == 0
+    assert rel < 1e-15    # double rounding alone leaves about 1e-16 per operation, 1e-13 at this size
