@@ -144,6 +144,16 @@ tt_status tt_cross_sweep(tt_job *job, int32_t n_sweeps, tt_info *info);
 /* Sweep until every integral stops (stopping rule or max_sweeps); fills info. */
 tt_status tt_cross_run(tt_job *job, tt_info *info);
 
+/* Enqueue n_sweeps sweeps of Alg. 6 on the context stream and return at once:
+ * no host synchronisation, no allocation, no memset, so the call may run while
+ * the caller captures that stream into a HIP graph.  Every enqueued sweep uses
+ * the kernels sized for the job's rank caps, so captured launches stay valid
+ * however far a replayed graph advances the integrals; sweeps of integrals that
+ * have stopped return at once.  Read the results with tt_cross_integrate after
+ * the work has run.  Errors: TT_EINVAL (NULL job, n_sweeps < 0, or per-kernel
+ * profiling switched on), TT_EDEVICE. */
+tt_status tt_cross_enqueue(tt_job *job, int32_t n_sweeps);
+
 /* Copy the integral values (count doubles, host) and infos (may be NULL). */
 tt_status tt_cross_integrate(tt_job *job, double *values, tt_info *info);
 

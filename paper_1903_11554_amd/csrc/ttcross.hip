@@ -33,6 +33,7 @@ struct tt_job {
   int maxm = 0, maxR = 1;
   int fam = 3;            // integrand class the job's kernels are specialised for
   bool dd = false;        // double-double job
+  bool full_bucket = false;   // sweeps were enqueued for graph capture: size kernels for the rank caps
   std::vector<std::pair<double*, double*>> gl64;   // per integral: the double node tables
   int launched = 0;       // sweeps enqueued so far
   int max_sweeps_all = 0;
@@ -90,7 +91,7 @@ void enqueue_sweep(tt_job* j, int rb) { launch(j, LAUNCH_SWEEP, rb); }
 tt_status enqueue_sweeps(tt_job* j, int n_sweeps) {
   for (int s = 0; s < n_sweeps; ++s) {
     if (j->launched >= j->max_sweeps_all) break;
-    if (j->nbond > 0) enqueue_sweep(j, bucket_r(std::min(j->maxR, j->launched + 2)));
+    if (j->nbond > 0) enqueue_sweep(j, bucket_r(j->full_bucket ? j->maxR : std::min(j->maxR, j->launched + 2)));
     ++j->launched;
   }
   TT_HIP(hipGetLastError());
@@ -388,6 +389,19 @@ tt_status tt_cross_sweep(tt_job* j, int32_t n_sweeps, tt_info* info) {
     all = all && st[k].done;
   }
   return all ? TT_CONVERGED : TT_NOT_CONVERGED;
+}
+
+tt_status tt_cross_enqueue(tt_job* j, int32_t n_sweeps) {
+  if (!j || n_sweeps < 0) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  if (j->ctx->profiling) return TT_EINVAL;   // event pairs would be captured too
+  TT_HIP(hipSetDevice(j->ctx->device));
+  j->full_bucket = true;                      // from now on the host does not know the ranks
+  if (j->nbond > 0)
+    for (int s = 0; s < n_sweeps; ++s) enqueue_sweep(j, bucket_r(j->maxR));
+  j->launched += n_sweeps;
+  TT_HIP(hipGetLastError());
+  return TT_OK;
 }
 
 // Sweeps are queued kQueued ahead of the last one known complete; after each

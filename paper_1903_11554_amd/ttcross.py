@@ -67,7 +67,7 @@ EXPORTS = [
     "tt_cross_free", "tt_eval_points", "tt_eval_fibers", "tt_status_string",
     "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
     "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
-    "tt_server_get_stats", "tt_server_destroy",
+    "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue",
 ]
 
 KERNEL_KINDS = {"sweep": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
@@ -117,6 +117,7 @@ def load_library():
         "tt_server_wait": (i32, [vp, ctypes.c_uint64, P(_Info), P(dbl)]),
         "tt_server_get_stats": (i32, [vp, P(_ServerStats)]),
         "tt_server_destroy": (None, [vp]),
+        "tt_cross_enqueue": (i32, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -255,6 +256,10 @@ class Job:
         infos = self._infos()
         st = _check(self._lib.tt_cross_sweep(self.handle, n, infos), "tt_cross_sweep")
         return st == TT_CONVERGED, self._info_dicts(infos)
+
+    def enqueue(self, n=1):
+        """Enqueue n sweeps without waiting (capturable into a HIP graph)."""
+        _check(self._lib.tt_cross_enqueue(self.handle, n), "tt_cross_enqueue")
 
     def run(self):
         infos = self._infos()

@@ -315,3 +315,42 @@ def test_high_dimension_against_printed_values(d):
     print(f"D_{d}: {info} rel err {rel:.3e}", flush=True)
     assert info["reason"] == "converged" and info["err_flags"] == 0
     assert rel < 10 * p.tol
+
+
+def test_captured_sweeps_replay_to_the_solo_result():
+    """Sweeps enqueued under HIP graph capture, replayed until every integral stops.
+
+    Eager work and synchronisations run between the replays; the results must be
+    bitwise those of tt_cross_run on the same problems.
+    """
+    torch = require_gpu()
+    from paper_1903_11554_amd import Context
+    probs = [SMALL[i] for i in (3, 4, 6, 7)]
+    ref = []
+    for p in probs:
+        j = gpu_context().job([p])
+        ref.append(j.run()[0])
+        j.free()
+    side = torch.cuda.Stream()
+    ctx = Context(0, stream=side)
+    job = ctx.job(probs)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        job.enqueue(4)
+    infos = None
+    for rep in range(200):
+        x = torch.arange(4096, dtype=torch.float64, device="cuda")
+        assert float(x.sum()) == 4095 * 4096 / 2
+        torch.cuda.synchronize()
+        graph.replay()
+        side.synchronize()
+        infos = job.values()[1]
+        if all(i["reason"] != "running" for i in infos):
+            break
+    print(f"replays {rep + 1}: {infos}", flush=True)
+    for p, a, b in zip(probs, infos, ref):
+        for key in ("value", "evals", "sweeps", "reason", "max_rank", "err_flags"):
+            assert a[key] == b[key], (p, key, a, b)
+    del graph
+    job.free()
+    ctx.close()
