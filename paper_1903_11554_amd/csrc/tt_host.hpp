@@ -54,6 +54,9 @@ struct tt_ctx {
   double* params = nullptr;                        // device scratch for synthetic params
   size_t params_cap = 0;
   std::multimap<size_t, void*> arenas;             // freed job arenas kept for reuse
+  std::multimap<size_t, void*> pinned;             // freed pinned host blocks kept for reuse
+  size_t pinned_cached = 0;
+  std::vector<hipEvent_t> ring_pool;               // timing-less events kept for reuse
   size_t arena_bytes_cached = 0;
 };
 

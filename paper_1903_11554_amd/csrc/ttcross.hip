@@ -38,7 +38,8 @@ struct tt_job {
   int launched = 0;       // sweeps enqueued so far
   int max_sweeps_all = 0;
   ProbState* dstate = nullptr;
-  std::vector<char> image;   // host image of the table region (source of the async upload)
+  char* pinned = nullptr;                  // pinned host block: done flags, then the table image
+  size_t pinned_bytes = 0;
   int32_t* done_host = nullptr;            // pinned, one flag per integral, written by the kernels
   std::vector<hipEvent_t> ring;            // one event per queued sweep (tt_cross_run)
 };
@@ -69,6 +70,33 @@ tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd) {
 }  // namespace ttx_host
 
 namespace {
+
+// Pinned host blocks of freed jobs are kept (up to this many bytes) for later jobs.
+constexpr size_t kPinnedCacheBytes = size_t(64) << 20;
+
+tt_status pinned_take(tt_ctx* c, size_t bytes, char** out, size_t* got) {
+  auto it = c->pinned.lower_bound(bytes);
+  if (it != c->pinned.end() && it->first <= 2 * bytes + 4096) {
+    *out = (char*)it->second;
+    *got = it->first;
+    c->pinned_cached -= it->first;
+    c->pinned.erase(it);
+    return TT_OK;
+  }
+  if (hipHostMalloc((void**)out, bytes, hipHostMallocDefault) != hipSuccess) return TT_ENOMEM;
+  *got = bytes;
+  return TT_OK;
+}
+
+void pinned_give(tt_ctx* c, char* p, size_t bytes) {
+  if (!p) return;
+  if (c->pinned_cached + bytes <= kPinnedCacheBytes) {
+    c->pinned.emplace(bytes, p);
+    c->pinned_cached += bytes;
+  } else {
+    (void)hipHostFree(p);
+  }
+}
 
 void launch(tt_job* j, int what, int rb) {
   LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, bucket_m_for(j->fam, j->dd, j->maxm),
@@ -207,6 +235,8 @@ void tt_ctx_destroy(tt_ctx* c) {
   }
   if (c->params) hipFree(c->params);
   for (auto& kv : c->arenas) hipFree(kv.second);
+  for (auto& kv : c->pinned) hipHostFree(kv.second);
+  for (hipEvent_t e : c->ring_pool) hipEventDestroy(e);
   for (auto& pe : c->pending) {
     hipEventDestroy(pe.second.first);
     hipEventDestroy(pe.second.second);
@@ -327,7 +357,7 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   auto fail = [&](tt_status s) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(j->arena);
-    if (j->done_host) (void)hipHostFree(j->done_host);
+    if (j->pinned) (void)hipHostFree(j->pinned);
     delete j;
     return s;
   };
@@ -337,10 +367,13 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->dcore = (int2*)(base + core_off);
   j->nbond = (int)bond_tasks.size();
   j->ncore = (int)core_tasks.size();
-  j->image.assign(table_bytes, 0);
-  char* img = j->image.data();
-  if (hipHostMalloc((void**)&j->done_host, sizeof(int32_t) * count, hipHostMallocDefault) != hipSuccess)
-    return fail(TT_ENOMEM);
+  // one pinned block (reused from the context when possible): done flags, then
+  // the host image of the table region, the source of the asynchronous upload
+  const size_t flags_bytes = (sizeof(int32_t) * count + 255) & ~size_t(255);
+  if (pinned_take(ctx, flags_bytes + table_bytes, &j->pinned, &j->pinned_bytes) != TT_OK) return fail(TT_ENOMEM);
+  j->done_host = (int32_t*)j->pinned;
+  char* img = j->pinned + flags_bytes;
+  std::memset(img, 0, table_bytes);
   for (int k = 0; k < count; ++k) j->done_host[k] = 0;
   for (int k = 0; k < count; ++k) {
     const tt_problem& p = problems[k];
@@ -417,7 +450,12 @@ tt_status tt_cross_run(tt_job* j, tt_info* info) {
     TT_HIP(hipSetDevice(j->ctx->device));
     while ((int)j->ring.size() < kQueued) {
       hipEvent_t e;
-      TT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      if (!j->ctx->ring_pool.empty()) {
+        e = j->ctx->ring_pool.back();
+        j->ctx->ring_pool.pop_back();
+      } else {
+        TT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      }
       j->ring.push_back(e);
     }
     auto all_done = [&]() {
@@ -604,8 +642,8 @@ void tt_cross_free(tt_job* j) {
   std::lock_guard<std::mutex> lock(c->mu);
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  if (j->done_host) (void)hipHostFree(j->done_host);
-  for (hipEvent_t e : j->ring) (void)hipEventDestroy(e);
+  pinned_give(c, j->pinned, j->pinned_bytes);
+  for (hipEvent_t e : j->ring) c->ring_pool.push_back(e);
   if (c->arena_bytes_cached + j->bytes <= kArenaCacheBytes) {
     c->arenas.emplace(j->bytes, j->arena);
     c->arena_bytes_cached += j->bytes;
