@@ -73,21 +73,24 @@ def flops_per_eval(family, m, weight_muls):
 
 
 def sweep_work(job, k, prob):
-    """Integrand evaluations and algorithmic FP64 flops of the sweep kernel for integral k.
+    """Integrand evaluations, algorithmic FP64 flops and bytes of the sweep kernel for integral k.
 
     Reconstructed exactly from the pivot log (ranks start at 1 and grow by the
-    accepted pivots).  Per sweep and superblock b (if searched): samples
-    min(r_{b-1} n + n r_{b+1}, 1024) plus, per rook iteration, one column
-    (r_{b-1} n points) and one row (n r_{b+1} points), each point also an
-    r_b-term dot product (2 r_b flops).  Per core c: the new fibre entries
-    (new row: n r_c', new column: r_{c-1} n), the LU of the r x r cross
-    (2 r^3 / 3) and the triangular solves of its r_{c-1}' n rows (2 r^2 each),
-    and the core sum (r_{c-1}' n r_c'); the quadrature adds 2 r_{c-1} r_c per core.
+    accepted pivots), counting what the kernels do.
 
-    Algorithmic bytes: the samples and every rook iteration read the
-    interpolation core C_b and the fibre core F_{b+1} once (8 (r_{b-1} n r_b +
-    r_b n r_{b+1})); each core update writes its new fibre entries, reads and
-    writes C_c (16 r_{c-1}' n r_c') and reads it again for the core sum.
+    Search of superblock b (when searched): min(r_{b-1} n + n r_{b+1}, 1024)
+    samples plus, per rook iteration, one column (r_{b-1} n points) and one row
+    (n r_{b+1} points); every point is one integrand value and an r_b-term dot
+    product (2 r_b flops).  Bytes: C_b and F_{b+1} read once per pass, and the
+    column and row values written into the free fibre slots.
+
+    Core update of core c (ranks rl -> rl', rr -> rr'): integrand values only
+    where no search evaluated them (the corner (rl'-rl) n (rr'-rr), and the new
+    column at the old rows when bond c's last column step was not at its
+    pivot's column); the new rows of C_c by forward and backward substitution
+    (2 rr^2 flops per row); bordering the LU (2 rr^2 + 2 rr); the rank-1 update
+    of C_c (4 rr + 1 flops per row, rl' n rows, C_c read and written); the core
+    sums (rl' n rr' additions, C_c read).  The quadrature: 2 r_{c-1} r_c per core.
     """
     m, n = prob.modes(), prob.n
     nb = m - 1
@@ -106,19 +109,31 @@ def sweep_work(job, k, prob):
             evals += e
             flops += e * (fs + 2 * ranks[b])
             nbytes += (1 + rec["iters"]) * 8 * (rl * n * ranks[b] + ranks[b] * n * rr)
+            nbytes += 8 * rec["iters"] * (nrows + ncols)
         new = [ranks[b] + (1 if sweep[b]["accepted"] else 0) for b in range(nb)]
         for c in range(m):
             rl_old = ranks[c - 1] if c > 0 else 1
             rl_new = new[c - 1] if c > 0 else 1
             rr_old = ranks[c] if c < nb else 1
             rr_new = new[c] if c < nb else 1
-            e = (rl_new - rl_old) * n * rr_new + rl_old * n * (rr_new - rr_old)
+            acc_l, acc_r = rl_new - rl_old, rr_new - rr_old
+            fresh = c < nb and sweep[c]["col_fresh"]
+            e = acc_l * n * acc_r + (0 if fresh else rl_old * n * acc_r)
             evals += e
             flops += e * fc
-            nbytes += 8 * e + 24 * rl_new * n * rr_new
+            nbytes += 8 * e
             if c < nb:
-                r = rr_new
-                flops += 2 * r ** 3 // 3 + 2 * rl_new * n * r * r + rl_new * n * r
+                r0 = rr_old
+                if acc_l:
+                    flops += 2 * n * r0 * r0
+                if acc_r:
+                    flops += 2 * r0 * r0 + 2 * r0 + rl_new * n * (4 * r0 + 1)
+                    nbytes += 16 * rl_new * n * r0
+                flops += rl_new * n * rr_new
+                nbytes += 8 * rl_new * n * rr_new
+            else:
+                flops += rl_new * n
+                nbytes += 8 * rl_new * n
             flops += 2 * rl_new * rr_new
         ranks = new
     return evals, flops, nbytes

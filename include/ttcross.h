@@ -112,6 +112,9 @@ typedef struct {
   int32_t iters;       /* rook (column,row) pairs used, 1..5; 0 if not searched            */
   double  err;         /* B - B~ at the pivot (signed; TT_DD: leading double)             */
   double  value;       /* B at the pivot (TT_DD: leading double)                          */
+  int32_t col_fresh;   /* 1 if the last column step of the rook loop was at `col`: its
+                          values are the new column of the core left of the bond       */
+  int32_t reserved;
 } tt_pivot;
 
 typedef struct tt_ctx tt_ctx;

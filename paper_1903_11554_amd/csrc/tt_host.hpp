@@ -159,7 +159,7 @@ struct Layout {
 
 struct ProbOffsets {
   size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, LU, S, rank, piv, scale, log, hist, start, sync,
-      colok, phase;
+      phase;
   std::vector<int64_t> foff, coff;
 };
 
@@ -200,7 +200,6 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   o.hist = L.take((size_t)(ms + 1) * D);
   o.start = L.take((size_t)(m > 0 ? m : 1) * I);
   o.sync = L.take((size_t)(m + 1) * I);
-  o.colok = L.take((size_t)(nb > 0 ? nb : 1) * I);
   o.phase = L.take((size_t)ms * (nb > 0 ? nb : 1) * kPhases * sizeof(long long));
   return o;
 }
@@ -324,7 +323,6 @@ inline ProbDesc make_desc(const tt_problem& p, const ProbOffsets& o, char* pb, c
   d.hist = (double*)(pb + o.hist);
   d.start = (int32_t*)(pb + o.start);
   d.sync = (int32_t*)(pb + o.sync);
-  d.colok = (int32_t*)(pb + o.colok);
   d.done_host = done_host;
   d.st_host = st_host;
   d.phase = profiling ? (long long*)(pb + o.phase) : nullptr;

@@ -31,6 +31,7 @@ namespace ttx {
 struct PivRec {
   int32_t row, col, acc, iters;
   double err, val;
+  int32_t col_fresh, pad;   // the last column step was at the final column
 };
 static_assert(sizeof(PivRec) == sizeof(tt_pivot), "PivRec must mirror tt_pivot");
 
@@ -64,7 +65,6 @@ struct ProbDesc {
   double *hist;                          // T [max_sweeps+1]
   int32_t *start;                        // [m] start multi-index
   int32_t *sync;                         // [m+1] per-sweep dataflow counters (cores ready, cores done)
-  int32_t *colok;                        // [nbonds] the search's last column step was at its final column
   int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
   ProbState *st_host;                    // pinned host copy of the final state (may be null)
   long long *phase;                      // [max_sweeps][nbonds][kPhases] wall-clock marks, or null
@@ -366,7 +366,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   const int rR = b < m - 2 ? p.rank[b + 1] : 1;
   if (rb >= R) {
     if (tid == 0) {
-      PivRec rec{-1, -1, 0, 0, 0.0, 0.0};
+      PivRec rec{-1, -1, 0, 0, 0.0, 0.0, 0, 0};
       p.piv[b] = rec;
       p.log[(size_t)sweep * nb + b] = rec;
     }
@@ -524,10 +524,9 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
     const double scale = fmax(p.scale[b], seen);
     p.scale[b] = scale;
     const int acc = (fabs(e_star) > p.tol * scale) && !dup && !any_bad && !invalid;
-    PivRec rec{row, col, acc, iters, e_star, a_star};
+    PivRec rec{row, col, acc, iters, e_star, a_star, col_fresh ? 1 : 0, 0};
     p.piv[b] = rec;
     p.log[(size_t)sweep * nb + b] = rec;
-    p.colok[b] = col_fresh ? 1 : 0;
     if (any_bad || invalid) atomicOr(&st->err_flags, 1);
     const int per_step = nrows + ncols;
     atomicAdd(&st->evals, (unsigned long long)(nsamp + iters * per_step));
@@ -633,7 +632,7 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   const int cc = colcap(p, c);
   const int nBc = rR_new - rR_old;
   const int nA = (rL_new - rL_old) * n * nBc;               // new rows x new columns
-  const bool col_done = !init && accR && p.colok[c];
+  const bool col_done = !init && accR && p.piv[c].col_fresh;
   const int nB = col_done ? 0 : rL_old * n * nBc;           // new column (old rows)
   bool bad = false;
   for (int e = tid; e < nA + nB; e += blockDim.x) {

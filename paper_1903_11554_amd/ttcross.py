@@ -57,7 +57,8 @@ class _ServerStats(ctypes.Structure):
 class _Pivot(ctypes.Structure):
     _fields_ = [("row", ctypes.c_int32), ("col", ctypes.c_int32),
                 ("accepted", ctypes.c_int32), ("iters", ctypes.c_int32),
-                ("err", ctypes.c_double), ("value", ctypes.c_double)]
+                ("err", ctypes.c_double), ("value", ctypes.c_double),
+                ("col_fresh", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 EXPORTS = [
@@ -281,7 +282,7 @@ class Job:
         _check(self._lib.tt_job_pivot_log(self.handle, k, buf, cap, ctypes.byref(written)),
                "tt_job_pivot_log")
         recs = [dict(row=r.row, col=r.col, accepted=bool(r.accepted), iters=r.iters, err=r.err,
-                     value=r.value) for r in buf[:written.value]]
+                     value=r.value, col_fresh=bool(r.col_fresh)) for r in buf[:written.value]]
         return [recs[s * nb:(s + 1) * nb] for s in range(written.value // nb)] if nb else []
 
     def history(self, k):

@@ -61,6 +61,7 @@ def compare(job, k, p, ref, exact_log=True, value_scale=None):
                     divergence = ("tie", s, b, g, o)
                     break
                 assert abs(g["err"] - o.err) <= 1e-11 * scale, (s, b, g, o, scale)
+                assert g["col_fresh"] == o.col_fresh, (s, b, g, o)
             elif not g["accepted"] and not o.accepted:
                 if (g["row"], g["col"], g["iters"]) != (o.row, o.col, o.iters):
                     noise_positions = True
@@ -354,3 +355,21 @@ def test_captured_sweeps_replay_to_the_solo_result():
     del graph
     job.free()
     ctx.close()
+
+
+def test_bench_work_model_counts_the_device_evaluations():
+    """bench.sweep_work reconstructs, from the pivot log, every integrand evaluation the kernels count."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    ctx = gpu_context()
+    probs = config_single_sweep() + [SMALL[6], SMALL[4]]
+    job = ctx.job(probs)
+    infos = job.run()
+    for k, p in enumerate(probs):
+        e, f, nbytes = bench.sweep_work(job, k, p)
+        m = p.modes()
+        assert e == infos[k]["evals"] - 1024 - m * p.n, (p, e, infos[k]["evals"])
+        assert f > 0 and nbytes > 0
+    job.free()
