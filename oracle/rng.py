@@ -15,8 +15,12 @@ Counter layout (a reading of the paper, which does not fix the distribution):
 
 * random samples of bond b in sweep s, sample j:  c = s * 2**40 + b * 2**24 + j
 * rank-1 start, sample q, mode k:                 c = 2**63 + q * 2**16 + k
+* Monte Carlo estimator j, point i, coordinate k (m coordinates per point):
+                                                  c = 2**62 + j * 2**40 + i * m + k
+* lattice shift of estimator j, coordinate k:     c = 2**62 + 2**61 + j * 2**6 + k
 
-A uniform integer in [0, N), N < 2**32, is ``((u >> 32) * N) >> 32``.
+A uniform integer in [0, N), N < 2**32, is ``((u >> 32) * N) >> 32``; a
+uniform double in the open interval (0, 1) is ``((u >> 11) + 0.5) * 2**-53``.
 
 Pinned by: the published first outputs of the seed-0 stream (tests/golden).
 """
@@ -64,3 +68,20 @@ def sample_counter(sweep, bond, j):
 
 def start_counter(q, k):
     return START_DOMAIN + (q << 16) + k
+
+
+MC_DOMAIN = 1 << 62
+SHIFT_DOMAIN = (1 << 62) + (1 << 61)
+
+
+def mc_counter(j, i, m, k):
+    return MC_DOMAIN + (j << 40) + i * m + k
+
+
+def shift_counter(j, k):
+    return SHIFT_DOMAIN + (j << 6) + k
+
+
+def uniform_open01(u):
+    """A 64-bit draw mapped to a double in (0, 1): the top 53 bits, centred in their cell."""
+    return ((u >> 11) + 0.5) * 2.0 ** -53

@@ -29,7 +29,8 @@ def load_copy(tmp_path, name, file=None, old=None, new=None):
     sys.path.insert(0, str(tmp_path))
     try:
         return {m: importlib.import_module(f"{name}.{m}")
-                for m in ("rng", "gauss", "integrands", "quadrature", "ttcross", "ddarith", "ttcross_dd")}
+                for m in ("rng", "gauss", "integrands", "quadrature", "ttcross", "ddarith", "ttcross_dd",
+                          "montecarlo")}
     finally:
         sys.path.remove(str(tmp_path))
 
@@ -149,6 +150,20 @@ def pin_dd_tt(o):
         return abs((mp.mpf(tt.history[-1]) + mp.mpf(tt.history_lo[-1])) / d4 - 1) < 1e-25
 
 
+def pin_mc(o):
+    mcm = o["montecarlo"]
+    ests = mcm.estimators("ising_c", 2, 512, 16, mcm.RANDOM, seed=5)
+    mean, eps = mcm.error_estimate(ests)
+    if not abs(mean - 1.0) < 5 * eps * abs(mean) / 4:
+        return False
+    t, w = o["gauss"].gauss_legendre_01(64)
+    f = o["integrands"].f_values("ising_d", t.reshape(-1, 1))
+    sd = float(np.sqrt(np.dot(w, f * f) - np.dot(w, f) ** 2))
+    _, eps2 = mcm.error_estimate(mcm.estimators("ising_d", 2, 400, 40, mcm.RANDOM, seed=11))
+    x = mcm.lattice_points([1, 34], 89, mcm.shift(7, 0, 2))
+    return 0.65 < eps2 / (sd / 20 / np.dot(w, f)) < 1.35 and bool(np.all(x < 1))
+
+
 MUTATIONS = [
     # (file, original text, planted mistake, pin that must catch it)
     ("integrands.py", "a_d = a_d * ((1.0 - p) / (1.0 + p)) ** 2", "a_d = a_d * ((1.0 - p) / (1.0 + p))",
@@ -179,6 +194,10 @@ MUTATIONS = [
      "return DD(dd_sum(Fb[np.asarray(rows), :] * X.T, axis=1).hi)", pin_dd_tt),
     ("gauss.py", "return DD.from_mp(t), DD.from_mp(w)", "return DD.from_mp(t), DD([float(v) for v in w])",
      pin_dd_quad),
+    # Monte Carlo / lattice oracle
+    ("montecarlo.py", "    mean = sum(ests) / S", "    mean = sum(ests) / (S - 1)", pin_mc),
+    ("montecarlo.py", "return mean, math.sqrt(var) / abs(mean)", "return mean, var / abs(mean)", pin_mc),
+    ("montecarlo.py", "x[i - 1, k] = v - 1.0 if v >= 1.0 else v", "x[i - 1, k] = v", pin_mc),
 ]
 
 
