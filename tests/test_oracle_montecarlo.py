@@ -20,15 +20,28 @@ def test_points_are_uniform_in_the_open_unit_cube():
     assert not np.array_equal(x, mc.random_points(3, 1, 4000, 3))
 
 
+def sd_of_f(family, d, params=None):
+    """Standard deviation of f over [0,1]^m by a tensor Gauss--Legendre rule (m <= 4)."""
+    import itertools
+    m = d - 1 if family.startswith("ising") else d
+    t, w = gauss_legendre_01(24)
+    idx = np.array(list(itertools.product(range(24), repeat=m)))
+    f = f_values(family, t[idx], params)
+    wt = np.prod(w[idx], axis=1)
+    mean = np.dot(wt, f)
+    return math.sqrt(np.dot(wt, f * f) - mean ** 2)
+
+
 def test_monte_carlo_is_unbiased_against_exact_integrals():
-    # the mean of S estimators lies within a few of its own standard errors of the integral
+    # the mean of S estimators of N points lies within 5 sd(f)/sqrt(N S) of the integral
     cases = [("ising_c", 2, None, 1.0), ("ising_d", 2, None, 1.0 / 3.0)]
     p = synthetic_params(4, 9)
     cases.append(("sum2_exp_cos", 4, p, exact_synthetic("sum2_exp_cos", p, 4)))
+    N, S = 512, 16
     for family, d, params, exact in cases:
-        ests = mc.estimators(family, d, 512, 16, mc.RANDOM, seed=5, params=params)
+        ests = mc.estimators(family, d, N, S, mc.RANDOM, seed=5, params=params)
         mean, eps = mc.error_estimate(ests)
-        assert abs(mean - exact) < 5 * eps * abs(mean) / math.sqrt(len(ests)), (family, mean, exact, eps)
+        assert abs(mean - exact) < 5 * sd_of_f(family, d, params) / math.sqrt(N * S), (family, mean, exact)
 
 
 def test_error_estimate_matches_the_variance_of_f():

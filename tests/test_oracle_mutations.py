@@ -152,11 +152,12 @@ def pin_dd_tt(o):
 
 def pin_mc(o):
     mcm = o["montecarlo"]
-    ests = mcm.estimators("ising_c", 2, 512, 16, mcm.RANDOM, seed=5)
-    mean, eps = mcm.error_estimate(ests)
-    if not abs(mean - 1.0) < 5 * eps * abs(mean) / 4:
-        return False
     t, w = o["gauss"].gauss_legendre_01(64)
+    fc = o["integrands"].f_values("ising_c", t.reshape(-1, 1))
+    sd_c = float(np.sqrt(np.dot(w, fc * fc) - np.dot(w, fc) ** 2))
+    mean, _ = mcm.error_estimate(mcm.estimators("ising_c", 2, 512, 16, mcm.RANDOM, seed=5))
+    if not abs(mean - 1.0) < 5 * sd_c / np.sqrt(512 * 16):     # C_2 = 1
+        return False
     f = o["integrands"].f_values("ising_d", t.reshape(-1, 1))
     sd = float(np.sqrt(np.dot(w, f * f) - np.dot(w, f) ** 2))
     _, eps2 = mcm.error_estimate(mcm.estimators("ising_d", 2, 400, 40, mcm.RANDOM, seed=11))
