@@ -196,13 +196,31 @@ tt_status tt_eval_fibers(tt_ctx *ctx, const tt_problem *problem, int32_t pos,
                          const int32_t *d_left, int32_t r_left,
                          const int32_t *d_right, int32_t r_right, double *d_out);
 
+/* Equal-weight quadratures of Sec. 4.2, the baselines the paper compares the
+ * cross with: Monte Carlo (kind TT_MC_RANDOM, eq. mc) and a randomly shifted
+ * rank-1 lattice rule (kind TT_MC_LATTICE, eq. qmc, x_i = frac(i q / N + s),
+ * i = 1..N) for the caller's generating vector gen[m] (host, reduced mod N).
+ * n_sets estimators of n_points points each (independent points, or
+ * independent shifts of one lattice) are computed in one launch; estimates
+ * (host, n_sets doubles) receives them, *mean their mean and *rel_err the
+ * relative empirical standard deviation of eq. std.  The integrand is the
+ * problem's f without weights (n_nodes, rank_cap and tol are not used; seed keys
+ * the generator).  Double precision only.  Synchronises.
+ * Errors: TT_EINVAL (invalid problem, n_points < 1 or >= 2^31, n_sets < 2 or
+ * > 4096, missing gen for a lattice, TT_DD), TT_ENOMEM, TT_EDEVICE. */
+enum { TT_MC_RANDOM = 0, TT_MC_LATTICE = 1 };
+tt_status tt_mc_integrate(tt_ctx *ctx, const tt_problem *problem, int32_t kind, int64_t n_points,
+                          int32_t n_sets, const int64_t *gen, double *estimates, double *mean,
+                          double *rel_err);
+
 /* Optional per-kernel timing with HIP events recorded on the context stream
  * around every launch (adds two event records per launch).  tt_ctx_profile
  * switches it on or off and clears the totals; tt_ctx_kernel_time returns the
  * number of timed launches and their summed duration in ms for a kernel kind:
  * 0 sweep (pivot search, core updates, quadrature and stopping rule fused in
  * one launch per sweep), 1 core update at init, 2 quadrature at init,
- * 3 rank-1 start, 4 Gauss--Legendre nodes, 5 tt_eval_points, 6 tt_eval_fibers.
+ * 3 rank-1 start, 4 Gauss--Legendre nodes, 5 tt_eval_points, 6 tt_eval_fibers,
+ * 7 tt_mc_integrate.
  * Errors: TT_EINVAL (bad kind or NULL outputs). */
 tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
 tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);

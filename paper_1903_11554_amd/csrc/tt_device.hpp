@@ -126,6 +126,17 @@ __device__ __forceinline__ uint64_t sample_counter(int sweep, int bond, int j) {
 __device__ __forceinline__ uint64_t start_counter(int q, int k) {
   return (1ull << 63) + ((uint64_t)q << 16) + (uint64_t)k;
 }
+// Monte Carlo point i of estimator j (m coordinates), and the lattice shifts
+__device__ __forceinline__ uint64_t mc_counter(int j, int64_t i, int m, int k) {
+  return (1ull << 62) + ((uint64_t)j << 40) + (uint64_t)i * (uint64_t)m + (uint64_t)k;
+}
+__device__ __forceinline__ uint64_t shift_counter(int j, int k) {
+  return (1ull << 62) + (1ull << 61) + ((uint64_t)j << 6) + (uint64_t)k;
+}
+// a draw mapped to (0, 1): the top 53 bits, centred in their cell
+__device__ __forceinline__ double uniform_open01(uint64_t u) {
+  return ((double)(u >> 11) + 0.5) * 0x1.0p-53;
+}
 
 // ---------------------------------------------------------------- integrands
 // y[0..m) holds the coordinates of one point (entries >= m are ignored).

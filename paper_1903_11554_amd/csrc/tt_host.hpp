@@ -34,7 +34,7 @@ inline hipError_t& last_hip_error() {
 
 // kernel kinds timed by the optional event profiler
 enum { KK_SWEEP = 0, KK_UPDATE = 1, KK_INTEGRAL = 2, KK_START = 3, KK_GL = 4, KK_EVAL_POINTS = 5,
-       KK_EVAL_FIBERS = 6, KK_COUNT = 7 };
+       KK_EVAL_FIBERS = 6, KK_MC = 7, KK_COUNT = 8 };
 
 struct tt_ctx {
   int device = 0;
@@ -57,6 +57,8 @@ struct tt_ctx {
   std::multimap<size_t, void*> pinned;             // freed pinned host blocks kept for reuse
   size_t pinned_cached = 0;
   std::vector<hipEvent_t> ring_pool;               // timing-less events kept for reuse
+  double* mc_buf = nullptr;                        // device scratch of tt_mc_integrate
+  size_t mc_cap = 0;
   size_t arena_bytes_cached = 0;
 };
 

@@ -1148,4 +1148,70 @@ __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa_in, int n,
   }
 }
 
+// ------------------------------------------------- equal-weight quadrature
+// Monte Carlo (eq. mc) and randomly shifted rank-1 lattice rules (eq. qmc),
+// Sec. 4.2.  Estimator j = blockIdx.y sums f over its N points: random points
+// (kind 0) drawn from the counter-based generator, or x_i = frac(i q / N + s_j)
+// for i = 1..N (kind 1), with (i q_k) mod N in exact integer arithmetic.  Each
+// workgroup writes one partial sum; k_mc_finish adds them in a fixed order.
+template <int FAM, int MAXM>
+__global__ __launch_bounds__(kBlock) void k_mc(FamilyArgs fa, int kind, int64_t N, const int64_t* __restrict__ gen,
+                                               uint64_t seed, double* __restrict__ partial) {
+  __shared__ double sshift[TT_MAX_MODES];
+  __shared__ double red[kBlock / kWave];
+  const int j = blockIdx.y, m = fa.m, tid = threadIdx.x;
+  if (tid < m) sshift[tid] = uniform_open01(splitmix_at(seed, shift_counter(j, tid)));
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + tid; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    double y[MAXM];
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+      double v = 0.0;
+      if (k < m) {
+        if (kind == 0) {
+          v = uniform_open01(splitmix_at(seed, mc_counter(j, i, m, k)));
+        } else {
+          const uint64_t r = ((uint64_t)(i + 1) * (uint64_t)gen[k]) % (uint64_t)N;
+          v = (double)r / (double)N + sshift[k];
+          v = (v >= 1.0) ? v - 1.0 : v;
+        }
+      }
+      y[k] = v;
+    }
+    acc += integrand_fam<double, FAM, MAXM>(fa, y);
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  if ((tid & (kWave - 1)) == 0) red[tid / kWave] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) sum += red[w];
+    partial[(size_t)j * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
+// out[j] = (sum of the partial sums of estimator j) / N for j < S, then
+// out[S] = their mean and out[S+1] = the relative standard deviation (eq. std).
+static __global__ __launch_bounds__(kBlock) void k_mc_finish(const double* __restrict__ partial, int blocks, int S,
+                                                             int64_t N, double* __restrict__ out) {
+  for (int j = threadIdx.x; j < S; j += blockDim.x) {
+    double sum = 0.0;
+    for (int b = 0; b < blocks; ++b) sum += partial[(size_t)j * blocks + b];
+    out[j] = sum / (double)N;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mean = 0.0;
+    for (int j = 0; j < S; ++j) mean += out[j];
+    mean = mean / S;
+    double var = 0.0;
+    for (int j = 0; j < S; ++j) var += (out[j] - mean) * (out[j] - mean);
+    var = var / (S - 1);
+    out[S] = mean;
+    out[S + 1] = sqrt(var) / fabs(mean);
+  }
+}
+
 }  // namespace ttx

@@ -237,6 +237,7 @@ void tt_ctx_destroy(tt_ctx* c) {
   for (auto& kv : c->arenas) hipFree(kv.second);
   for (auto& kv : c->pinned) hipHostFree(kv.second);
   for (hipEvent_t e : c->ring_pool) hipEventDestroy(e);
+  if (c->mc_buf) hipFree(c->mc_buf);
   for (auto& pe : c->pending) {
     hipEventDestroy(pe.second.first);
     hipEventDestroy(pe.second.second);
@@ -713,6 +714,69 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
     eval_fibers_f<double, FAM_SYNTH>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right,
                                      d_out);
   TT_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+tt_status tt_mc_integrate(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_t n_points, int32_t n_sets,
+                          const int64_t* gen, double* estimates, double* mean, double* rel_err) {
+  if (!ctx || validate(p) != TT_OK || p->precision != TT_FP64) return TT_EINVAL;
+  if (kind != TT_MC_RANDOM && kind != TT_MC_LATTICE) return TT_EINVAL;
+  if (n_points < 1 || n_points >= (int64_t(1) << 31) || n_sets < 2 || n_sets > 4096) return TT_EINVAL;
+  if (kind == TT_MC_LATTICE && !gen) return TT_EINVAL;
+  if (!estimates || !mean || !rel_err) return TT_EINVAL;
+  const int m = modes_of(*p);
+  if (m < 1) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  TT_HIP(hipSetDevice(ctx->device));
+  FamilyArgs fa;
+  tt_status s = family_for(ctx, p, &fa);
+  if (s != TT_OK) return s;
+  const int blocks = (int)std::min<int64_t>((n_points + kBlock - 1) / kBlock, 256);
+  // scratch: partial sums [S x blocks], results [S + 2], generating vector [m]
+  const size_t need = sizeof(double) * ((size_t)n_sets * blocks + n_sets + 2) + sizeof(int64_t) * TT_MAX_MODES;
+  if (need > ctx->mc_cap) {
+    TT_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->mc_buf) TT_HIP(hipFree(ctx->mc_buf));
+    ctx->mc_buf = nullptr;
+    ctx->mc_cap = 0;
+    if (hipMalloc(&ctx->mc_buf, need) != hipSuccess) return TT_ENOMEM;
+    ctx->mc_cap = need;
+  }
+  double* partial = ctx->mc_buf;
+  double* out = partial + (size_t)n_sets * blocks;
+  int64_t* dgen = (int64_t*)(out + n_sets + 2);
+  if (kind == TT_MC_LATTICE) {
+    int64_t g[TT_MAX_MODES];
+    for (int k = 0; k < m; ++k) g[k] = ((gen[k] % n_points) + n_points) % n_points;
+    TT_HIP(hipStreamSynchronize(ctx->stream));   // the earlier upload source is a stack array
+    TT_HIP(hipMemcpy(dgen, g, sizeof(int64_t) * m, hipMemcpyHostToDevice));
+  }
+  const dim3 grid((unsigned)blocks, (unsigned)n_sets), block(kBlock);
+  const int fam = fam_of(p->integrand), mb = bucket_m(m);
+  {
+    Timed tm(ctx, KK_MC);
+#define TT_MC(F, M) \
+  hipLaunchKernelGGL((k_mc<F, M>), grid, block, 0, ctx->stream, fa, kind, n_points, dgen, p->seed, partial)
+#define TT_MC_M(F)               \
+  switch (mb) {                  \
+    case 8: TT_MC(F, 8); break;   \
+    case 16: TT_MC(F, 16); break; \
+    default: TT_MC(F, 32); break; \
+  }
+    if (fam == FAM_PAPER) { TT_MC_M(FAM_PAPER) }
+    else if (fam == FAM_UFORM) { TT_MC_M(FAM_UFORM) }
+    else { TT_MC_M(FAM_SYNTH) }
+#undef TT_MC_M
+#undef TT_MC
+    hipLaunchKernelGGL(k_mc_finish, dim3(1), block, 0, ctx->stream, partial, blocks, n_sets, n_points, out);
+  }
+  TT_HIP(hipGetLastError());
+  std::vector<double> h(n_sets + 2);
+  TT_HIP(hipMemcpyAsync(h.data(), out, sizeof(double) * (n_sets + 2), hipMemcpyDeviceToHost, ctx->stream));
+  TT_HIP(hipStreamSynchronize(ctx->stream));
+  for (int j = 0; j < n_sets; ++j) estimates[j] = h[j];
+  *mean = h[n_sets];
+  *rel_err = h[n_sets + 1];
   return TT_OK;
 }
 

@@ -68,11 +68,12 @@ EXPORTS = [
     "tt_cross_free", "tt_eval_points", "tt_eval_fibers", "tt_status_string",
     "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
     "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
-    "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue",
+    "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue", "tt_mc_integrate",
 ]
 
 KERNEL_KINDS = {"sweep": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
-                "eval_points": 5, "eval_fibers": 6}
+                "eval_points": 5, "eval_fibers": 6, "mc": 7}
+MC_RANDOM, MC_LATTICE = 0, 1
 
 _lib = None
 
@@ -119,6 +120,7 @@ def load_library():
         "tt_server_get_stats": (i32, [vp, P(_ServerStats)]),
         "tt_server_destroy": (None, [vp]),
         "tt_cross_enqueue": (i32, [vp, i32]),
+        "tt_mc_integrate": (i32, [vp, P(_Problem), i32, i64, i32, P(i64), P(dbl), P(dbl), P(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +198,19 @@ class Context:
 
     def job(self, problems):
         return Job(self, problems)
+
+    def mc_integrate(self, p: Problem, n_points, n_sets, kind=MC_RANDOM, gen=None):
+        """Monte Carlo / shifted lattice estimators: (estimates, mean, relative error)."""
+        keep = []
+        est = (ctypes.c_double * n_sets)()
+        mean, err = ctypes.c_double(), ctypes.c_double()
+        g = None
+        if gen is not None:
+            g = (ctypes.c_int64 * len(gen))(*[int(v) for v in gen])
+        _check(self._lib.tt_mc_integrate(self.handle, ctypes.byref(_c_problem(p, keep)), kind, n_points,
+                                         n_sets, g, est, ctypes.byref(mean), ctypes.byref(err)),
+               "tt_mc_integrate")
+        return list(est), mean.value, err.value
 
     def server(self, max_bytes=1 << 30, max_active=256):
         return Server(self, max_bytes, max_active)
