@@ -203,7 +203,7 @@ def run_gpu(args):
         ctx.close()
         return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
                     s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=None,
-                    errs={}, probs=probs, batch=None, dd=None, serving=None)
+                    errs={}, probs=probs, batch=None, dd=None, serving=None, mc=None)
 
     # the fibre-evaluation kernel alone on a large fibre set (D_10, middle mode)
     import numpy as np
@@ -245,6 +245,7 @@ def run_gpu(args):
 
     batch = run_batch(ctx)
     dd = run_dd(ctx)
+    mcres = run_mc(ctx, infos, probs)
     serving = run_serving(ctx, args.serve_seconds)
 
     refs = reference_values()
@@ -256,7 +257,45 @@ def run_gpu(args):
     ctx.close()
     return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
                 s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
-                errs=errs, probs=probs, batch=batch, dd=dd, serving=serving)
+                errs=errs, probs=probs, batch=batch, dd=dd, serving=serving, mc=mcres)
+
+
+def run_mc(ctx, tt_infos, tt_probs):
+    """Monte Carlo (Sec. 4.2) on D_10: throughput of the evaluation, and accuracy against the cross.
+
+    Throughput: 16 estimators of 2^20 random points (one launch).  Accuracy:
+    for D_8, Monte Carlo with as many evaluations as the cross needed, its
+    relative error estimate (eq. std) beside the cross's error against the
+    printed value.
+    """
+    import torch
+
+    from paper_1903_11554_amd.ttcross import MC_RANDOM
+    from paper_1903_11554_amd.workloads import Problem
+    p10 = Problem("ising_d", 10, 64, 32, 1e-10, seed=10)
+    n_pts, n_sets = 1 << 20, 16
+    ctx.mc_integrate(p10, n_pts, n_sets, MC_RANDOM)
+    t = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        ctx.mc_integrate(p10, n_pts, n_sets, MC_RANDOM)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    pts = n_pts * n_sets
+    tflops = pts * flops_per_eval("ising_d", 9, 0) / dt / 1e12
+    k8 = next(k for k, p in enumerate(tt_probs) if p.family == "ising_d" and p.d == 8)
+    ev8 = tt_infos[k8]["evals"]
+    p8 = Problem("ising_d", 8, 64, 32, 1e-10, seed=8)
+    _, mean8, err8 = ctx.mc_integrate(p8, max(ev8 // 16, 1), 16, MC_RANDOM)
+    return {"workload": "Monte Carlo, D_10, 16 estimators x 2^20 random points, one launch (with the finish "
+                        "and the copy back)",
+            "ms": dt * 1e3, "evals_per_s": pts / dt, "tflops": tflops, "frac": tflops / FP64_PEAK_TFLOPS,
+            "d8_same_evals": {"evals": ev8, "mc_rel_err_estimate": err8,
+                              "tt_rel_err_vs_printed": reference_errors_d8(tt_infos[k8]["value"])}}
+
+
+def reference_errors_d8(v):
+    return abs(v / reference_values()[("ising_d", 8)] - 1)
 
 
 def run_serving(ctx, seconds, warm_s=1.0, plain_sample=100):
@@ -507,6 +546,7 @@ def main():
         "batch_mixed64": r["batch"],
         "precision_dd": r["dd"],
         "serving": r["serving"],
+        "monte_carlo": r["mc"],
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(r["probs"], args.cpu_budget)
