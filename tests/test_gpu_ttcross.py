@@ -373,3 +373,18 @@ def test_bench_work_model_counts_the_device_evaluations():
         assert e == infos[k]["evals"] - 1024 - m * p.n, (p, e, infos[k]["evals"])
         assert f > 0 and nbytes > 0
     job.free()
+
+
+def test_zero_start_is_reported_as_a_numeric_error():
+    """Every start sample underflows to zero: tt_cross_init fails with TT_ENUMERIC (no fault, no hang)."""
+    from paper_1903_11554_amd.ttcross import TT_ENUMERIC, TTError
+    ctx = gpu_context()
+    params = {"a": [1e7, 1e7, 1e7], "b": [0.0, 0.0, 0.0]}    # prod exp(-1e7 x_j) underflows at every node
+    with pytest.raises(TTError) as exc:
+        ctx.job([Problem("prod_exp", 3, 8, 4, 1e-10, params=params)])
+    assert exc.value.status == TT_ENUMERIC
+    # the context stays usable
+    job = ctx.job([SMALL[3]])
+    info = job.run()[0]
+    assert info["err_flags"] == 0 and info["reason"] in ("converged", "rank_cap")
+    job.free()
