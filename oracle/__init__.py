@@ -21,11 +21,15 @@ integrands   Ising integrands C_d, D_d, E_d (eqs. c/d/e, Sec. 5.1), the
 quadrature   Brute-force tensor-product quadrature (eq. quad_product).
 ttcross      Alg. 2 (matrix cross step: random + rook pivoting) run on every
              superblock at once with the previous sweep's index sets (Alg. 6),
-             and the TT quadrature as a product of 2d-1 matrices (Sec. 4.1).
+             and the TT quadrature as a product of 2d-1 matrices (Sec. 4.1),
+             with the folded weights and the chain scaled by exact powers
+             of two so that a thousand modes stay in the double range.
 ddarith      Double-double arithmetic on numpy arrays from the error-free
              transformations (Knuth two-sum, Dekker/Veltkamp two-product).
 ttcross_dd   The same TT cross with every value in double-double (the
              quadruple/multiple-precision runs of Sec. 5.2), paper form only.
+montecarlo   Monte Carlo and randomly shifted lattice rules with the
+             empirical error estimate (Sec. 4.2).
 
 Parity status of every function is listed in the module headers.  Functions
 pinned by closed forms, the paper's printed values or exact-recovery theorems

@@ -24,6 +24,16 @@ re-evaluates every core and cross matrix from the definition of B, and every
 approximate entry is computed as B(row, I_>b) @ solve(B(I_<=b, I_>b), B(I_<=b, col))
 with numpy's LU solve.
 
+Scaled weights and a scaled quadrature (the paper does not say how its
+1023-mode double-precision run keeps the folded weights in range): every
+folded weight is multiplied by 2^s, s the integer nearest log2 n (the weights
+sum to 1, so their mean becomes about 1), and the chain of Sec. 4.1 is brought
+back after every factor to a vector whose largest entry lies in [1/2, 1),
+counting the powers of two it removes.  The integral is the chain's value
+times 2^(E - s m).  Both scalings are exact, so for every size that does not
+leave the double range the decisions and the values are those of the unscaled
+computation, bit for bit.
+
 Readings of the paper where it is silent (also listed in the design doc):
   * start: rank 1 at the largest |B| among 1024 SplitMix64 samples of the grid;
   * samples: |R| = min(r_{b-1} n + n r_{b+1}, 1024), uniform over the superblock,
@@ -39,7 +49,9 @@ Readings of the paper where it is silent (also listed in the design doc):
 
 Pinned by: exact integrals of rank-1 and rank-2 synthetic functions (Thm. 2),
 interpolation on every evaluated fiber (Thm. 1), brute-force tensor quadrature
-for small m, closed forms C_3, C_4, D_3, D_4 and the printed D_8.
+for small m, closed forms C_3, C_4, D_3, D_4 and the printed D_8; the scaled
+weights and chain by equality with the unscaled computation and by rank-1
+products of 1100 factors far below the double range.
 """
 
 import math
@@ -53,6 +65,38 @@ from .integrands import n_modes, weighted_values
 T_ROOK = 5
 MAX_SAMPLES = 1024
 N_START = 1024
+
+
+def weight_shift(n):
+    """The integer nearest log2 n: floor(log2(n sqrt 2))."""
+    return math.frexp(n * math.sqrt(2.0))[1] - 1
+
+
+def scaled_ldexp(mant, e):
+    """mant * 2^e as a double (0 below the range, +-inf above it)."""
+    try:
+        return math.ldexp(mant, e)
+    except OverflowError:
+        return math.copysign(math.inf, mant)
+
+
+def renormalise(v, e):
+    """Scale v by a power of two so that max |v| lies in [1/2, 1); returns (v, e + shift)."""
+    mx = float(np.max(np.abs(v))) if v.size else 0.0
+    if mx > 0.0 and math.isfinite(mx):
+        k = math.frexp(mx)[1]
+        v = np.ldexp(v, -k)
+        e += k
+    return v, e
+
+
+def rel_change_scaled(cur, prev):
+    """|I_s - I_{s-1}| / |I_s| for values given as (mantissa, exponent) pairs."""
+    mc, ec = cur
+    mp_, ep = prev
+    if mc == 0.0:
+        return math.inf
+    return abs(mc - scaled_ldexp(mp_, ep - ec)) / abs(mc)
 
 
 class PivotRecord:
@@ -78,8 +122,9 @@ class TTCross:
     """Alg. 6 (one superblock per process) over the weighted tensor B."""
 
     def __init__(self, family, d, n, rank_cap, tol, seed, max_sweeps=0, params=None,
-                 t_rook=T_ROOK, max_samples=MAX_SAMPLES, n_start=N_START):
+                 t_rook=T_ROOK, max_samples=MAX_SAMPLES, n_start=N_START, scale_weights=True):
         self.family, self.d, self.n = family, d, n
+        self.wshift = weight_shift(n) if scale_weights else 0
         self.rank_cap, self.tol, self.seed = rank_cap, tol, seed
         self.max_sweeps = max_sweeps if max_sweeps > 0 else 4 * rank_cap
         self.params = params
@@ -93,6 +138,7 @@ class TTCross:
         self.sweeps = 0
         self.evals = 0
         self.history = []       # integral after the start and after every sweep
+        self.history_scaled = []  # the same as (mantissa, exponent): value = mantissa * 2^exponent
         self.rel_changes = []
         self.pivot_log = []     # one list of PivotRecord per sweep
         self.stop_reason = None
@@ -101,7 +147,8 @@ class TTCross:
 
     # ----------------------------------------------------------------- tensor
     def _nodes(self, n):
-        return gauss_legendre_01(n)
+        t, w = gauss_legendre_01(n)
+        return t, np.ldexp(w, self.wshift)
 
     def B(self, idx):
         idx = np.asarray(idx, dtype=np.int64)
@@ -129,13 +176,9 @@ class TTCross:
     # ------------------------------------------------------------ the start
     def _start(self):
         m, n = self.m, self.n
-        if m == 0:
-            self.history.append(float(self.B(np.zeros((1, 0), dtype=np.int64))[0]))
-            self.stop_reason = "converged"
-            return
-        if m == 1:
-            self.evals += n
-            self.history.append(float(np.sum(self.B(np.arange(n).reshape(n, 1)))))
+        if m <= 1:
+            self.evals += n if m == 1 else 0
+            self._record(self.integral_scaled())
             self.stop_reason = "converged"
             return
         idx = np.empty((self.n_start, m), dtype=np.int64)
@@ -156,7 +199,11 @@ class TTCross:
             self.right[b].append(i0[b + 1:])
             self.scale[b] = abs(float(vals[q]))
         self._count_new_core_entries()
-        self.history.append(self.integral())
+        self._record(self.integral_scaled())
+
+    def _record(self, scaled):
+        self.history_scaled.append(scaled)
+        self.history.append(scaled_ldexp(*scaled))
 
     def _count_new_core_entries(self, recs=()):
         """Count the entries the core updates evaluate after the sets grew.
@@ -178,18 +225,27 @@ class TTCross:
         self.evals -= reused
 
     # ------------------------------------------------------------ quadrature
-    def integral(self):
-        """Product of 2m-1 matrices (Sec. 4.1) with weights folded into B."""
+    def integral_scaled(self):
+        """Product of 2m-1 matrices (Sec. 4.1) with weights folded into B, as (mantissa, exponent).
+
+        The running vector is rescaled by a power of two after every factor;
+        the exponent collects those powers and the weights' 2^(-s m).
+        """
         if self.m == 0:
-            return self.history[0]
-        if self.m == 1:
-            return float(np.sum(self.B(np.arange(self.n).reshape(self.n, 1))))
-        v = self.core(0).sum(axis=1)                      # 1 x r_0
-        for c in range(1, self.m):
-            M = self.cross_matrix(c - 1)                  # r_{c-1} x r_{c-1}
-            v = np.linalg.solve(M.T, v.T).T               # v [M]^-1
-            v = v @ self.core(c).sum(axis=1)              # r_{c-1} x r_c
-        return float(v[0, 0])
+            v, e = np.array([[float(self.B(np.zeros((1, 0), dtype=np.int64))[0])]]), 0
+        elif self.m == 1:
+            v, e = np.array([[float(np.sum(self.B(np.arange(self.n).reshape(self.n, 1))))]]), 0
+        else:
+            v, e = renormalise(self.core(0).sum(axis=1), 0)          # 1 x r_0
+            for c in range(1, self.m):
+                M = self.cross_matrix(c - 1)                         # r_{c-1} x r_{c-1}
+                v = np.linalg.solve(M.T, v.T).T                      # v [M]^-1
+                v, e = renormalise(v @ self.core(c).sum(axis=1), e)  # r_{c-1} x r_c
+        mant, k = math.frexp(float(v[0, 0]))
+        return mant, e + k - self.wshift * self.m
+
+    def integral(self):
+        return scaled_ldexp(*self.integral_scaled())
 
     # ------------------------------------------------ Alg. 2 on superblock b
     def cross_step(self, b, sweep, cores):
@@ -282,10 +338,9 @@ class TTCross:
         self.pivot_log.append(recs)
         self.sweeps += 1
         self._count_new_core_entries(recs)
-        value = self.integral()
-        prev = self.history[-1]
-        rel = abs(value - prev) / abs(value) if value != 0.0 else math.inf
-        self.history.append(value)
+        value = self.integral_scaled()
+        rel = rel_change_scaled(value, self.history_scaled[-1])
+        self._record(value)
         prev_rel = self.rel_changes[-1] if self.rel_changes else math.inf
         self.rel_changes.append(rel)
         if rel <= self.tol and prev_rel <= self.tol:

@@ -16,7 +16,10 @@ stopping rule on the relative change of the integral, computed in
 double-double and rounded to a double.  Everything else (the readings of the
 start, the samples, the rook budget, the stopping rule) is that of the double
 oracle.  Only the paper-form Ising integrands (eqs. c, d, e) have a
-double-double evaluation.
+double-double evaluation.  The folded weights carry the double oracle's exact
+factor 2^s (s the integer nearest log2 n), removed from the quadrature at the
+end; no double-double size here leaves the double exponent range, so the
+chain needs no rescaling.
 
 As in the double oracle nothing is incremental: every sweep re-evaluates the
 cores and cross matrices from the definition of B, and every approximate entry
@@ -52,7 +55,12 @@ class TTCrossDD(TTCross):
 
     # ----------------------------------------------------------------- tensor
     def _nodes(self, n):
-        return gauss_legendre_01_dd(n)
+        t, w = gauss_legendre_01_dd(n)
+        return t, DD(np.ldexp(w.hi, self.wshift), np.ldexp(w.lo, self.wshift))   # exact scaling
+
+    def _unscale(self, v):
+        k = -self.wshift * self.m
+        return DD(np.ldexp(v.hi, k), np.ldexp(v.lo, k))
 
     def B(self, idx):
         idx = np.asarray(idx, dtype=np.int64)
@@ -75,7 +83,7 @@ class TTCrossDD(TTCross):
             return
         if m == 1:
             self.evals += n
-            self._record(dd_sum(self.B(np.arange(n).reshape(n, 1)), axis=0))
+            self._record(self._unscale(dd_sum(self.B(np.arange(n).reshape(n, 1)), axis=0)))
             self.stop_reason = "converged"
             return
         idx = np.empty((self.n_start, m), dtype=np.int64)
@@ -110,7 +118,7 @@ class TTCrossDD(TTCross):
             for a in range(S.shape[0]):
                 acc = acc + v[:, a:a + 1] * S[a:a + 1, :]
             v = acc
-        return v[0, 0]
+        return self._unscale(v[0, 0])
 
     def integral(self):
         if self.m <= 1:

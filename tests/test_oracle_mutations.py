@@ -165,6 +165,28 @@ def pin_mc(o):
     return 0.65 < eps2 / (sd / 20 / np.dot(w, f)) < 1.35 and bool(np.all(x < 1))
 
 
+def pin_scaled_weights(o):
+    tt = o["ttcross"]
+    a = tt.TTCross("ising_d", 5, 10, 6, 1e-12, seed=3, max_sweeps=3)
+    b = tt.TTCross("ising_d", 5, 10, 6, 1e-12, seed=3, max_sweeps=3, scale_weights=False)
+    a.run()
+    b.run()
+    return a.history == b.history
+
+
+def pin_scaled_chain(o):
+    d, n = 300, 16
+    a = np.random.default_rng(7).uniform(0.05, 0.3, d)
+    tt = o["ttcross"].solve("prod_exp", d, n, 2, 1e-12, seed=1, max_sweeps=2,
+                            params={"a": list(a), "b": [1.0] * d})
+    t, w = o["gauss"].gauss_legendre_01(n)
+    log_q = sum(np.log(np.dot(w, np.exp(-aj * t))) for aj in a)
+    mant, e = tt.history_scaled[-1]
+    if not 0.5 <= mant < 1.0:
+        return False
+    return bool(abs(np.log(mant) + e * np.log(2.0) - log_q) < 1e-10 * abs(log_q))
+
+
 MUTATIONS = [
     # (file, original text, planted mistake, pin that must catch it)
     ("integrands.py", "a_d = a_d * ((1.0 - p) / (1.0 + p)) ** 2", "a_d = a_d * ((1.0 - p) / (1.0 + p))",
@@ -183,6 +205,9 @@ MUTATIONS = [
      "w.append(2 / ((1 - x * x) * dp * dp))", pin_gl),                       # interval map
     ("rng.py", "GAMMA = 0x9E3779B97F4A7C15", "GAMMA = 0x9E3779B97F4A7C13", pin_rng),
     ("rng.py", "z = ((z ^ (z >> 27)) * M2) & MASK", "z = ((z ^ (z >> 28)) * M2) & MASK", pin_rng),
+    ("ttcross.py", "return mant, e + k - self.wshift * self.m", "return mant, e + k",
+     pin_scaled_weights),                                                    # weight scale kept
+    ("ttcross.py", "v = np.ldexp(v, -k)", "v = np.ldexp(v, k)", pin_scaled_chain),   # wrong-way rescale
     # double-double oracle
     ("ddarith.py", "e = e + (self.hi * y.lo + self.lo * y.hi)", "e = e + self.hi * y.lo", pin_dd_ops),
     ("ddarith.py", "SPLITTER = 134217729.0", "SPLITTER = 67108865.0", pin_dd_ops),

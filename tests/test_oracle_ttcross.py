@@ -55,8 +55,9 @@ def test_rank2_exact_recovery(d):
     q_n = tensor_quadrature("sum2_exp_cos", d, n, params)
     assert abs(tt.history[-1] - q_n) < 1e-13 * abs(q_n)
     # after rank 2 is reached, every search sees only rounding-level errors
+    # (pivot errors are entries of the tensor with scaled weights, 2^(s m) B)
     late = [abs(r.err) for sweep in tt.pivot_log[1:] for r in sweep if r.searched]
-    assert all(e < 1e-14 * abs(q_n) for e in late)
+    assert all(e < 1e-14 * abs(q_n) * 2.0 ** (tt.wshift * tt.m) for e in late)
     # n = 6 is not enough for the exact integral: only the tensor sum is exact
     assert abs(q_n - exact) < 1e-3
 
@@ -217,3 +218,40 @@ def test_update_evaluations_exclude_the_reused_rook_fibres():
         assert tt.evals - ev0 - search == sum(len(new[c]) - len(reused[c]) for c in range(tt.m))
         checked += sum(len(x) for x in reused)
     assert checked > 0
+
+
+@pytest.mark.parametrize("family,d,n,params", [
+    ("ising_c", 6, 12, None), ("ising_d", 5, 10, None),
+    ("sum2_exp_cos", 6, 8, {"a": [0.7, 1.9, 3.1, 0.9, 2.2, 1.4], "b": [1.3, 0.6, 2.4, 3.3, 1.1, 2.8]})])
+def test_scaled_weights_give_the_unscaled_computation_bit_for_bit(family, d, n, params):
+    # the weights carry an exact factor 2^s and the chain exact powers of two:
+    # every decision and every value must be the unscaled one (values times 2^(s m))
+    a = ttcross.TTCross(family, d, n, 8, 1e-12, seed=3, max_sweeps=4, params=params)
+    b = ttcross.TTCross(family, d, n, 8, 1e-12, seed=3, max_sweeps=4, params=params, scale_weights=False)
+    a.run()
+    b.run()
+    k = a.wshift * a.m
+    assert a.wshift == round(math.log2(n)) and b.wshift == 0
+    assert a.history == b.history and a.stop_reason == b.stop_reason and len(a.history) > 2
+    for sa, sb in zip(a.pivot_log, b.pivot_log):
+        for ra, rb in zip(sa, sb):
+            assert (ra.row, ra.col, ra.accepted, ra.iters) == (rb.row, rb.col, rb.accepted, rb.iters)
+            assert ra.err == math.ldexp(rb.err, k) and ra.value == math.ldexp(rb.value, k)
+
+
+def test_rank1_product_of_300_modes_through_the_scaled_chain():
+    # Thm. 2 (exact recovery at rank 1): the TT quadrature of a product function
+    # is the product of its 1-D Gauss-Legendre sums.  Unscaled, the folded
+    # weights' sum over the grid (16^300 times the integral, about 1e350) would
+    # overflow; the scaled chain must still give the product to rounding.
+    from oracle.gauss import gauss_legendre_01
+    d, n = 300, 16
+    a = np.random.default_rng(7).uniform(0.05, 0.3, d)
+    tt = ttcross.solve("prod_exp", d, n, 2, 1e-12, seed=1, max_sweeps=2,
+                       params={"a": list(a), "b": [1.0] * d})
+    t, w = gauss_legendre_01(n)
+    log_q = math.fsum(math.log(float(np.dot(w, np.exp(-aj * t)))) for aj in a)
+    mant, e = tt.history_scaled[-1]
+    assert 0.5 <= abs(mant) < 1.0 and max(tt.ranks()) == 1
+    assert abs(math.log(mant) + e * math.log(2.0) - log_q) < 1e-12 * abs(log_q)
+    assert tt.history[-1] == math.ldexp(mant, e)
