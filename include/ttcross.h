@@ -11,6 +11,10 @@
  * superblock runs one step of Alg. 2 (random then rook pivoting, eq. rook)
  * against the previous sweep's index sets, and accepted pivots are appended
  * after the sweep.  The integral is the product of 2m-1 matrices of Sec. 4.1.
+ * Inside a job the folded weights are the rule's times 2^s, s the integer
+ * nearest log2 n (their mean becomes about 1; exact, so no decision changes),
+ * and the chain of matrices is rescaled by exact powers of two: the values of
+ * B that the pivot log reports carry the factor 2^(s m); the integral does not.
  *
  * All compute runs in HIP kernels on the device; the host code only validates,
  * allocates and launches.  Every function returns a tt_status (or a plain value
@@ -73,8 +77,15 @@ typedef enum { TT_FP64 = 0, TT_DD = 1 } tt_precision;
 /* Stop reasons reported in tt_info.reason. */
 enum { TT_RUNNING = 0, TT_STOP_CONVERGED = 1, TT_STOP_RANK_CAP = 2, TT_STOP_MAX_SWEEPS = 3 };
 
-/* Library limits (a problem beyond them is rejected with TT_EINVAL). */
-#define TT_MAX_MODES 32
+/* Library limits (a problem beyond them is rejected with TT_EINVAL).
+ * Jobs take up to TT_MAX_MODES modes.  Above TT_MAX_REG_MODES the kernels read
+ * the coordinates of every point from the index-set rows in device memory one
+ * at a time (the paper's 1023-mode C_1024 of Sec. 5.3 is such a job); that path
+ * covers the paper-form and synthetic integrands in TT_FP64.  Double-double
+ * jobs, the u-form integrands, tt_eval_points/tt_eval_fibers, tt_mc_integrate
+ * and the serving loop take at most TT_MAX_REG_MODES modes. */
+#define TT_MAX_MODES 1024
+#define TT_MAX_REG_MODES 32
 #define TT_MAX_RANK 64
 #define TT_MAX_NODES 256
 
@@ -101,6 +112,9 @@ typedef struct {
   double  value;       /* integral estimate (TT_DD: its leading double)                   */
   double  rel_change;  /* |I_s - I_{s-1}| / |I_s| of the last sweep                       */
   double  value_lo;    /* TT_DD: the low double of the estimate (value + value_lo); else 0 */
+  double  value_mant;  /* the estimate is value_mant * 2^value_exp2 exactly (TT_DD: its    */
+  int32_t value_exp2;  /*   leading double), 1/2 <= |value_mant| < 1 or 0; value and       */
+  int32_t reserved;    /*   value_lo are 0 or +-inf when the estimate leaves the double range */
 } tt_info;
 
 /* One accepted-or-rejected pivot search of one superblock in one sweep.
@@ -110,8 +124,9 @@ typedef struct {
   int32_t row, col;    /* pivot position in the superblock (-1: not searched)            */
   int32_t accepted;    /* 1 if appended to the index sets                                 */
   int32_t iters;       /* rook (column,row) pairs used, 1..5; 0 if not searched            */
-  double  err;         /* B - B~ at the pivot (signed; TT_DD: leading double)             */
-  double  value;       /* B at the pivot (TT_DD: leading double)                          */
+  double  err;         /* B - B~ at the pivot, B with the job's weights (times 2^(s m));
+                          signed; TT_DD: leading double                                   */
+  double  value;       /* B at the pivot (same scale; TT_DD: leading double)              */
   int32_t col_fresh;   /* 1 if the last column step of the rook loop was at `col`: its
                           values are the new column of the core left of the bond       */
   int32_t reserved;
@@ -133,7 +148,8 @@ size_t tt_job_footprint(const tt_problem *problem);
  * serves all of them).  Generates the Gauss--Legendre nodes, draws the rank-1
  * start of each integral (largest |B| among 1024 SplitMix64 grid samples),
  * evaluates the first cores and the first quadrature value.  Synchronises.
- * Errors: TT_EINVAL (bad problem: d < 1, modes > TT_MAX_MODES, n or rank out of
+ * Errors: TT_EINVAL (bad problem: d < 1, modes > TT_MAX_MODES (> TT_MAX_REG_MODES
+ * for TT_DD and the u-form), n or rank out of
  * range, tol <= 0, unknown integrand or precision, TT_DD for an integrand
  * without a double-double path, precisions mixed in one job, missing params),
  * TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC (all start samples zero or non-finite). */
@@ -163,13 +179,16 @@ tt_status tt_cross_integrate(tt_job *job, double *values, tt_info *info);
 /* Diagnostics for tests: the pivot log of integral k (sweeps x (m-1) records,
  * host buffer of `capacity` records, *written = records copied), the
  * integral after the start and after each sweep (sweeps+1 values: leading
- * doubles in `values`, low doubles in `values_lo` if not NULL, 0 for TT_FP64), and the
+ * doubles in `values`, low doubles in `values_lo` if not NULL, 0 for TT_FP64;
+ * with exp2 not NULL, values and values_lo receive mantissas and exp2 the
+ * powers of two, value = (values + values_lo) * 2^exp2, for integrals outside
+ * the double range), and the
  * index sets: for bond b the left set I_<=b as rows of (b+1) node indices and
  * the right set I_>b as rows of (m-b-1) node indices, packed bond by bond
  * (left then right), each row in insertion order; ranks[m-1] receives r_b. */
 tt_status tt_job_pivot_log(tt_job *job, int32_t k, tt_pivot *log, int64_t capacity, int64_t *written);
-tt_status tt_job_history(tt_job *job, int32_t k, double *values, double *values_lo, int64_t capacity,
-                         int64_t *written);
+tt_status tt_job_history(tt_job *job, int32_t k, double *values, double *values_lo, int32_t *exp2,
+                         int64_t capacity, int64_t *written);
 tt_status tt_job_index_sets(tt_job *job, int32_t k, int32_t *ranks, int32_t *nodes,
                             int64_t capacity, int64_t *written);
 /* Gauss--Legendre nodes and weights of integral k as generated on the device, n

@@ -5,6 +5,8 @@
 //   * the integrands of the Ising family (eqs. c, d, e of Sec. 5.1), their
 //     u-form, and the synthetic product families, evaluated one point per lane
 //     with the coordinates held in registers,
+//   * the same integrands over coordinates produced one at a time, for any
+//     number of modes (the streaming path of large integrals),
 //   * workgroup argmax / max reductions for 64-wide wavefronts.
 // All floating-point code is compiled with contraction off; every FMA below is
 // written explicitly, so a point gets the same bits in every kernel.
@@ -97,6 +99,9 @@ __device__ __forceinline__ double n_mad(double a, double b, double c) { return f
 __device__ __forceinline__ dd n_mad(dd a, dd b, dd c) { return dd_add(dd_mul(a, b), c); }
 __device__ __forceinline__ double n_nmad(double a, double b, double c) { return fma(-a, b, c); }
 __device__ __forceinline__ dd n_nmad(dd a, dd b, dd c) { return dd_sub(c, dd_mul(a, b)); }
+// exact scaling by 2^e (both parts of a double-double)
+__device__ __forceinline__ double n_ldexp(double a, int e) { return ldexp(a, e); }
+__device__ __forceinline__ dd n_ldexp(dd a, int e) { return {ldexp(a.hi, e), ldexp(a.lo, e)}; }
 __device__ __forceinline__ double n_shfl(double a, int lane) { return __shfl(a, lane, kWave); }
 __device__ __forceinline__ dd n_shfl(dd a, int lane) {
   return {__shfl(a.hi, lane, kWave), __shfl(a.lo, lane, kWave)};
@@ -277,6 +282,68 @@ __device__ __forceinline__ double integrand(const FamilyArgs& fa, const double (
     default:
       return synthetic<MAXM>(fa.family, fa.m, y, fa.a, fa.b);
   }
+}
+
+// ------------------------------------------------------ streaming integrands
+// Any number of modes: the coordinates come from an accessor y(k) (one load per
+// use, from the index-set rows in memory) instead of registers.
+//
+// Paper form.  B_d in one forward pass: the prefix sum q = sum_b y_0..y_b and
+// the suffix sum s = sum_a y_a..y_{m-1} by the recurrence s <- y_k (1 + s).
+// A_d over the runs y_a..y_b by their first index a; a run is left as soon as
+// its product p falls below 2^-54, since from there on p only decreases and
+// pn (1 - p), pd (1 + p) round back to pn and pd (the FMA's exact product is
+// below half an ulp), so stopping changes no bit.  pn and pd are brought back
+// by the same exact power of two every 32 factors and after every run.
+template <class Y>
+__device__ __forceinline__ double ising_paper_stream(int family, int m, const Y& y) {
+  double den = 1.0;
+  if (family != TT_ISING_E) {
+    double P = 1.0, q = 0.0, s = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const double yk = y(k);
+      P = P * yk;
+      q = q + P;
+      s = fma(yk, s, yk);
+    }
+    den = (1.0 + q) * (1.0 + s);
+  }
+  double nm = 2.0;
+  if (family != TT_ISING_C) {
+    double pn = 1.0, pd = 1.0;
+    for (int a = 0; a < m; ++a) {
+      double p = 1.0;
+      for (int b = a; b < m; ++b) {
+        p = p * y(b);
+        if (p < 0x1.0p-54) break;
+        pn = fma(-pn, p, pn);
+        pd = fma(pd, p, pd);
+        if (((b - a) & 31) == 31) {
+          const int e = ilogb(pd);
+          pn = ldexp(pn, -e);
+          pd = ldexp(pd, -e);
+        }
+      }
+      const int e = ilogb(pd);
+      pn = ldexp(pn, -e);
+      pd = ldexp(pd, -e);
+    }
+    const double r = pn / pd;
+    nm = nm * r * r;
+  }
+  return nm / den;
+}
+
+template <class Y>
+__device__ __forceinline__ double synthetic_stream(int family, int m, const Y& y, const double* __restrict__ a,
+                                                   const double* __restrict__ b) {
+  double s = 0.0;
+  for (int k = 0; k < m; ++k) s = fma(a[k], y(k), s);
+  const double e = exp(-s);
+  if (family == TT_PROD_EXP) return e;
+  double c = 1.0;
+  for (int k = 0; k < m; ++k) c = c * cos(b[k] * y(k));
+  return e + c;
 }
 
 // --------------------------------------------------------------- reductions

@@ -49,6 +49,8 @@ struct tt_ctx {
   struct GL {
     double *t, *w;     // nodes and weights rounded to double
     dd *t2, *w2;       // the same in double-double
+    double* ws;        // weights times 2^weight_shift(n), the scale jobs fold in
+    dd* ws2;
   };
   std::map<int, GL> gl;                            // n -> device tables
   double* params = nullptr;                        // device scratch for synthetic params
@@ -139,6 +141,8 @@ inline tt_status validate(const tt_problem* p) {
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return TT_EINVAL;
   if (p->precision != TT_FP64 && p->precision != TT_DD) return TT_EINVAL;
   if (p->precision == TT_DD && fam_of(p->integrand) != FAM_PAPER) return TT_EINVAL;
+  // beyond the register bucket only the streaming kernels (double, paper form and synthetic)
+  if (m > TT_MAX_REG_MODES && (p->precision != TT_FP64 || fam_of(p->integrand) == FAM_UFORM)) return TT_EINVAL;
   if (p->max_sweeps < 0 || p->max_sweeps > 1024) return TT_EINVAL;
   if (is_synthetic(p->integrand) && !p->params) return TT_EINVAL;
   // the superblock size r n n r must fit a 32-bit sample index
@@ -160,7 +164,7 @@ struct Layout {
 };
 
 struct ProbOffsets {
-  size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, LU, S, rank, piv, scale, log, hist, start, sync,
+  size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, LU, S, rank, piv, scale, log, hist, hexp, start, sync,
       phase;
   std::vector<int64_t> foff, coff;
 };
@@ -200,6 +204,7 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   o.scale = L.take((size_t)(nb > 0 ? nb : 1) * sizeof(double));
   o.log = L.take((size_t)ms * (nb > 0 ? nb : 1) * sizeof(PivRec));
   o.hist = L.take((size_t)(ms + 1) * D);
+  o.hexp = L.take((size_t)(ms + 1) * I);
   o.start = L.take((size_t)(m > 0 ? m : 1) * I);
   o.sync = L.take((size_t)(m + 1) * I);
   o.phase = L.take((size_t)ms * (nb > 0 ? nb : 1) * kPhases * sizeof(long long));
@@ -208,8 +213,10 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
 
 inline int bucket_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : 32; }
 // Mode bucket of the sweep kernels of one integrand class and number type
-// (must match the instantiations in tt_inst.hip).
+// (must match the instantiations in tt_inst.hip); 0 is the streaming bucket
+// for more modes than the register kernels hold.
 inline int bucket_m_for(int fam, bool dd, int m) {
+  if (m > TT_MAX_REG_MODES) return 0;
   if (fam == FAM_PAPER && !dd) return m <= 4 ? 4 : m <= 8 ? 8 : m <= 10 ? 10 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 24 ? 24 : 32;
   return bucket_m(m);
 }
@@ -221,20 +228,28 @@ inline double four_over_fact(int m) {
   return 4.0 / f;
 }
 
+// Power of two carried by the folded weights of a job: the integer nearest
+// log2 n, so that the weights (which sum to 1) have a mean of about 1.
+inline int weight_shift(int n) { return std::ilogb((double)n * 1.4142135623730951); }
+
 inline void fill_info(const ProbState& s, tt_info* out) {
   out->sweeps = s.sweeps;
   out->max_rank = s.max_rank;
   out->reason = s.done ? s.reason : TT_RUNNING;
   out->err_flags = s.err_flags;
   out->evals = (int64_t)s.evals;
-  out->value = s.value;
+  out->value = std::ldexp(s.value, s.vexp);
   out->rel_change = s.rel;
-  out->value_lo = s.value_lo;
+  out->value_lo = std::ldexp(s.value_lo, s.vexp);
+  out->value_mant = s.value;
+  out->value_exp2 = s.vexp;
+  out->reserved = 0;
 }
 
 // Node tables for n, generated on first use (defined in ttcross.hip).  With
-// want_dd the returned pointers are the double-double tables (as double*).
-tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd = false);
+// want_dd the returned pointers are the double-double tables (as double*);
+// with scaled the weights are the rule's times 2^weight_shift(n) (exact).
+tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd = false, bool scaled = false);
 
 inline tt_status family_for(tt_ctx* ctx, const tt_problem* p, FamilyArgs* fa) {
   const int m = modes_of(*p);
@@ -297,6 +312,7 @@ inline ProbDesc make_desc(const tt_problem& p, const ProbOffsets& o, char* pb, c
   d.R = p.rank_cap;
   d.max_sweeps = max_sweeps_of(p);
   d.nbonds = d.m > 1 ? d.m - 1 : 0;
+  d.wshift = weight_shift(p.n_nodes);
   d.tol = p.tol;
   d.four_over_mfact = four_over_fact(d.m);
   d.seed = p.seed;
@@ -323,6 +339,7 @@ inline ProbDesc make_desc(const tt_problem& p, const ProbOffsets& o, char* pb, c
   d.scale = (double*)(pb + o.scale);
   d.log = (PivRec*)(pb + o.log);
   d.hist = (double*)(pb + o.hist);
+  d.hexp = (int32_t*)(pb + o.hexp);
   d.start = (int32_t*)(pb + o.start);
   d.sync = (int32_t*)(pb + o.sync);
   d.done_host = done_host;

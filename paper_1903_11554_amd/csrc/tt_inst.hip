@@ -50,10 +50,13 @@ void by_rank(const LaunchArgs& a, int what, int rb) {
 
 // Mode buckets: the paper-form class in double (the Ising workloads) has fine
 // buckets, since every mode a kernel is compiled for beyond the problem's costs
-// a guarded loop step per run; the other classes share 8, 16, 32.
+// a guarded loop step per run; the other classes share 8, 16, 32.  Bucket 0 is
+// the streaming path for more modes than the registers hold (double only,
+// paper-form and synthetic integrands).
 void dispatch(const LaunchArgs& a, int what, int rb) {
 #if TT_FAM == 0 && !TT_INST_DD
   switch (a.mbucket) {
+    case 0: by_rank<0>(a, what, rb); break;
     case 4: by_rank<4>(a, what, rb); break;
     case 8: by_rank<8>(a, what, rb); break;
     case 10: by_rank<10>(a, what, rb); break;
@@ -64,6 +67,9 @@ void dispatch(const LaunchArgs& a, int what, int rb) {
   }
 #else
   switch (a.mbucket) {
+#if !TT_INST_DD && TT_FAM != 1
+    case 0: by_rank<0>(a, what, rb); break;
+#endif
     case 8: by_rank<8>(a, what, rb); break;
     case 16: by_rank<16>(a, what, rb); break;
     default: by_rank<32>(a, what, rb); break;

@@ -35,16 +35,18 @@ struct PivRec {
 };
 static_assert(sizeof(PivRec) == sizeof(tt_pivot), "PivRec must mirror tt_pivot");
 
+// The integral is value_mant * 2^vexp (with value_lo the low part of the
+// mantissa for double-double jobs), 1/2 <= |value| < 1 or value = 0.
 struct ProbState {
   int32_t sweeps, done, reason, err_flags;
-  int32_t nacc, max_rank, pad0, pad1;
+  int32_t nacc, max_rank, vexp, pad1;
   unsigned long long evals;
-  double value, rel, value_lo;   // value_lo: low part of the integral (double-double jobs)
+  double value, rel, value_lo;
 };
 
 struct ProbDesc {
   int32_t family, m, n, R;
-  int32_t max_sweeps, nbonds, pad0, pad1;
+  int32_t max_sweeps, nbonds, wshift, pad1;   // weights w are the rule's times 2^wshift
   double tol, four_over_mfact;
   uint64_t seed;
   const double *t, *w;                   // T: nodes and weights
@@ -62,7 +64,8 @@ struct ProbDesc {
   PivRec *piv;                           // [nbonds] current sweep's pivots
   double *scale;                         // [nbonds] largest |B| seen per bond
   PivRec *log;                           // [max_sweeps][nbonds]
-  double *hist;                          // T [max_sweeps+1]
+  double *hist;                          // T [max_sweeps+1] mantissas of the integral after each sweep
+  int32_t *hexp;                         // [max_sweeps+1] their exponents
   int32_t *start;                        // [m] start multi-index
   int32_t *sync;                         // [m+1] per-sweep dataflow counters (cores ready, cores done)
   int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
@@ -96,6 +99,7 @@ __device__ __forceinline__ void signal_done(const ProbDesc& p) {
     dst->err_flags = src->err_flags;
     dst->nacc = src->nacc;
     dst->max_rank = src->max_rank;
+    dst->vexp = src->vexp;
     dst->evals = src->evals;
     dst->value = src->value;
     dst->rel = src->rel;
@@ -131,6 +135,32 @@ __device__ __forceinline__ T integrand_fam(const FamilyArgs& fa, const T (&y)[MA
   } else {
     return integrand<MAXM>(fa, y);
   }
+}
+
+// Streaming path (MAXM = 0, any number of modes, double precision): the
+// paper-form and synthetic integrands over an accessor y(k).
+template <int FAM, class Y>
+__device__ __forceinline__ double integrand_stream(const FamilyArgs& fa, const Y& y) {
+  static_assert(FAM == FAM_PAPER || FAM == FAM_SYNTH || FAM == FAM_ANY, "no streaming u-form");
+  if constexpr (FAM == FAM_PAPER) {
+    return ising_paper_stream(fa.family, fa.m, y);
+  } else if constexpr (FAM == FAM_SYNTH) {
+    return synthetic_stream(fa.family, fa.m, y, fa.a, fa.b);
+  } else {
+    if (fa.family == TT_ISING_C || fa.family == TT_ISING_D || fa.family == TT_ISING_E)
+      return ising_paper_stream(fa.family, fa.m, y);
+    return synthetic_stream(fa.family, fa.m, y, fa.a, fa.b);
+  }
+}
+
+// v = mant * 2^e with 1/2 <= |mant| < 1 (mant = v for 0 and non-finite v)
+template <class T>
+__device__ __forceinline__ T normalise(T v, int& e) {
+  const double h = n_hi(v);
+  e = 0;
+  if (h == 0.0 || !isfinite(h)) return v;
+  e = ilogb(h) + 1;
+  return n_ldexp(v, -e);
 }
 
 // The arrays of a job hold T values; the descriptor carries them as double*.
@@ -194,15 +224,19 @@ __device__ inline void gl_node(int n, int k, dd& t_out, dd& w_out) {
   w_out = wk;
 }
 
+// ws, ws2: the weights times 2^shift (exact), the scale a job folds in
 static __global__ void k_gl(int n, double* __restrict__ t, double* __restrict__ w, dd* __restrict__ t2,
-                            dd* __restrict__ w2) {
+                            dd* __restrict__ w2, int shift, double* __restrict__ ws, dd* __restrict__ ws2) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     dd tk, wk;
     gl_node(n, k, tk, wk);
+    const double w1 = wk.hi + wk.lo;
     t[n - 1 - k] = tk.hi + tk.lo;   // increasing order
-    w[n - 1 - k] = wk.hi + wk.lo;
+    w[n - 1 - k] = w1;
     t2[n - 1 - k] = tk;
     w2[n - 1 - k] = wk;
+    ws[n - 1 - k] = ldexp(w1, shift);
+    ws2[n - 1 - k] = n_ldexp(wk, shift);
   }
 }
 
@@ -210,6 +244,7 @@ static __global__ void k_gl(int n, double* __restrict__ t, double* __restrict__ 
 // ----------------------------------------------------- rank-1 start (m >= 0)
 template <class T, int FAM, int MAXM>
 __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
+  constexpr bool kStream = MAXM == 0;   // coordinates one at a time, any number of modes
   const ProbDesc p = P[blockIdx.x];
   const int m = p.m, n = p.n, tid = threadIdx.x;
   const FamilyArgs fa = family_args(p);
@@ -217,11 +252,11 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   const T* __restrict__ ww = tp<T>(p.w);
   __shared__ double sv[kBlock / kWave + 1];
   __shared__ int si[kBlock / kWave + 1];
-  __shared__ int s_i0[MAXM];
+  __shared__ int s_i0[kStream ? TT_MAX_MODES : MAXM];
   __shared__ T s_buf[TT_MAX_NODES];
   ProbState* st = p.st;
 
-  if (m <= 1) {   // no bond: the tensor is a vector (or a scalar for m = 0)
+  if constexpr (!kStream) if (m <= 1) {   // no bond: the tensor is a vector (or a scalar for m = 0)
     T val = num<T>(0.0);
     if (m == 0) {
       T y[MAXM];
@@ -241,9 +276,14 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
         for (int i = 0; i < n; ++i) val = n_add(val, s_buf[i]);
     }
     if (tid == 0) {
-      tp<T>(p.hist)[0] = val;
-      st->value = n_hi(val);
-      st->value_lo = n_lo(val);
+      int e;
+      const T mant = normalise(val, e);
+      e -= p.wshift * m;
+      tp<T>(p.hist)[0] = mant;
+      p.hexp[0] = e;
+      st->value = n_hi(mant);
+      st->value_lo = n_lo(mant);
+      st->vexp = e;
       st->rel = 0.0;
       st->sweeps = 0;
       st->done = 1;
@@ -259,26 +299,37 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   ArgMax best{-1.0, 0x7fffffff};
   bool bad = false;
   for (int q = tid; q < kStart; q += blockDim.x) {
-    T y[MAXM];
-    T W = num<T>(1.0);
+    double v;
+    if constexpr (kStream) {
+      auto node = [&](int k) {
+        return (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n);
+      };
+      T W = num<T>(1.0);
+      for (int k = 0; k < m; ++k) W = n_mul(W, ww[node(k)]);
+      v = n_hi(n_mul(W, integrand_stream<FAM>(fa, [&](int k) { return tt[node(k)]; })));
+    } else {
+      T y[kStream ? 1 : MAXM];
+      T W = num<T>(1.0);
 #pragma unroll
-    for (int k = 0; k < MAXM; ++k) {
-      if (k < m) {
-        int ik = (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n);
-        y[k] = tt[ik];
-        W = n_mul(W, ww[ik]);
-      } else {
-        y[k] = num<T>(0.0);
+      for (int k = 0; k < MAXM; ++k) {
+        if (k < m) {
+          int ik = (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n);
+          y[k] = tt[ik];
+          W = n_mul(W, ww[ik]);
+        } else {
+          y[k] = num<T>(0.0);
+        }
       }
+      v = n_hi(n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y)));
     }
-    const double v = n_hi(n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y)));
     if (!isfinite(v)) bad = true;
     if (better(fabs(v), q, best.v, best.idx)) { best.v = fabs(v); best.idx = q; }
   }
   best = block_argmax(best, sv, si);
   int any_bad = __syncthreads_or(bad);
   const int q = best.idx;
-  if (tid < m) s_i0[tid] = (int)uniform_below(splitmix_at(p.seed, start_counter(q, tid)), (uint32_t)n);
+  for (int k = tid; k < m; k += blockDim.x)
+    s_i0[k] = (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n);
   __syncthreads();
   if (any_bad || !(best.v > 0.0)) {
     if (tid == 0) {
@@ -290,6 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       st->max_rank = 0;
       st->value = 0.0;
       st->value_lo = 0.0;
+      st->vexp = 0;
       st->rel = __builtin_huge_val();
       signal_done(p);
     }
@@ -357,6 +409,7 @@ struct SearchSmem {
 template <class T, int FAM, int MAXM>
 __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, SearchSmem<T, MAXM>& sm) {
   constexpr int LD = MAXM + 1;
+  constexpr bool kStream = MAXM == 0;   // coordinates read from the index-set rows in memory
   const int tid = threadIdx.x;
   ProbState* st = p.st;
   const int m = p.m, n = p.n, R = p.R, nb = p.nbonds;
@@ -381,14 +434,16 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   const T* __restrict__ gw = tp<T>(p.w);
   mark(p, sweep, b, 0);
   // stage index-set coordinates, node table and weights in LDS
-  for (int e = tid; e < rL * b; e += blockDim.x) {
-    const int a = e / b, k = e % b;
-    sm.Lx[a * LD + k] = gLx[((size_t)(b - 1) * R + a) * m + k];
-  }
-  const int nright = m - b - 2;
-  for (int e = tid; e < rR * nright; e += blockDim.x) {
-    const int a = e / nright, k = b + 2 + e % nright;
-    sm.Rx[a * LD + k] = gRx[((size_t)(b + 1) * R + a) * m + k];
+  if constexpr (!kStream) {
+    for (int e = tid; e < rL * b; e += blockDim.x) {
+      const int a = e / b, k = e % b;
+      sm.Lx[a * LD + k] = gLx[((size_t)(b - 1) * R + a) * m + k];
+    }
+    const int nright = m - b - 2;
+    for (int e = tid; e < rR * nright; e += blockDim.x) {
+      const int a = e / nright, k = b + 2 + e % nright;
+      sm.Rx[a * LD + k] = gRx[((size_t)(b + 1) * R + a) * m + k];
+    }
   }
   for (int a = tid; a < rL; a += blockDim.x) sm.Lw[a] = b > 0 ? gLw[(size_t)(b - 1) * R + a] : num<T>(1.0);
   for (int a = tid; a < rR; a += blockDim.x)
@@ -446,21 +501,31 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
       // B at (alpha, i, j, beta): coordinates of I_<=b-1[alpha], t_i, t_j, I_>b+1[beta]
       const int al = pr / n, i = pr - al * n;
       const int j = pc / rR, be = pc - j * rR;
-      T y[MAXM];
-#pragma unroll
-      for (int k = 0; k < MAXM; ++k) {
-        T v = num<T>(0.0);
-        if (k < m) {
-          v = (k < b) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
-          v = (k == b) ? sm.t[i] : v;
-          v = (k == b + 1) ? sm.t[j] : v;
-        }
-        y[k] = v;
-      }
       // weights multiplied in the order the core update uses for the same entry
       const T W = (mode == 1) ? n_mul(n_mul(sm.Lw[al], sm.w[i]), n_mul(sm.w[j], sm.Rw[be]))
                               : n_mul(n_mul(n_mul(sm.Lw[al], sm.w[i]), sm.w[j]), sm.Rw[be]);
-      const T a = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
+      T a;
+      if constexpr (kStream) {
+        const T* Lrow = gLx + ((size_t)(b > 0 ? b - 1 : 0) * R + al) * m;
+        const T* Rrow = gRx + ((size_t)(b + 1 <= m - 2 ? b + 1 : 0) * R + be) * m;
+        const T ti = sm.t[i], tj = sm.t[j];
+        a = n_mul(W, integrand_stream<FAM>(fa, [&](int k) {
+          return k < b ? Lrow[k] : k == b ? ti : k == b + 1 ? tj : Rrow[k];
+        }));
+      } else {
+        T y[MAXM];
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+          T v = num<T>(0.0);
+          if (k < m) {
+            v = (k < b) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
+            v = (k == b) ? sm.t[i] : v;
+            v = (k == b + 1) ? sm.t[j] : v;
+          }
+          y[k] = v;
+        }
+        a = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
+      }
       if (mode == 1) Fb_new[(size_t)pr * ccb] = a;
       else if (mode == 2) F1_new[(size_t)j * cc1 + be] = a;
       T s = num<T>(0.0);
@@ -555,6 +620,7 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
                                             UpdateSmem<T, MAXM, RMAX>& sm, const int mb = -1) {
   constexpr int LD = MAXM + 1;
   constexpr int LA = RMAX + 1;
+  constexpr bool kStream = MAXM == 0;   // coordinates read from the index-set rows in memory
   // a row of C_c is kept in registers while it is updated when it is small
   // enough; otherwise it is worked on in place in memory
   constexpr bool kRowInRegs = sizeof(T) * RMAX <= 256;
@@ -608,14 +674,16 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   }
   __syncthreads();
   // ---- stage I_<=c-1 and I_>c coordinates
-  for (int e = tid; e < rL_new * c; e += blockDim.x) {
-    const int a = e / c, k = e % c;
-    sm.Lx[a * LD + k] = gLx[((size_t)(c - 1) * R + a) * m + k];
-  }
-  const int nright = m - c - 1;
-  for (int e = tid; e < rR_new * nright; e += blockDim.x) {
-    const int a = e / nright, k = c + 1 + e % nright;
-    sm.Rx[a * LD + k] = gRx[((size_t)c * R + a) * m + k];
+  if constexpr (!kStream) {
+    for (int e = tid; e < rL_new * c; e += blockDim.x) {
+      const int a = e / c, k = e % c;
+      sm.Lx[a * LD + k] = gLx[((size_t)(c - 1) * R + a) * m + k];
+    }
+    const int nright = m - c - 1;
+    for (int e = tid; e < rR_new * nright; e += blockDim.x) {
+      const int a = e / nright, k = c + 1 + e % nright;
+      sm.Rx[a * LD + k] = gRx[((size_t)c * R + a) * m + k];
+    }
   }
   for (int a = tid; a < rL_new; a += blockDim.x) sm.Lw[a] = hasL ? gLw[(size_t)(c - 1) * R + a] : num<T>(1.0);
   for (int a = tid; a < rR_new; a += blockDim.x) sm.Rw[a] = hasR ? gRw[(size_t)c * R + a] : num<T>(1.0);
@@ -649,18 +717,26 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
       i = rem / nBc;
       be = rR_old + rem % nBc;
     }
-    T y[MAXM];
-#pragma unroll
-    for (int k = 0; k < MAXM; ++k) {
-      T v = num<T>(0.0);
-      if (k < m) {
-        v = (k < c) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
-        v = (k == c) ? sm.t[i] : v;
-      }
-      y[k] = v;
-    }
     const T W = n_mul(n_mul(sm.Lw[al], sm.w[i]), sm.Rw[be]);
-    const T v = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
+    T v;
+    if constexpr (kStream) {
+      const T* Lrow = gLx + ((size_t)(c > 0 ? c - 1 : 0) * R + al) * m;
+      const T* Rrow = gRx + ((size_t)(c <= m - 2 ? c : 0) * R + be) * m;
+      const T ti = sm.t[i];
+      v = n_mul(W, integrand_stream<FAM>(fa, [&](int k) { return k < c ? Lrow[k] : k == c ? ti : Rrow[k]; }));
+    } else {
+      T y[MAXM];
+#pragma unroll
+      for (int k = 0; k < MAXM; ++k) {
+        T yk = num<T>(0.0);
+        if (k < m) {
+          yk = (k < c) ? sm.Lx[al * LD + k] : sm.Rx[be * LD + k];
+          yk = (k == c) ? sm.t[i] : yk;
+        }
+        y[k] = yk;
+      }
+      v = n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y));
+    }
     bad |= !isfinite(n_hi(v));
     Fc[((size_t)al * n + i) * cc + be] = v;
   }
@@ -756,8 +832,8 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     if (mb >= 0) mark(p, msw, mb, 11);
     if (accR) {
       const int prow = p.piv[c].row;   // the row of F_c appended to I_<=c this sweep
-      // (c) border the LU: w = L^-1 u, l = v U^-1, delta = F_c(prow, r0) - l . w, with
-      //     u = F_c(I_<=c, r0) the new column at the old cross rows and v = F_c(prow, :r0)
+      // (c) border the LU: w = L^-1 u, l = v U^-1 and the pivot delta, with u = F_c(I_<=c, r0)
+      //     the new column at the old cross rows and v = F_c(prow, :r0)
       if (tid < kWave) {
         T wa = (tid < r0) ? Fc[(size_t)sm.rowidx[tid] * cc + r0] : num<T>(0.0);
         T lq = (tid < r0) ? Fc[(size_t)prow * cc + tid] : num<T>(0.0);
@@ -771,21 +847,26 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
           if (tid == k2) lq = lk;
           else if (tid > k2 && tid < r0) lq = n_nmad(lk, sm.A[k2 * LA + tid], lq);
         }
-        T prod = (tid < r0) ? n_mul(lq, wa) : num<T>(0.0);
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) prod = n_add(prod, n_shfl_xor(prod, off));
-        const T delta = n_sub(Fc[(size_t)prow * cc + r0], prod);
         if (tid < r0) {
           LU[(size_t)r0 * R + tid] = lq;
           LU[(size_t)tid * R + r0] = wa;
         }
-        if (tid == 0) {
-          LU[(size_t)r0 * R + r0] = delta;
-          sm.delta = delta;
-          if (n_hi(delta) == 0.0) atomicOr(&st->err_flags, 2);
-        }
       }
       if (tid < r0) sm.cp[tid] = Cc[(size_t)tid * ldC + prow];   // C_c(prow, :) before the update
+      __syncthreads();
+      // The pivot is the residual of the new cross row, delta = F_c(prow, r0) - C_c(prow, :) u
+      // (equal to F_c(prow, r0) - l . w in exact arithmetic), computed with the very operations
+      // the update below applies to row prow: the update then gives C_c(prow, :) = e_r0 exactly,
+      // keeping the interpolation property at the new cross row.  With the Schur complement of
+      // the bordered LU instead, the two roundings differ by about eps |C_c(prow,:)| |u|, which
+      // a pivot near the rounding level of the cross turns into an O(1) error of that row.
+      if (tid == 0) {
+        T e = Fc[(size_t)prow * cc + r0];
+        for (int k = 0; k < r0; ++k) e = n_nmad(sm.cp[k], sm.u[k], e);
+        LU[(size_t)r0 * R + r0] = e;
+        sm.delta = e;
+        if (n_hi(e) == 0.0) atomicOr(&st->err_flags, 2);
+      }
       __syncthreads();
       if (mb >= 0) mark(p, msw, mb, 12);
       // (b) rank-1 update of every row: e = F_c(:, r0) - C_c u, C_c <- [C_c - (e/delta) c_piv, e/delta]
@@ -843,6 +924,7 @@ struct IntSmem {
   T stage[kStage];
   int s_rank[TT_MAX_MODES];
   int s_off[TT_MAX_MODES + 1];
+  int cnt[2];   // accepted pivots, largest rank
 };
 
 template <class T>
@@ -855,6 +937,7 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
   // state needed by the stopping rule, loaded now so its latency overlaps the chain
   const int sw0 = st->sweeps;
   const T prev = hist[sw0];
+  const int prev_exp = p.hexp[sw0];
   const double prev_rel = st->rel;
   T* v = sm.v;
   T* v2 = sm.v2;
@@ -862,20 +945,30 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
   int* s_rank = sm.s_rank;
   int* s_off = sm.s_off;
   const int m = p.m, R = p.R, nb = p.nbonds, tid = threadIdx.x;
-  // commit the ranks: r_b += accepted_b (one thread per bond)
-  int acc = 0, r = 0;
-  if (tid < nb) {
-    acc = init ? 0 : p.piv[tid].acc;
-    r = p.rank[tid] + acc;
-    p.rank[tid] = r;
-    s_rank[tid] = r;
+  // commit the ranks: r_b += accepted_b
+  if (tid == 0) {
+    sm.cnt[0] = 0;
+    sm.cnt[1] = 1;
   }
-  const int nacc = __syncthreads_count(acc);
-  const int below_cap = __syncthreads_or(tid < nb && r < R);
-  int maxr = 1;
-  for (int b = 0; b < nb; ++b) maxr = max(maxr, s_rank[b]);
+  __syncthreads();
+  int acc = 0, below = 0, maxr = 1;
+  for (int b = tid; b < nb; b += blockDim.x) {
+    const int a = init ? 0 : p.piv[b].acc;
+    const int r = p.rank[b] + a;
+    p.rank[b] = r;
+    s_rank[b] = r;
+    acc += a;
+    below |= r < R;
+    maxr = max(maxr, r);
+  }
+  if (acc) atomicAdd(&sm.cnt[0], acc);
+  if (maxr > 1) atomicMax(&sm.cnt[1], maxr);
+  const int below_cap = __syncthreads_or(below);
+  const int nacc = sm.cnt[0];
+  maxr = sm.cnt[1];
   // v = S_0 (1 x r_0), then v <- v S_c for c = 1..m-1 (2m-1 matrices, inverses in C)
   for (int k = tid; k < s_rank[0]; k += blockDim.x) v[k] = gS[k];
+  int vexp = 0;   // v times 2^vexp is the chain's value (kept by wave 0)
   int c0 = 1;
   while (c0 < m) {
     // stage as many consecutive S_c as fit, all loads in flight together; a core
@@ -906,17 +999,26 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
       __syncthreads();
     }
     // the chain itself runs in wave 0 alone (lane k owns column k of every S_c,
-    // r <= 64), ping-ponging v and v2 in LDS with wave-level ordering only
+    // r <= 64), ping-ponging v and v2 in LDS with wave-level ordering only;
+    // every 16 factors v is brought back near 1 by an exact power of two, so
+    // long chains (up to a thousand modes) stay in the double range
     if (tid < kWave) {
       for (int c = c0; c < c1; ++c) {
         const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
         const T* Sc = direct ? gS + (size_t)c * R * R : stage + s_off[c - c0];
         const int ldS = direct ? R : rr;
-        if (tid < rr) {
-          T s = num<T>(0.0);
+        T s = num<T>(0.0);
+        if (tid < rr)
           for (int a = 0; a < rl; ++a) s = n_mad(v[a], Sc[a * ldS + tid], s);
-          v2[tid] = s;
+        if ((c & 15) == 0) {
+          const double mag = wave_max(fabs(n_hi(s)));   // lanes >= rr hold 0
+          if (mag > 0.0 && isfinite(mag)) {
+            const int e = ilogb(mag) + 1;
+            s = n_ldexp(s, -e);
+            vexp += e;
+          }
         }
+        if (tid < rr) v2[tid] = s;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -935,21 +1037,30 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
     c0 = c1;
   }
   if (tid != 0) return;
-  const T value = v[0];
+  // the integral as mantissa * 2^exponent; the folded weights carried 2^wshift per mode
+  int e;
+  const T value = normalise(v[0], e);
+  const int vx = vexp + e - p.wshift * m;
   st->max_rank = maxr;
   if (!isfinite(n_hi(value))) st->err_flags |= 1;
   if (init) {
     hist[0] = value;
+    p.hexp[0] = vx;
     st->value = n_hi(value);
     st->value_lo = n_lo(value);
+    st->vexp = vx;
     return;
   }
-  const double rel = n_hi(value) != 0.0 ? fabs(n_hi(n_div(n_sub(value, prev), value))) : __builtin_huge_val();
+  // relative change, the previous value brought to this one's exponent (exact scaling)
+  const T prev_al = n_ldexp(prev, prev_exp - vx);
+  const double rel = n_hi(value) != 0.0 ? fabs(n_hi(n_div(n_sub(value, prev_al), value))) : __builtin_huge_val();
   const int s = sw0 + 1;
   st->sweeps = s;
   hist[s] = value;
+  p.hexp[s] = vx;
   st->value = n_hi(value);
   st->value_lo = n_lo(value);
+  st->vexp = vx;
   st->rel = rel;
   st->nacc = nacc;
   int done = 0, reason = TT_RUNNING;
@@ -1157,7 +1268,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa_in, int n,
 template <int FAM, int MAXM>
 __global__ __launch_bounds__(kBlock) void k_mc(FamilyArgs fa, int kind, int64_t N, const int64_t* __restrict__ gen,
                                                uint64_t seed, double* __restrict__ partial) {
-  __shared__ double sshift[TT_MAX_MODES];
+  __shared__ double sshift[TT_MAX_REG_MODES];
   __shared__ double red[kBlock / kWave];
   const int j = blockIdx.y, m = fa.m, tid = threadIdx.x;
   if (tid < m) sshift[tid] = uniform_open01(splitmix_at(seed, shift_counter(j, tid)));

@@ -15,7 +15,7 @@ struct LaunchArgs {
   const int2* core_tasks;
   int ncore;
   int nprob;
-  int mbucket;        // 8, 16 or 32: compile-time bound on the number of modes
+  int mbucket;        // compile-time bound on the number of modes (0: streaming, any number)
   hipStream_t stream;
 };
 

@@ -29,7 +29,7 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr int kMaxBonds = TT_MAX_MODES - 1;
+constexpr int kMaxBonds = TT_MAX_REG_MODES - 1;
 constexpr int kStages = 4;       // pinned upload buffers in rotation
 constexpr int kInFlight = 3;     // sweep launches allowed ahead of the host
 
@@ -176,7 +176,7 @@ tt_status start_requests(tt_server* s, std::vector<Running>& fresh) {
     const ProbOffsets o = layout_problem(p, pl);
     const size_t arrays = L.take(pl.off);
     double *t, *w;
-    st = gl_table(ctx, p.n_nodes, &t, &w);
+    st = gl_table(ctx, p.n_nodes, &t, &w, false, true);
     if (st != TT_OK) return st;
     s->flags[r.slot] = 0;
     r.desc = make_desc(p, o, base + arrays, base, tb, t, w, s->flags + r.slot, (ProbState*)(base + st_off),
@@ -411,7 +411,7 @@ tt_status tt_server_create(tt_ctx* ctx, size_t max_bytes, int32_t max_active, tt
     s->off_sdesc = L.take(sizeof(ProbDesc) * max_active);
     s->off_stask = L.take(sizeof(int2) * max_active * kMaxBonds);
     s->off_idesc = L.take(sizeof(ProbDesc) * max_active);
-    s->off_itask = L.take(sizeof(int2) * max_active * TT_MAX_MODES);
+    s->off_itask = L.take(sizeof(int2) * max_active * TT_MAX_REG_MODES);
     s->table_bytes = L.off;
     if (hipMalloc(&s->dtable, s->table_bytes) != hipSuccess) return fail(TT_ENOMEM);
     if (hipHostMalloc((void**)&s->flags, sizeof(int32_t) * max_active, hipHostMallocDefault) != hipSuccess)
@@ -445,6 +445,7 @@ tt_status tt_server_create(tt_ctx* ctx, size_t max_bytes, int32_t max_active, tt
 
 tt_status tt_server_submit(tt_server* s, const tt_problem* p, uint64_t* ticket) {
   if (!s || !p || !ticket || validate(p) != TT_OK || p->precision != TT_FP64) return TT_EINVAL;
+  if (modes_of(*p) > TT_MAX_REG_MODES) return TT_EINVAL;
   Request r;
   r.prob = *p;
   const int m = modes_of(*p);

@@ -47,23 +47,32 @@ struct tt_job {
 namespace ttx_host {
 // Node tables for n, generated on first use.  With want_dd the returned
 // pointers are the double-double tables (reinterpreted as double*).
-tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd) {
+tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd, bool scaled) {
   auto it = ctx->gl.find(n);
   if (it == ctx->gl.end()) {
-    tt_ctx::GL g{nullptr, nullptr, nullptr, nullptr};
-    TT_HIP(hipMalloc(&g.t, n * sizeof(double)));
-    TT_HIP(hipMalloc(&g.w, n * sizeof(double)));
-    TT_HIP(hipMalloc(&g.t2, n * sizeof(dd)));
-    TT_HIP(hipMalloc(&g.w2, n * sizeof(dd)));
+    tt_ctx::GL g{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // inserted first so that tt_ctx_destroy frees whatever was allocated
+    it = ctx->gl.emplace(n, g).first;
+    tt_ctx::GL& e = it->second;
+    TT_HIP(hipMalloc(&e.t, n * sizeof(double)));
+    TT_HIP(hipMalloc(&e.w, n * sizeof(double)));
+    TT_HIP(hipMalloc(&e.t2, n * sizeof(dd)));
+    TT_HIP(hipMalloc(&e.w2, n * sizeof(dd)));
+    TT_HIP(hipMalloc(&e.ws, n * sizeof(double)));
+    TT_HIP(hipMalloc(&e.ws2, n * sizeof(dd)));
     {
       Timed tm(ctx, KK_GL);
-      hipLaunchKernelGGL(k_gl, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, g.t, g.w, g.t2, g.w2);
+      hipLaunchKernelGGL(k_gl, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, e.t, e.w, e.t2, e.w2,
+                         weight_shift(n), e.ws, e.ws2);
     }
     TT_HIP(hipGetLastError());
-    it = ctx->gl.emplace(n, g).first;
   }
-  *t = want_dd ? reinterpret_cast<double*>(it->second.t2) : it->second.t;
-  *w = want_dd ? reinterpret_cast<double*>(it->second.w2) : it->second.w;
+  const tt_ctx::GL& g = it->second;
+  *t = want_dd ? reinterpret_cast<double*>(g.t2) : g.t;
+  if (scaled)
+    *w = want_dd ? reinterpret_cast<double*>(g.ws2) : g.ws;
+  else
+    *w = want_dd ? reinterpret_cast<double*>(g.w2) : g.w;
   return TT_OK;
 }
 
@@ -159,12 +168,12 @@ void eval_fibers_k(tt_ctx* ctx, dim3 grid, dim3 block, const FamilyArgs& fa, int
                      d_right, r_right, reinterpret_cast<T*>(d_out));
 }
 
-// Paper form in double: one kernel per exact number of modes (1..TT_MAX_MODES).
+// Paper form in double: one kernel per exact number of modes (1..TT_MAX_REG_MODES).
 template <int M>
 void eval_fibers_exact(tt_ctx* ctx, int m, dim3 grid, dim3 block, const FamilyArgs& fa, int n, const double* t,
                        const double* w, int pos, const int32_t* d_left, int r_left, const int32_t* d_right,
                        int r_right, double* d_out) {
-  if constexpr (M <= TT_MAX_MODES) {
+  if constexpr (M <= TT_MAX_REG_MODES) {
     if (m == M)
       eval_fibers_k<double, FAM_PAPER, M, true>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right,
                                                 r_right, d_out);
@@ -232,6 +241,8 @@ void tt_ctx_destroy(tt_ctx* c) {
     hipFree(kv.second.w);
     hipFree(kv.second.t2);
     hipFree(kv.second.w2);
+    hipFree(kv.second.ws);
+    hipFree(kv.second.ws2);
   }
   if (c->params) hipFree(c->params);
   for (auto& kv : c->arenas) hipFree(kv.second);
@@ -302,7 +313,7 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->gl64.resize(count);
   for (int k = 0; k < count; ++k) {
     tt_status s = gl_table(ctx, problems[k].n_nodes, &j->gl64[k].first, &j->gl64[k].second);
-    if (s == TT_OK) s = gl_table(ctx, problems[k].n_nodes, &gl[k].first, &gl[k].second, j->dd);
+    if (s == TT_OK) s = gl_table(ctx, problems[k].n_nodes, &gl[k].first, &gl[k].second, j->dd, true);
     if (s != TT_OK) {
       delete j;
       return s;
@@ -498,7 +509,7 @@ tt_status tt_cross_integrate(tt_job* j, double* values, tt_info* info) {
   tt_status s = read_states(j, st);
   if (s != TT_OK) return s;
   for (int k = 0; k < j->nprob; ++k) {
-    values[k] = st[k].value;
+    values[k] = std::ldexp(st[k].value, st[k].vexp);
     if (info) fill_info(st[k], &info[k]);
   }
   return TT_OK;
@@ -518,8 +529,8 @@ tt_status tt_job_pivot_log(tt_job* j, int32_t k, tt_pivot* log, int64_t capacity
   return TT_OK;
 }
 
-tt_status tt_job_history(tt_job* j, int32_t k, double* values, double* values_lo, int64_t capacity,
-                         int64_t* written) {
+tt_status tt_job_history(tt_job* j, int32_t k, double* values, double* values_lo, int32_t* exp2,
+                         int64_t capacity, int64_t* written) {
   if (!j || k < 0 || k >= j->nprob || !values || !written) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(j->ctx->mu);
   std::vector<ProbState> st;
@@ -527,17 +538,22 @@ tt_status tt_job_history(tt_job* j, int32_t k, double* values, double* values_lo
   if (s != TT_OK) return s;
   const int64_t nv = st[k].sweeps + 1;
   if (nv > capacity) return TT_EINVAL;
+  // the device keeps mantissas and exponents
+  std::vector<dd> h(nv);
+  std::vector<int32_t> e(nv);
   if (j->dd) {
-    std::vector<dd> h(nv);
     TT_HIP(hipMemcpy(h.data(), j->hdesc[k].hist, nv * sizeof(dd), hipMemcpyDeviceToHost));
-    for (int64_t q = 0; q < nv; ++q) {
-      values[q] = h[q].hi;
-      if (values_lo) values_lo[q] = h[q].lo;
-    }
   } else {
-    TT_HIP(hipMemcpy(values, j->hdesc[k].hist, nv * sizeof(double), hipMemcpyDeviceToHost));
-    if (values_lo)
-      for (int64_t q = 0; q < nv; ++q) values_lo[q] = 0.0;
+    std::vector<double> h1(nv);
+    TT_HIP(hipMemcpy(h1.data(), j->hdesc[k].hist, nv * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t q = 0; q < nv; ++q) h[q] = dd{h1[q], 0.0};
+  }
+  TT_HIP(hipMemcpy(e.data(), j->hdesc[k].hexp, nv * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int64_t q = 0; q < nv; ++q) {
+    const int x = exp2 ? 0 : e[q];
+    values[q] = std::ldexp(h[q].hi, x);
+    if (values_lo) values_lo[q] = std::ldexp(h[q].lo, x);
+    if (exp2) exp2[q] = e[q];
   }
   *written = nv;
   return TT_OK;
@@ -658,6 +674,7 @@ void tt_cross_free(tt_job* j) {
 tt_status tt_eval_points(tt_ctx* ctx, const tt_problem* p, const int32_t* d_idx, int64_t npts,
                          double* d_out) {
   if (!ctx || validate(p) != TT_OK || npts < 0 || (npts > 0 && (!d_idx || !d_out))) return TT_EINVAL;
+  if (modes_of(*p) > TT_MAX_REG_MODES) return TT_EINVAL;
   if (npts == 0) return TT_OK;
   std::lock_guard<std::mutex> lock(ctx->mu);
   TT_HIP(hipSetDevice(ctx->device));
@@ -682,7 +699,7 @@ tt_status tt_eval_points(tt_ctx* ctx, const tt_problem* p, const int32_t* d_idx,
 
 tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const int32_t* d_left,
                          int32_t r_left, const int32_t* d_right, int32_t r_right, double* d_out) {
-  if (!ctx || validate(p) != TT_OK) return TT_EINVAL;
+  if (!ctx || validate(p) != TT_OK || modes_of(*p) > TT_MAX_REG_MODES) return TT_EINVAL;
   const int m = modes_of(*p);
   if (m < 1 || pos < 0 || pos >= m) return TT_EINVAL;
   if (r_left < 1 || r_left > TT_MAX_RANK || r_right < 1 || r_right > TT_MAX_RANK || !d_out) return TT_EINVAL;
@@ -719,7 +736,8 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
 
 tt_status tt_mc_integrate(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_t n_points, int32_t n_sets,
                           const int64_t* gen, double* estimates, double* mean, double* rel_err) {
-  if (!ctx || validate(p) != TT_OK || p->precision != TT_FP64) return TT_EINVAL;
+  if (!ctx || validate(p) != TT_OK || p->precision != TT_FP64 || modes_of(*p) > TT_MAX_REG_MODES)
+    return TT_EINVAL;
   if (kind != TT_MC_RANDOM && kind != TT_MC_LATTICE) return TT_EINVAL;
   if (n_points < 1 || n_points >= (int64_t(1) << 31) || n_sets < 2 || n_sets > 4096) return TT_EINVAL;
   if (kind == TT_MC_LATTICE && !gen) return TT_EINVAL;
@@ -733,7 +751,7 @@ tt_status tt_mc_integrate(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_
   if (s != TT_OK) return s;
   const int blocks = (int)std::min<int64_t>((n_points + kBlock - 1) / kBlock, 256);
   // scratch: partial sums [S x blocks], results [S + 2], generating vector [m]
-  const size_t need = sizeof(double) * ((size_t)n_sets * blocks + n_sets + 2) + sizeof(int64_t) * TT_MAX_MODES;
+  const size_t need = sizeof(double) * ((size_t)n_sets * blocks + n_sets + 2) + sizeof(int64_t) * TT_MAX_REG_MODES;
   if (need > ctx->mc_cap) {
     TT_HIP(hipStreamSynchronize(ctx->stream));
     if (ctx->mc_buf) TT_HIP(hipFree(ctx->mc_buf));
@@ -746,7 +764,7 @@ tt_status tt_mc_integrate(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_
   double* out = partial + (size_t)n_sets * blocks;
   int64_t* dgen = (int64_t*)(out + n_sets + 2);
   if (kind == TT_MC_LATTICE) {
-    int64_t g[TT_MAX_MODES];
+    int64_t g[TT_MAX_REG_MODES];
     for (int k = 0; k < m; ++k) g[k] = ((gen[k] % n_points) + n_points) % n_points;
     TT_HIP(hipStreamSynchronize(ctx->stream));   // the earlier upload source is a stack array
     TT_HIP(hipMemcpy(dgen, g, sizeof(int64_t) * m, hipMemcpyHostToDevice));

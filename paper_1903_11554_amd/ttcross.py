@@ -44,7 +44,9 @@ class _Info(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("reason", ctypes.c_int32), ("err_flags", ctypes.c_int32),
                 ("evals", ctypes.c_int64), ("value", ctypes.c_double),
-                ("rel_change", ctypes.c_double), ("value_lo", ctypes.c_double)]
+                ("rel_change", ctypes.c_double), ("value_lo", ctypes.c_double),
+                ("value_mant", ctypes.c_double), ("value_exp2", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -103,7 +105,7 @@ def load_library():
         "tt_cross_run": (i32, [vp, P(_Info)]),
         "tt_cross_integrate": (i32, [vp, P(dbl), P(_Info)]),
         "tt_job_pivot_log": (i32, [vp, i32, P(_Pivot), i64, P(i64)]),
-        "tt_job_history": (i32, [vp, i32, P(dbl), P(dbl), i64, P(i64)]),
+        "tt_job_history": (i32, [vp, i32, P(dbl), P(dbl), P(i32), i64, P(i64)]),
         "tt_job_index_sets": (i32, [vp, i32, P(i32), P(i32), i64, P(i64)]),
         "tt_job_nodes": (i32, [vp, i32, P(dbl), P(dbl), P(dbl), P(dbl)]),
         "tt_cross_free": (None, [vp]),
@@ -265,7 +267,7 @@ class Job:
     def _info_dicts(infos):
         return [dict(sweeps=i.sweeps, max_rank=i.max_rank, reason=STOP_REASONS.get(i.reason, i.reason),
                      err_flags=i.err_flags, evals=i.evals, value=i.value, rel_change=i.rel_change,
-                     value_lo=i.value_lo)
+                     value_lo=i.value_lo, value_mant=i.value_mant, value_exp2=i.value_exp2)
                 for i in infos]
 
     def sweep(self, n=1):
@@ -310,8 +312,20 @@ class Job:
         buf = (ctypes.c_double * cap)()
         lo = (ctypes.c_double * cap)()
         written = ctypes.c_int64()
-        _check(self._lib.tt_job_history(self.handle, k, buf, lo, cap, ctypes.byref(written)), "tt_job_history")
+        _check(self._lib.tt_job_history(self.handle, k, buf, lo, None, cap, ctypes.byref(written)),
+               "tt_job_history")
         return list(buf[:written.value]), list(lo[:written.value])
+
+    def history_scaled(self, k):
+        """[(mantissa, exponent)]: the integral after the start and every sweep is mantissa * 2^exponent."""
+        p = self.problems[k]
+        cap = (p.max_sweeps if p.max_sweeps > 0 else 4 * p.rank_cap) + 1
+        buf = (ctypes.c_double * cap)()
+        ex = (ctypes.c_int32 * cap)()
+        written = ctypes.c_int64()
+        _check(self._lib.tt_job_history(self.handle, k, buf, None, ex, cap, ctypes.byref(written)),
+               "tt_job_history")
+        return [(buf[q], ex[q]) for q in range(written.value)]
 
     def index_sets(self, k):
         """[(left rows, right rows)] per bond, each a list of tuples of node indices."""

@@ -45,7 +45,9 @@ def test_footprint_host_only():
 
 @pytest.mark.parametrize("bad", [
     Problem("ising_d", 0, 64, 32, 1e-10),            # d < 1
-    Problem("ising_d", 34, 64, 32, 1e-10),           # more than 32 modes
+    Problem("ising_d", 1026, 33, 8, 1e-10),          # more than 1024 modes
+    Problem("ising_d", 34, 64, 32, 1e-10, precision="dd"),   # double-double beyond 32 modes
+    Problem("ising_c_u", 33, 64, 8, 1e-10),          # u-form beyond 32 modes
     Problem("ising_d", 5, 0, 32, 1e-10),             # no nodes
     Problem("ising_d", 5, 257, 32, 1e-10),           # too many nodes
     Problem("ising_d", 5, 64, 65, 1e-10),            # rank over the cap
@@ -54,6 +56,14 @@ def test_footprint_host_only():
 ])
 def test_invalid_problems_rejected(bad):
     assert binding.footprint(bad) == 0
+
+
+def test_large_jobs_accepted():
+    # the streaming path: up to 1024 modes, double precision, paper form and synthetic
+    assert binding.footprint(Problem("ising_c", 1024, 33, 16, 1e-12)) > 0
+    assert binding.footprint(Problem("ising_d", 34, 64, 32, 1e-10)) > 0
+    a = [0.1] * 1000
+    assert binding.footprint(Problem("prod_exp", 1000, 16, 4, 1e-12, params={"a": a, "b": a})) > 0
 
 
 def test_ctx_fails_loudly_without_gpu():
