@@ -246,6 +246,7 @@ def run_gpu(args):
     batch = run_batch(ctx)
     dd = run_dd(ctx)
     mcres = run_mc(ctx, infos, probs)
+    large = run_large(ctx)
     serving = run_serving(ctx, args.serve_seconds)
 
     refs = reference_values()
@@ -257,7 +258,7 @@ def run_gpu(args):
     ctx.close()
     return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
                 s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
-                errs=errs, probs=probs, batch=batch, dd=dd, serving=serving, mc=mcres)
+                errs=errs, probs=probs, batch=batch, dd=dd, serving=serving, mc=mcres, large=large)
 
 
 def run_mc(ctx, tt_infos, tt_probs):
@@ -292,6 +293,37 @@ def run_mc(ctx, tt_infos, tt_probs):
             "ms": dt * 1e3, "evals_per_s": pts / dt, "tflops": tflops, "frac": tflops / FP64_PEAK_TFLOPS,
             "d8_same_evals": {"evals": ev8, "mc_rel_err_estimate": err8,
                               "tt_rel_err_vs_printed": reference_errors_d8(tt_infos[k8]["value"])}}
+
+
+def run_large(ctx, reps=2):
+    """Large integrals on the streaming path (Sec. 5.3, 5.5), one integral per job, double precision.
+
+    C_1024 (1023 modes) against 2 exp(-2 gamma), and D_64, D_128 against the
+    values the paper prints; time from tt_cross_init to the stopping rule.
+    """
+    import torch
+
+    from paper_1903_11554_amd.workloads import Problem
+    c_inf = 2.0 * math.exp(-2.0 * 0.57721566490153286061)
+    cases = [("C_1024", Problem("ising_c", 1024, 33, 12, 1e-10, seed=1024), c_inf),
+             ("D_64", Problem("ising_d", 64, 33, 16, 1e-9, seed=64), 5.6650255053330577357994408887987e-45),
+             ("D_128", Problem("ising_d", 128, 33, 12, 1e-8, seed=128), 3.8211244448448883068502878086763e-90)]
+    out = {}
+    for name, p, ref in cases:
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            job = ctx.job([p])
+            info = job.run()[0]
+            dt = time.perf_counter() - t
+            job.free()
+            best = dt if best is None else min(best, dt)
+        out[name] = {"modes": p.modes(), "nodes": p.n, "rank_cap": p.rank_cap, "tol": p.tol,
+                     "ms_to_solution": best * 1e3, "sweeps": info["sweeps"], "max_rank": info["max_rank"],
+                     "evals": info["evals"], "evals_per_s": info["evals"] / best,
+                     "rel_err_vs_reference": abs(info["value"] / ref - 1)}
+    return out
 
 
 def reference_errors_d8(v):
@@ -547,6 +579,7 @@ def main():
         "precision_dd": r["dd"],
         "serving": r["serving"],
         "monte_carlo": r["mc"],
+        "large_integrals": r["large"],
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(r["probs"], args.cpu_budget)
