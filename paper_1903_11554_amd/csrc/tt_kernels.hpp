@@ -1112,7 +1112,10 @@ union SweepSmem {
 // neighbouring superblocks finishes last, and the quadrature by whichever core
 // finishes last.  Each hand-over is a release fence plus an atomic increment,
 // observed by the arriving workgroup after an acquire fence; no workgroup waits
-// for another, so any subset of workgroups may be resident at a time.
+// for another, so any subset of workgroups may be resident at a time.  The
+// release fence writes this workgroup's results back from its XCD's L2; only the
+// last arriver, which goes on to read the others' results, takes the acquire
+// fence (an L2 invalidate), so the other workgroups keep their caches warm.
 template <class T, int FAM, int MAXM, int RMAX>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
                                                        const int2* __restrict__ tasks) {
@@ -1128,14 +1131,14 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
   __syncthreads();
   mark(p, sweep, b, 4);
   if (tid == 0) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     int nt = 0;
     for (int c = b; c <= b + 1; ++c) {
       const int target = (c >= 1 ? 1 : 0) + (c <= m - 2 ? 1 : 0);
       if (atomicAdd(&p.sync[c], 1) + 1 == target) s_todo[nt++] = c;
     }
     s_todo[2] = nt;
-    __threadfence();
+    if (nt > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   const int nt = s_todo[2];
@@ -1146,9 +1149,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
     __syncthreads();
     mark(p, sweep, b, 5);
     if (tid == 0) {
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       s_last = (atomicAdd(&p.sync[m], 1) + 1 == m);
-      __threadfence();
+      if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (s_last) {
