@@ -645,48 +645,72 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   const int msw = init ? 0 : st->sweeps;
 
   // ---- append the accepted pivots (each set element is written by exactly one workgroup)
-  if (accL) {   // new element of I_<=c-1: (alpha*, i*) with alpha* in I_<=c-2
-    const int bl = c - 1;
-    const int row = p.piv[bl].row;
-    const int al = row / n, i = row - al * n;
-    const size_t dst = (size_t)bl * R + rL_old;
-    for (int k = tid; k < bl; k += blockDim.x) gLx[dst * m + k] = gLx[((size_t)(bl - 1) * R + al) * m + k];
-    if (tid == 0) {
-      p.Lpar[dst] = al;
-      p.Lnode[dst] = i;
-      gLx[dst * m + bl] = gt[i];
-      gLw[dst] = n_mul(bl >= 1 ? gLw[(size_t)(bl - 1) * R + al] : num<T>(1.0), gw[i]);
-    }
+  int alL = 0, iL = 0;   // new element of I_<=c-1: (alpha*, i*) with alpha* in I_<=c-2
+  if (accL) {
+    const int row = p.piv[c - 1].row;
+    alL = row / n;
+    iL = row - alL * n;
   }
-  if (accR) {   // new element of I_>c: (j*, beta*) with beta* in I_>c+1
+  int jR = 0, beR = 0;   // new element of I_>c: (j*, beta*) with beta* in I_>c+1
+  if (accR) {
     const int rRR = (c + 1 <= m - 2) ? p.rank[c + 1] : 1;
     const int col = p.piv[c].col;
-    const int j = col / rRR, be = col - j * rRR;
-    const size_t dst = (size_t)c * R + rR_old;
-    for (int k = c + 2 + tid; k < m; k += blockDim.x)
-      gRx[dst * m + k] = gRx[((size_t)(c + 1) * R + be) * m + k];
+    jR = col / rRR;
+    beR = col - jR * rRR;
+  }
+  // their weights, multiplied as the earlier elements' were
+  const T wL = accL ? n_mul(c - 1 >= 1 ? gLw[(size_t)(c - 2) * R + alL] : num<T>(1.0), gw[iL]) : num<T>(0.0);
+  const T wR = accR ? n_mul(gw[jR], (c + 1 <= m - 2) ? gRw[(size_t)(c + 1) * R + beR] : num<T>(1.0)) : num<T>(0.0);
+  if (accL) {
+    const int bl = c - 1;
+    const size_t dst = (size_t)bl * R + rL_old;
+    for (int k = tid; k < bl; k += blockDim.x) gLx[dst * m + k] = gLx[((size_t)(bl - 1) * R + alL) * m + k];
     if (tid == 0) {
-      p.Rnode[dst] = j;
-      p.Rpar[dst] = be;
-      gRx[dst * m + c + 1] = gt[j];
-      gRw[dst] = n_mul(gw[j], (c + 1 <= m - 2) ? gRw[(size_t)(c + 1) * R + be] : num<T>(1.0));
+      p.Lpar[dst] = alL;
+      p.Lnode[dst] = iL;
+      gLx[dst * m + bl] = gt[iL];
+      gLw[dst] = wL;
     }
   }
-  __syncthreads();
-  // ---- stage I_<=c-1 and I_>c coordinates
+  if (accR) {
+    const size_t dst = (size_t)c * R + rR_old;
+    for (int k = c + 2 + tid; k < m; k += blockDim.x)
+      gRx[dst * m + k] = gRx[((size_t)(c + 1) * R + beR) * m + k];
+    if (tid == 0) {
+      p.Rnode[dst] = jR;
+      p.Rpar[dst] = beR;
+      gRx[dst * m + c + 1] = gt[jR];
+      gRw[dst] = wR;
+    }
+  }
+  // ---- stage I_<=c-1 and I_>c coordinates; a new element is staged from its parent
+  //      row, so the staging does not wait for the appended rows (the streaming
+  //      evaluation reads those after the barrier below)
   if constexpr (!kStream) {
     for (int e = tid; e < rL_new * c; e += blockDim.x) {
       const int a = e / c, k = e % c;
-      sm.Lx[a * LD + k] = gLx[((size_t)(c - 1) * R + a) * m + k];
+      T v;
+      if (accL && a == rL_old)
+        v = (k < c - 1) ? gLx[((size_t)(c - 2) * R + alL) * m + k] : gt[iL];
+      else
+        v = gLx[((size_t)(c - 1) * R + a) * m + k];
+      sm.Lx[a * LD + k] = v;
     }
     const int nright = m - c - 1;
     for (int e = tid; e < rR_new * nright; e += blockDim.x) {
       const int a = e / nright, k = c + 1 + e % nright;
-      sm.Rx[a * LD + k] = gRx[((size_t)c * R + a) * m + k];
+      T v;
+      if (accR && a == rR_old)
+        v = (k == c + 1) ? gt[jR] : gRx[((size_t)(c + 1) * R + beR) * m + k];
+      else
+        v = gRx[((size_t)c * R + a) * m + k];
+      sm.Rx[a * LD + k] = v;
     }
   }
-  for (int a = tid; a < rL_new; a += blockDim.x) sm.Lw[a] = hasL ? gLw[(size_t)(c - 1) * R + a] : num<T>(1.0);
-  for (int a = tid; a < rR_new; a += blockDim.x) sm.Rw[a] = hasR ? gRw[(size_t)c * R + a] : num<T>(1.0);
+  for (int a = tid; a < rL_new; a += blockDim.x)
+    sm.Lw[a] = !hasL ? num<T>(1.0) : (accL && a == rL_old) ? wL : gLw[(size_t)(c - 1) * R + a];
+  for (int a = tid; a < rR_new; a += blockDim.x)
+    sm.Rw[a] = !hasR ? num<T>(1.0) : (accR && a == rR_old) ? wR : gRw[(size_t)c * R + a];
   for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = gt[i]; sm.w[i] = gw[i]; }
   __syncthreads();
   if (mb >= 0) mark(p, msw, mb, 9);
