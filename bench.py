@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # what the same counters read for a 1 GiB device copy (FETCH 2.0, WRITE 1.0).
 # Valid only for the kernel sources they were taken on (hash below); for any
 # other source the traffic is reported as null.
-SWEEP_TRAFFIC = {"source_hash": "cb7d4b6ddd5645bd", "fetch_kib": 3353.4, "fetch_scale": 2.0,
-                 "write_kib": 2009.0, "write_scale": 1.0}
+SWEEP_TRAFFIC = {"source_hash": "577f44f4fd7f62de", "fetch_kib": 3353.0, "fetch_scale": 2.0,
+                 "write_kib": 2003.6, "write_scale": 1.0}
 KERNEL_SOURCES = ("tt_device.hpp", "tt_inst.hip", "tt_kernels.hpp", "tt_launch.hpp")
 
 
@@ -203,7 +203,7 @@ def run_gpu(args):
         ctx.close()
         return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
                     s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=None,
-                    errs={}, probs=probs, batch=None, dd=None, serving=None, mc=None)
+                    errs={}, probs=probs, batch=None, dd=None, serving=None, mc=None, large=None)
 
     # the fibre-evaluation kernel alone on a large fibre set (D_10, middle mode)
     import numpy as np
