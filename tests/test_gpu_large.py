@@ -181,3 +181,32 @@ def test_d_large_against_printed_values(d, rank, tol, bound):
     assert info["err_flags"] == 0 and info["reason"] == "converged"
     assert rel < bound
     job.free()
+
+
+def test_large_jobs_outside_the_streaming_path_are_rejected():
+    # 33 or more modes: double precision jobs of the paper-form and synthetic
+    # integrands only; the evaluation, Monte Carlo and serving entry points and
+    # double-double jobs stay at 32 modes (rejected with TT_EINVAL, nothing runs)
+    import torch
+
+    from paper_1903_11554_amd.ttcross import MC_RANDOM, TT_EINVAL, TTError
+    ctx = gpu_context()
+    big = Problem("ising_d", 40, 8, 4, 1e-10)
+    cases = [lambda: ctx.job([Problem("ising_d", 40, 8, 4, 1e-20, precision="dd")]),
+             lambda: ctx.job([Problem("ising_c_u", 40, 8, 4, 1e-10)]),
+             lambda: ctx.mc_integrate(big, 1024, 4, MC_RANDOM)]
+    out = torch.empty(16, dtype=torch.float64, device="cuda")
+    idx = torch.zeros(16 * 39, dtype=torch.int32, device="cuda")
+    cases.append(lambda: ctx.eval_points(big, idx.data_ptr(), out.data_ptr(), 1))
+    srv = ctx.server(max_bytes=256 << 20, max_active=2)
+    cases.append(lambda: srv.submit(big))
+    for call in cases:
+        with pytest.raises(TTError) as exc:
+            call()
+        assert exc.value.status == TT_EINVAL
+    srv.close()
+    # the context still runs a large job afterwards, on the boundary of the two paths
+    job = ctx.job([Problem("ising_c", 34, 8, 4, 1e-9, seed=34, max_sweeps=3)])
+    info = job.run()[0]
+    assert info["err_flags"] == 0 and abs(info["value"] / 0.63 - 1) < 0.01
+    job.free()
