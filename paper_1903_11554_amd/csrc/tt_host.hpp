@@ -165,7 +165,7 @@ struct Layout {
 
 struct ProbOffsets {
   size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, LU, S, rank, piv, scale, log, hist, hexp, start, sync,
-      phase;
+      rfl, phase;
   std::vector<int64_t> foff, coff;
 };
 
@@ -207,6 +207,7 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   o.hexp = L.take((size_t)(ms + 1) * I);
   o.start = L.take((size_t)(m > 0 ? m : 1) * I);
   o.sync = L.take((size_t)(m + 1) * I);
+  o.rfl = L.take((size_t)(m > 0 ? m : 1) * I);
   o.phase = L.take((size_t)ms * (nb > 0 ? nb : 1) * kPhases * sizeof(long long));
   return o;
 }
@@ -342,6 +343,7 @@ inline ProbDesc make_desc(const tt_problem& p, const ProbOffsets& o, char* pb, c
   d.hexp = (int32_t*)(pb + o.hexp);
   d.start = (int32_t*)(pb + o.start);
   d.sync = (int32_t*)(pb + o.sync);
+  d.rfl = (int32_t*)(pb + o.rfl);
   d.done_host = done_host;
   d.st_host = st_host;
   d.phase = profiling ? (long long*)(pb + o.phase) : nullptr;

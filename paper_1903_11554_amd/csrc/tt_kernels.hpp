@@ -68,6 +68,7 @@ struct ProbDesc {
   int32_t *hexp;                         // [max_sweeps+1] their exponents
   int32_t *start;                        // [m] start multi-index
   int32_t *sync;                         // [m+1] per-sweep dataflow counters (cores ready, cores done)
+  int32_t *rfl;                          // [m] 1: core c's interpolation core is recomputed every sweep
   int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
   ProbState *st_host;                    // pinned host copy of the final state (may be null)
   long long *phase;                      // [max_sweeps][nbonds][kPhases] wall-clock marks, or null
@@ -380,6 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
     }
     for (int k = 0; k < m; ++k) p.start[k] = s_i0[k];
     for (int k = 0; k <= m; ++k) p.sync[k] = 0;
+    for (int k = 0; k < m; ++k) p.rfl[k] = 0;
     st->sweeps = 0;
     st->done = 0;
     st->reason = TT_RUNNING;
@@ -612,8 +614,116 @@ struct UpdateSmem {
   };
   T u[RMAX], cp[RMAX];
   int rowidx[RMAX];
+  int perm[RMAX];                  // row permutation of the recomputation
+  int zf;                          // the recomputation met a zero pivot
+  double rv[kSweepBlock / kWave];  // per-wave largest |C_c| written this sweep
   T delta;
 };
+
+// |C_c| above which a core's interpolation core is recomputed (see update_core)
+constexpr double kDominance = 1024.0;
+
+// running max of |x| for the dominance test; a non-finite x counts as infinite
+__device__ __forceinline__ double cmax_of(double cmax, double x) {
+  const double a = fabs(x);
+  return (a <= cmax) ? cmax : (isfinite(a) ? a : __builtin_huge_val());
+}
+
+// C_c = F_c M_c^-1 from scratch (double precision): M_c = F_c(I_<=c, :r), the
+// old cross rows sm.rowidx[0..r0) and, when a pivot was accepted this sweep,
+// prow.  With A = M_c^T, Gaussian elimination with partial pivoting gives
+// P A = L U in LDS (in wave 0, ordered by wave barriers only); every row f of
+// F_c is then solved by the workgroup as A x = f^T, x = U^-1 L^-1 P f^T, in place
+// in C_c (a solve, not a product with an inverse: its residual stays at the
+// rounding level of the factors, so C_c(I_<=c, :) stays the identity to rounding
+// even for a nearly singular cross).  Loops are kept rolled so the routine adds
+// few registers to the sweep kernel.  Marks the core for later sweeps.
+template <int RMAX, class Smem>
+__device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, const int r, const int N, const int prow,
+                                             const int r0, const double* __restrict__ Fc, const int cc,
+                                             double* __restrict__ Cc, const size_t ldC, Smem& sm) {
+  constexpr int LA = RMAX + 1;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    p.rfl[c] = 1;
+    if (prow >= 0) sm.rowidx[r0] = prow;
+  }
+  if (tid < RMAX) sm.perm[tid] = tid;
+  __syncthreads();
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int i = e / r, j = e % r;
+    sm.A[i * LA + j] = Fc[(size_t)sm.rowidx[j] * cc + i];
+  }
+  __syncthreads();
+  if (tid < kWave) {   // the elimination runs in wave 0 alone, with wave-level ordering only
+    bool zero = false;
+#pragma unroll 1
+    for (int k = 0; k < r && !zero; ++k) {
+      // pivot row among k..r-1 (r <= 64), ties to the lowest row, NaN never
+      ArgMax a{-1.0, 0x7fffffff};
+      const int i = k + tid;
+      if (i < r) {
+        a.v = fabs(sm.A[i * LA + k]);
+        a.idx = i;
+      }
+      a = wave_argmax(a);
+      zero = !(a.v > 0.0);                   // a zero column: M_c is singular
+      if (zero) break;
+      const int pi = a.idx;
+      if (pi != k) {
+        if (tid < r) {
+          const double tmp = sm.A[k * LA + tid];
+          sm.A[k * LA + tid] = sm.A[pi * LA + tid];
+          sm.A[pi * LA + tid] = tmp;
+        }
+        if (tid == 0) {
+          const int t2 = sm.perm[k];
+          sm.perm[k] = sm.perm[pi];
+          sm.perm[pi] = t2;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int i2 = k + 1 + tid;           // multipliers of the rows below, stored in place (L)
+      if (i2 < r) sm.A[i2 * LA + k] = sm.A[i2 * LA + k] / sm.A[k * LA + k];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int w = r - k - 1;
+      for (int e = tid; e < w * w; e += kWave) {
+        const int i3 = k + 1 + e / w, j = k + 1 + e % w;
+        sm.A[i3 * LA + j] = fma(-sm.A[i3 * LA + k], sm.A[k * LA + j], sm.A[i3 * LA + j]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (tid == 0) sm.zf = zero ? 1 : 0;
+  }
+  __syncthreads();
+  if (tid == 0 && sm.zf) atomicOr(&p.st->err_flags, 2);
+#pragma unroll 1
+  for (int row = tid; row < N; row += blockDim.x) {
+#pragma unroll 1
+    for (int q = 0; q < r; ++q) Cc[(size_t)q * ldC + row] = Fc[(size_t)row * cc + sm.perm[q]];
+#pragma unroll 1
+    for (int q = 1; q < r; ++q) {   // L y = P f (unit lower)
+      double s2 = Cc[(size_t)q * ldC + row];
+#pragma unroll 1
+      for (int pp = 0; pp < q; ++pp) s2 = fma(-sm.A[q * LA + pp], Cc[(size_t)pp * ldC + row], s2);
+      Cc[(size_t)q * ldC + row] = s2;
+    }
+#pragma unroll 1
+    for (int q = r - 1; q >= 0; --q) {   // U x = y
+      double s2 = Cc[(size_t)q * ldC + row];
+#pragma unroll 1
+      for (int pp = q + 1; pp < r; ++pp) s2 = fma(-sm.A[q * LA + pp], Cc[(size_t)pp * ldC + row], s2);
+      Cc[(size_t)q * ldC + row] = s2 / sm.A[q * LA + q];
+    }
+  }
+  __syncthreads();
+}
 
 template <class T, int FAM, int MAXM, int RMAX>
 __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, const int init,
@@ -794,6 +904,8 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   T* __restrict__ Cc = tp<T>(p.C) + p.Coff[c];
   const size_t ldC = (size_t)rowcap(p, c) * n;
   __syncthreads();   // the evaluation stage's LDS is reused below
+  double cmax = 0.0;   // largest |entry| of C_c written below (double jobs)
+  bool sing = false;   // a zero pivot in the incremental steps
   if (init) {        // rank 1: M_c = (B(i0)), C_c = F_c / M_c
     const int row0 = p.Lpar[(size_t)c * R] * n + p.Lnode[(size_t)c * R];
     const T m00 = Fc[(size_t)row0 * cc];
@@ -838,7 +950,10 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
           }
 #pragma unroll
           for (int a = 0; a < RMAX; ++a)
-            if (a < r0) Cc[(size_t)a * ldC + row] = x[a];
+            if (a < r0) {
+              Cc[(size_t)a * ldC + row] = x[a];
+              cmax = cmax_of(cmax, n_hi(x[a]));
+            }
         } else {   // the same solves with the row of C_c as the working storage
           for (int q = 0; q < r0; ++q) {
             T s = Fc[(size_t)row * cc + q];
@@ -849,6 +964,7 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
             T s = Cc[(size_t)a * ldC + row];
             for (int bb = a + 1; bb < r0; ++bb) s = n_nmad(Cc[(size_t)bb * ldC + row], sm.A[bb * LA + a], s);
             Cc[(size_t)a * ldC + row] = s;
+            cmax = cmax_of(cmax, n_hi(s));
           }
         }
       }
@@ -889,12 +1005,14 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
         for (int k = 0; k < r0; ++k) e = n_nmad(sm.cp[k], sm.u[k], e);
         LU[(size_t)r0 * R + r0] = e;
         sm.delta = e;
-        if (n_hi(e) == 0.0) atomicOr(&st->err_flags, 2);
+        // a double job recomputes the core instead (below); double-double flags it
+        if (n_hi(e) == 0.0 && is_dd_t<T>::value) atomicOr(&st->err_flags, 2);
       }
       __syncthreads();
       if (mb >= 0) mark(p, msw, mb, 12);
       // (b) rank-1 update of every row: e = F_c(:, r0) - C_c u, C_c <- [C_c - (e/delta) c_piv, e/delta]
       const T delta = sm.delta;
+      sing = n_hi(delta) == 0.0;
       for (int row = tid; row < N; row += blockDim.x) {
         if constexpr (kRowInRegs) {
           T x[RMAX];
@@ -907,21 +1025,52 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
           const T f = n_div(e, delta);
 #pragma unroll
           for (int k = 0; k < RMAX; ++k)
-            if (k < r0) Cc[(size_t)k * ldC + row] = n_nmad(f, sm.cp[k], x[k]);
+            if (k < r0) {
+              const T cn = n_nmad(f, sm.cp[k], x[k]);
+              Cc[(size_t)k * ldC + row] = cn;
+              cmax = cmax_of(cmax, n_hi(cn));
+            }
           Cc[(size_t)r0 * ldC + row] = f;
+          cmax = cmax_of(cmax, n_hi(f));
         } else {
           T e = Fc[(size_t)row * cc + r0];
           for (int k = 0; k < r0; ++k) e = n_nmad(Cc[(size_t)k * ldC + row], sm.u[k], e);
           const T f = n_div(e, delta);
-          for (int k = 0; k < r0; ++k)
-            Cc[(size_t)k * ldC + row] = n_nmad(f, sm.cp[k], Cc[(size_t)k * ldC + row]);
+          for (int k = 0; k < r0; ++k) {
+            const T cn = n_nmad(f, sm.cp[k], Cc[(size_t)k * ldC + row]);
+            Cc[(size_t)k * ldC + row] = cn;
+            cmax = cmax_of(cmax, n_hi(cn));
+          }
           Cc[(size_t)r0 * ldC + row] = f;
+          cmax = cmax_of(cmax, n_hi(f));
         }
       }
     }
     if (mb >= 0) mark(p, msw, mb, 13);
+    // the largest |C_c| written (infinite for a zero pivot): one value per wave,
+    // combined after the barrier below
+    if constexpr (!is_dd_t<T>::value) {
+      const double cm = wave_max(sing ? __builtin_huge_val() : cmax);
+      if ((tid & (kWave - 1)) == 0) sm.rv[tid / kWave] = cm;
+    }
   }
   __syncthreads();
+  // ---- recomputation of C_c for crosses far from dominant (double jobs).  The
+  //      incremental steps above are exact algebra, but each carries the rounding
+  //      already in C_c over with a factor of about |C_c|^2.  Alg. 6 takes each
+  //      bond's pivot against the neighbours' previous sets, and on some
+  //      integrands (C_d with few nodes) the crosses lose dominance, |C_c|
+  //      reaching 1e4 within a few sweeps.  Once |C_c| exceeds kDominance (or a
+  //      pivot is zero) the core is recomputed from F_c with a pivoted LU of the
+  //      cross in this and every later sweep, as the plain definition does.
+  if constexpr (!is_dd_t<T>::value) {
+    if (!init) {
+      double cm = 0.0;
+      for (int w = 0; w < kSweepBlock / kWave; ++w) cm = fmax(cm, sm.rv[w]);
+      if (p.rfl[c] || !(cm <= kDominance))
+        refresh_core<RMAX>(p, c, r, N, accR ? p.piv[c].row : -1, r0, Fc, cc, Cc, ldC, sm);
+    }
+  }
   // ---- S_c(alpha, k) = sum_i C_c(alpha, i, k)
   for (int e = tid; e < rL_new * r; e += blockDim.x) {
     const int al = e / r, k = e % r;

@@ -210,3 +210,24 @@ def test_large_jobs_outside_the_streaming_path_are_rejected():
     info = job.run()[0]
     assert info["err_flags"] == 0 and abs(info["value"] / 0.63 - 1) < 0.01
     job.free()
+
+
+@pytest.mark.parametrize("d,rank,tol,bound", [(32, 16, 1e-12, 1e-7), (64, 12, 1e-11, 1e-11), (64, 12, 1e-12, 1e-11)])
+def test_c_d_with_few_nodes_stays_accurate(d, rank, tol, bound):
+    # C_d with 33 nodes: the crosses of Alg. 6 lose dominance within a few sweeps
+    # (|C_c| up to 1e4 and more); kept incrementally, these interpolation cores
+    # drifted and the quadrature diverged.  The cores far from dominance are
+    # recomputed from F_c, and the values stay within the distance of C_d from
+    # the limit 2 exp(-2 gamma) (about 1e-9 at d = 32 and below 4e-19 at d = 64).
+    p = Problem("ising_c", d, 33, rank, tol, seed=d)
+    ctx = gpu_context()
+    job = ctx.job([p])
+    info = job.run()[0]
+    c_inf = 2.0 * math.exp(-2.0 * 0.57721566490153286061)
+    hist = job.history(0)
+    print(f"C_{d} tol {tol:g}: {info['value']!r} sweeps {info['sweeps']} "
+          f"worst {max(abs(h / c_inf - 1) for h in hist[5:]):.2e}", flush=True)
+    assert info["err_flags"] == 0 and info["reason"] == "converged"
+    assert abs(info["value"] / c_inf - 1) < bound
+    assert max(abs(h / c_inf - 1) for h in hist[5:]) < 1e-3   # no excursion on the way
+    job.free()
