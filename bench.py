@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # what the same counters read for a 1 GiB device copy (FETCH 2.0, WRITE 1.0).
 # Valid only for the kernel sources they were taken on (hash below); for any
 # other source the traffic is reported as null.
-SWEEP_TRAFFIC = {"source_hash": "577f44f4fd7f62de", "fetch_kib": 3353.0, "fetch_scale": 2.0,
-                 "write_kib": 2003.6, "write_scale": 1.0}
+SWEEP_TRAFFIC = {"source_hash": "b97a63d5bbfe890e", "fetch_kib": 3378.5, "fetch_scale": 2.0,
+                 "write_kib": 2005.5, "write_scale": 1.0}
 KERNEL_SOURCES = ("tt_device.hpp", "tt_inst.hip", "tt_kernels.hpp", "tt_launch.hpp")
 
 
@@ -550,7 +550,8 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "alg_bytes_per_launch": r["s_bytes"] / max(nl_s, 1),
             "launches": nl_s, "avg_launch_ms": ms_s / max(nl_s, 1),
-            "flops_per_launch": r["s_flops"] / max(nl_s, 1), "evals_per_launch": r["s_evals"] / max(nl_s, 1)}
+            "flops_per_launch": r["s_flops"] / max(nl_s, 1), "evals_per_launch": r["s_evals"] / max(nl_s, 1),
+            "kernel_evals_per_s": r["s_evals"] / max(ms_s * 1e-3, 1e-12)}
     fib = None
     if r["fib"] is not None:
         nl, ms, npts, ff, ft = r["fib"]
