@@ -703,23 +703,56 @@ __device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, con
   }
   __syncthreads();
   if (tid == 0 && sm.zf) atomicOr(&p.st->err_flags, 2);
+  // Row solves in blocks of kB unknowns held in registers: the earlier (forward)
+  // or later (backward) unknowns are read from C_c once per block, not once per
+  // unknown.  The guards on q0 + t < r depend only on the block: no divergence.
+  constexpr int kB = 4;
 #pragma unroll 1
   for (int row = tid; row < N; row += blockDim.x) {
 #pragma unroll 1
-    for (int q = 0; q < r; ++q) Cc[(size_t)q * ldC + row] = Fc[(size_t)row * cc + sm.perm[q]];
+    for (int q0 = 0; q0 < r; q0 += kB) {   // L y = P f (unit lower)
+      double acc[kB];
+#pragma unroll
+      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? Fc[(size_t)row * cc + sm.perm[q0 + t]] : 0.0;
 #pragma unroll 1
-    for (int q = 1; q < r; ++q) {   // L y = P f (unit lower)
-      double s2 = Cc[(size_t)q * ldC + row];
-#pragma unroll 1
-      for (int pp = 0; pp < q; ++pp) s2 = fma(-sm.A[q * LA + pp], Cc[(size_t)pp * ldC + row], s2);
-      Cc[(size_t)q * ldC + row] = s2;
+      for (int pp = 0; pp < q0; ++pp) {
+        const double y = Cc[(size_t)pp * ldC + row];
+#pragma unroll
+        for (int t = 0; t < kB; ++t)
+          if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + pp], y, acc[t]);
+      }
+#pragma unroll
+      for (int t = 1; t < kB; ++t)
+#pragma unroll
+        for (int u = 0; u < t; ++u)
+          if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + q0 + u], acc[u], acc[t]);
+#pragma unroll
+      for (int t = 0; t < kB; ++t)
+        if (q0 + t < r) Cc[(size_t)(q0 + t) * ldC + row] = acc[t];
     }
 #pragma unroll 1
-    for (int q = r - 1; q >= 0; --q) {   // U x = y
-      double s2 = Cc[(size_t)q * ldC + row];
+    for (int q0 = ((r - 1) / kB) * kB; q0 >= 0; q0 -= kB) {   // U x = y
+      double acc[kB];
+#pragma unroll
+      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? Cc[(size_t)(q0 + t) * ldC + row] : 0.0;
 #pragma unroll 1
-      for (int pp = q + 1; pp < r; ++pp) s2 = fma(-sm.A[q * LA + pp], Cc[(size_t)pp * ldC + row], s2);
-      Cc[(size_t)q * ldC + row] = s2 / sm.A[q * LA + q];
+      for (int pp = q0 + kB; pp < r; ++pp) {
+        const double x = Cc[(size_t)pp * ldC + row];
+#pragma unroll
+        for (int t = 0; t < kB; ++t)
+          if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + pp], x, acc[t]);
+      }
+#pragma unroll
+      for (int t = kB - 1; t >= 0; --t)
+        if (q0 + t < r) {
+#pragma unroll
+          for (int u = t + 1; u < kB; ++u)
+            if (q0 + u < r) acc[t] = fma(-sm.A[(q0 + t) * LA + q0 + u], acc[u], acc[t]);
+          acc[t] = acc[t] / sm.A[(q0 + t) * LA + q0 + t];
+        }
+#pragma unroll
+      for (int t = 0; t < kB; ++t)
+        if (q0 + t < r) Cc[(size_t)(q0 + t) * ldC + row] = acc[t];
     }
   }
   __syncthreads();
