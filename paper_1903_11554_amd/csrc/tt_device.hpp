@@ -346,6 +346,114 @@ __device__ __forceinline__ double synthetic_stream(int family, int m, const Y& y
   return e + c;
 }
 
+// The coordinates of a fibre point in the sweep kernels: the row of a left set
+// (y_0..y_{nL-1}), one or two nodes, and the row of a right set (y_{nL+nM}..y_{m-1},
+// indexed by the absolute coordinate).  Loops over the two rows are contiguous,
+// so their loads issue several at a time instead of one per iteration.
+struct Segs {
+  const double* L;
+  int nL;
+  double mid0, mid1;
+  int nM;          // 1 or 2 nodes
+  const double* R;
+  int m;
+};
+
+template <class F>
+__device__ __forceinline__ void seg_each(const Segs& s, F&& f) {
+#pragma unroll 4
+  for (int k = 0; k < s.nL; ++k) f(k, s.L[k]);
+  f(s.nL, s.mid0);
+  if (s.nM > 1) f(s.nL + 1, s.mid1);
+#pragma unroll 4
+  for (int k = s.nL + s.nM; k < s.m; ++k) f(k, s.R[k]);
+}
+
+// Products of the runs y_a..y_b of A_d from a given a, in chunks of four factors:
+// the exit test on p < 2^-54 is taken after each chunk, which changes no bit, since
+// the factors after the first such p leave pn and pd unchanged (see above).
+struct PairRun {
+  double pn, pd, p;
+  __device__ __forceinline__ void step(double y) {
+    p = p * y;
+    pn = fma(-pn, p, pn);
+    pd = fma(pd, p, pd);
+  }
+  __device__ __forceinline__ bool done() const { return p < 0x1.0p-54; }
+  __device__ __forceinline__ void renorm() {
+    const int e = ilogb(pd);
+    pn = ldexp(pn, -e);
+    pd = ldexp(pd, -e);
+  }
+  // factors ptr[k0..k1); returns true once the run is over
+  __device__ __forceinline__ bool span(const double* __restrict__ ptr, int k0, int k1) {
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      const double y0 = ptr[k], y1 = ptr[k + 1], y2 = ptr[k + 2], y3 = ptr[k + 3];
+      step(y0);
+      step(y1);
+      step(y2);
+      step(y3);
+      if (done()) return true;
+      if (((k - k0) & 28) == 28) renorm();   // every 32 factors
+    }
+    for (; k < k1; ++k) {
+      step(ptr[k]);
+      if (done()) return true;
+    }
+    renorm();
+    return false;
+  }
+};
+
+__device__ __forceinline__ double ising_paper_seg(int family, const Segs& s) {
+  const int m = s.m;
+  double den = 1.0;
+  if (family != TT_ISING_E) {
+    double P = 1.0, q = 0.0, sf = 0.0;
+    seg_each(s, [&](int, double yk) {
+      P = P * yk;
+      q = q + P;
+      sf = fma(yk, sf, yk);
+    });
+    den = (1.0 + q) * (1.0 + sf);
+  }
+  double nm = 2.0;
+  if (family != TT_ISING_C) {
+    PairRun run{1.0, 1.0, 1.0};
+    const int mid = s.nL, right = s.nL + s.nM;
+    for (int a = 0; a < m; ++a) {
+      run.p = 1.0;
+      bool over = false;
+      if (a < mid) over = run.span(s.L, a, mid);
+      if (!over && a <= mid) {
+        run.step(s.mid0);
+        over = run.done();
+      }
+      if (!over && s.nM > 1 && a <= mid + 1) {
+        run.step(s.mid1);
+        over = run.done();
+      }
+      if (!over) run.span(s.R, a > right ? a : right, m);
+      run.renorm();
+    }
+    const double r = run.pn / run.pd;
+    nm = nm * r * r;
+  }
+  return nm / den;
+}
+
+__device__ __forceinline__ double synthetic_seg(int family, const Segs& s, const double* __restrict__ a,
+                                                const double* __restrict__ b) {
+  double sum = 0.0;
+  seg_each(s, [&](int k, double yk) { sum = fma(a[k], yk, sum); });
+  const double e = exp(-sum);
+  if (family == TT_PROD_EXP) return e;
+  double c = 1.0;
+  seg_each(s, [&](int k, double yk) { c = c * cos(b[k] * yk); });
+  return e + c;
+}
+
 // --------------------------------------------------------------- reductions
 // argmax of |e| with ties to the lowest index; NaN never wins (comparisons are false).
 struct ArgMax {

@@ -154,6 +154,20 @@ __device__ __forceinline__ double integrand_stream(const FamilyArgs& fa, const Y
   }
 }
 
+template <int FAM>
+__device__ __forceinline__ double integrand_seg(const FamilyArgs& fa, const Segs& sg) {
+  static_assert(FAM == FAM_PAPER || FAM == FAM_SYNTH || FAM == FAM_ANY, "no streaming u-form");
+  if constexpr (FAM == FAM_PAPER) {
+    return ising_paper_seg(fa.family, sg);
+  } else if constexpr (FAM == FAM_SYNTH) {
+    return synthetic_seg(fa.family, sg, fa.a, fa.b);
+  } else {
+    if (fa.family == TT_ISING_C || fa.family == TT_ISING_D || fa.family == TT_ISING_E)
+      return ising_paper_seg(fa.family, sg);
+    return synthetic_seg(fa.family, sg, fa.a, fa.b);
+  }
+}
+
 // v = mant * 2^e with 1/2 <= |mant| < 1 (mant = v for 0 and non-finite v)
 template <class T>
 __device__ __forceinline__ T normalise(T v, int& e) {
@@ -510,10 +524,8 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
       if constexpr (kStream) {
         const T* Lrow = gLx + ((size_t)(b > 0 ? b - 1 : 0) * R + al) * m;
         const T* Rrow = gRx + ((size_t)(b + 1 <= m - 2 ? b + 1 : 0) * R + be) * m;
-        const T ti = sm.t[i], tj = sm.t[j];
-        a = n_mul(W, integrand_stream<FAM>(fa, [&](int k) {
-          return k < b ? Lrow[k] : k == b ? ti : k == b + 1 ? tj : Rrow[k];
-        }));
+        const Segs sg{Lrow, b, sm.t[i], sm.t[j], 2, Rrow, m};
+        a = n_mul(W, integrand_seg<FAM>(fa, sg));
       } else {
         T y[MAXM];
 #pragma unroll
@@ -889,8 +901,8 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     if constexpr (kStream) {
       const T* Lrow = gLx + ((size_t)(c > 0 ? c - 1 : 0) * R + al) * m;
       const T* Rrow = gRx + ((size_t)(c <= m - 2 ? c : 0) * R + be) * m;
-      const T ti = sm.t[i];
-      v = n_mul(W, integrand_stream<FAM>(fa, [&](int k) { return k < c ? Lrow[k] : k == c ? ti : Rrow[k]; }));
+      const Segs sg{Lrow, c, sm.t[i], 0.0, 1, Rrow, m};
+      v = n_mul(W, integrand_seg<FAM>(fa, sg));
     } else {
       T y[MAXM];
 #pragma unroll
