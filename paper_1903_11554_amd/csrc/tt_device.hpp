@@ -406,17 +406,46 @@ struct PairRun {
   }
 };
 
+// B_d's prefix sum q = sum_b y_0..y_b and suffix recurrence s <- y (1 + s) over a
+// point, four coordinates at a time: a block of four is summarised on its own
+// (its product p4, its prefix sum q4 and its recurrence value g4 from s = 0),
+// then q <- q + P q4, s <- g4 + p4 s, P <- P p4.  The three running chains take
+// one operation per block, so the blocks' own work overlaps.
+struct PrefixSuffix {
+  double P = 1.0, q = 0.0, s = 0.0;
+  __device__ __forceinline__ void one(double y) {
+    P = P * y;
+    q = q + P;
+    s = fma(y, s, y);
+  }
+  __device__ __forceinline__ void four(double y0, double y1, double y2, double y3) {
+    const double p01 = y0 * y1, p012 = p01 * y2, p4 = p012 * y3;
+    const double q4 = (y0 + p01) + (p012 + p4);
+    double g4 = y0;
+    g4 = fma(y1, g4, y1);
+    g4 = fma(y2, g4, y2);
+    g4 = fma(y3, g4, y3);
+    q = fma(P, q4, q);
+    s = fma(p4, s, g4);
+    P = P * p4;
+  }
+  __device__ __forceinline__ void span(const double* __restrict__ ptr, int k0, int k1) {
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) four(ptr[k], ptr[k + 1], ptr[k + 2], ptr[k + 3]);
+    for (; k < k1; ++k) one(ptr[k]);
+  }
+};
+
 __device__ __forceinline__ double ising_paper_seg(int family, const Segs& s) {
   const int m = s.m;
   double den = 1.0;
   if (family != TT_ISING_E) {
-    double P = 1.0, q = 0.0, sf = 0.0;
-    seg_each(s, [&](int, double yk) {
-      P = P * yk;
-      q = q + P;
-      sf = fma(yk, sf, yk);
-    });
-    den = (1.0 + q) * (1.0 + sf);
+    PrefixSuffix ps;
+    ps.span(s.L, 0, s.nL);
+    ps.one(s.mid0);
+    if (s.nM > 1) ps.one(s.mid1);
+    ps.span(s.R, s.nL + s.nM, m);
+    den = (1.0 + ps.q) * (1.0 + ps.s);
   }
   double nm = 2.0;
   if (family != TT_ISING_C) {
