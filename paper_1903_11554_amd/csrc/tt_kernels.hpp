@@ -1138,6 +1138,7 @@ constexpr int kIntStageBytes = 49152;   // S staged in LDS at once
 template <class T>
 struct IntSmem {
   static constexpr int kStage = kIntStageBytes / (int)sizeof(T);
+  static constexpr int kIntBatch = (kStage + kSweepBlock - 1) / kSweepBlock;   // loads in flight per thread
   T v[TT_MAX_RANK], v2[TT_MAX_RANK];
   T stage[kStage];
   int s_rank[TT_MAX_MODES];
@@ -1148,6 +1149,7 @@ struct IntSmem {
 template <class T>
 __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int init, IntSmem<T>& sm) {
   constexpr int kStage = IntSmem<T>::kStage;
+  constexpr int kIntBatch = IntSmem<T>::kIntBatch;
   ProbState* st = p.st;
   if (st->done) return;
   T* __restrict__ hist = tp<T>(p.hist);
@@ -1208,11 +1210,31 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
     const bool direct = (c1 == c0);
     if (direct) c1 = c0 + 1;
     if (!direct) {
-      for (int c = c0; c < c1; ++c) {
-        const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
-        const T* __restrict__ S = gS + (size_t)c * R * R;
-        T* dst = stage + s_off[c - c0];
-        for (int e = tid; e < rl * rr; e += blockDim.x) dst[e] = S[(size_t)(e / rr) * R + e % rr];
+      // the staged entries as one flat range: each thread issues all its loads
+      // before the first store, so a stage costs one memory latency, not one
+      // per core
+      const int total = s_off[c1 - c0], ncore = c1 - c0;
+      for (int e0 = tid; e0 < total; e0 += kIntBatch * (int)blockDim.x) {
+        T buf[kIntBatch];
+#pragma unroll
+        for (int u = 0; u < kIntBatch; ++u) {
+          const int e = e0 + u * (int)blockDim.x;
+          if (e < total) {
+            int lo = 0, hi = ncore - 1;   // the core holding entry e: last s_off <= e
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (s_off[mid] <= e) lo = mid;
+              else hi = mid - 1;
+            }
+            const int c = c0 + lo, rr = (c <= m - 2) ? s_rank[c] : 1, el = e - s_off[lo];
+            buf[u] = gS[(size_t)c * R * R + (size_t)(el / rr) * R + el % rr];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kIntBatch; ++u) {
+          const int e = e0 + u * (int)blockDim.x;
+          if (e < total) stage[e] = buf[u];
+        }
       }
       __syncthreads();
     }
