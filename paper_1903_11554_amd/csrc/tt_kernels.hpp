@@ -1137,19 +1137,31 @@ constexpr int kIntStageBytes = 49152;   // S staged in LDS at once
 
 template <class T>
 struct IntSmem {
-  static constexpr int kStage = kIntStageBytes / (int)sizeof(T);
-  static constexpr int kIntBatch = (kStage + kSweepBlock - 1) / kSweepBlock;   // loads in flight per thread
-  T v[TT_MAX_RANK], v2[TT_MAX_RANK];
+  static constexpr int kStage = kIntStageBytes / (int)sizeof(T) > TT_MAX_RANK * TT_MAX_RANK
+                                     ? kIntStageBytes / (int)sizeof(T) : TT_MAX_RANK * TT_MAX_RANK;
+  static constexpr int kIntBatch = 6;   // staging loads (of one double) in flight per thread
+  T v[kWave], v2[kWave];
   T stage[kStage];
   int s_rank[TT_MAX_MODES];
   int s_off[TT_MAX_MODES + 1];
+  int wsum[kSweepBlock / kWave];
   int cnt[2];   // accepted pivots, largest rank
 };
 
-template <class T>
+// Column entries of a factor read at once in the quadrature chain: a rank-16 or
+// rank-32 kernel reads 16 (one block covers rank 16), the others 8, which keeps
+// their register count where the rest of the sweep puts it; 4 for double-double.
+template <class T, int RMAX>
+constexpr int chain_block_size() {
+  return sizeof(T) != sizeof(double) ? 4 : (RMAX == 16 || RMAX == 32) ? 16 : 8;
+}
+
+template <class T, int CB>
 __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int init, IntSmem<T>& sm) {
   constexpr int kStage = IntSmem<T>::kStage;
   constexpr int kIntBatch = IntSmem<T>::kIntBatch;
+  constexpr int kChainBlk = CB;
+  static_assert(kWave % kChainBlk == 0, "a block of v never runs past entry kWave - 1");
   ProbState* st = p.st;
   if (st->done) return;
   T* __restrict__ hist = tp<T>(p.hist);
@@ -1186,85 +1198,127 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
   const int below_cap = __syncthreads_or(below);
   const int nacc = sm.cnt[0];
   maxr = sm.cnt[1];
+  // In LDS a factor S_c (r_{c-1} x r_c, r_{m-1} = 1) is held column by column,
+  // each column padded with zeros to a whole number of chain blocks.  s_off[c] is
+  // the summed size of S_c' over 1 <= c' < c: where each factor sits once the
+  // factors are laid out back to back
+  auto pad = [](int r) { return (r + kChainBlk - 1) / kChainBlk * kChainBlk; };
+  {
+    const int nf = m - 1, per = (nf + (int)blockDim.x - 1) / (int)blockDim.x, f0 = tid * per;
+    const int f1 = min(f0 + per, nf), lane = tid & (kWave - 1), wid = tid / kWave;
+    int loc = 0;
+    for (int f = f0; f < f1; ++f) loc += pad(s_rank[f]) * (f + 1 <= m - 2 ? s_rank[f + 1] : 1);
+    int x = loc;   // inclusive scan over the wave, then over the waves
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int y = __shfl_up(x, d, kWave);
+      if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) sm.wsum[wid] = x;
+    __syncthreads();
+    int run = x - loc;
+    for (int w = 0; w < wid; ++w) run += sm.wsum[w];
+    for (int f = f0; f < f1; ++f) {
+      run += pad(s_rank[f]) * (f + 1 <= m - 2 ? s_rank[f + 1] : 1);
+      s_off[f + 2] = run;
+    }
+    if (tid == 0) s_off[1] = 0;
+  }
   // v = S_0 (1 x r_0), then v <- v S_c for c = 1..m-1 (2m-1 matrices, inverses in C)
-  for (int k = tid; k < s_rank[0]; k += blockDim.x) v[k] = gS[k];
+  if (tid < kWave) v[tid] = tid < s_rank[0] ? gS[tid] : num<T>(0.0);
+  __syncthreads();
   int vexp = 0;   // v times 2^vexp is the chain's value (kept by wave 0)
   int c0 = 1;
   while (c0 < m) {
-    // stage as many consecutive S_c as fit, all loads in flight together; a core
-    // whose S_c alone exceeds the stage is multiplied straight from memory
-    if (tid == 0) {
-      int off = 0, c = c0;
-      s_off[0] = 0;
-      while (c < m) {
-        const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
-        if (off + rl * rr > kStage) break;
-        off += rl * rr;
-        s_off[c - c0 + 1] = off;
-        ++c;
-      }
-      s_off[TT_MAX_MODES] = c;
+    // stage S_c0 .. S_c1-1, as many consecutive factors as fit (the stage holds
+    // at least one S_c of the largest rank), as one flat range of doubles (a
+    // double-double entry is two): each thread issues all its loads before the
+    // first store, so a stage costs one memory latency, not one per core
+    const int base = s_off[c0];
+    int c1 = c0 + 1;
+    for (int hi = m; c1 < hi;) {   // last c1 with s_off[c1] - base <= kStage
+      const int mid = (c1 + hi + 1) >> 1;
+      if (s_off[mid] - base <= kStage) c1 = mid;
+      else hi = mid - 1;
     }
-    __syncthreads();
-    int c1 = s_off[TT_MAX_MODES];
-    const bool direct = (c1 == c0);
-    if (direct) c1 = c0 + 1;
-    if (!direct) {
-      // the staged entries as one flat range: each thread issues all its loads
-      // before the first store, so a stage costs one memory latency, not one
-      // per core
-      const int total = s_off[c1 - c0], ncore = c1 - c0;
-      for (int e0 = tid; e0 < total; e0 += kIntBatch * (int)blockDim.x) {
-        T buf[kIntBatch];
+    {
+      constexpr int W = (int)(sizeof(T) / sizeof(double));
+      const double* __restrict__ gSw = reinterpret_cast<const double*>(gS);
+      double* stw = reinterpret_cast<double*>(stage);
+      const int total = (s_off[c1] - base) * W;
+      for (int w0 = tid; w0 < total; w0 += kIntBatch * (int)blockDim.x) {
+        double buf[kIntBatch];
 #pragma unroll
         for (int u = 0; u < kIntBatch; ++u) {
-          const int e = e0 + u * (int)blockDim.x;
-          if (e < total) {
-            int lo = 0, hi = ncore - 1;   // the core holding entry e: last s_off <= e
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (s_off[mid] <= e) lo = mid;
+          const int w = w0 + u * (int)blockDim.x;
+          if (w < total) {
+            const int e = w / W;
+            int c = c0;   // the factor holding entry e: last s_off[c] - base <= e
+            for (int hi = c1 - 1; c < hi;) {
+              const int mid = (c + hi + 1) >> 1;
+              if (s_off[mid] - base <= e) c = mid;
               else hi = mid - 1;
             }
-            const int c = c0 + lo, rr = (c <= m - 2) ? s_rank[c] : 1, el = e - s_off[lo];
-            buf[u] = gS[(size_t)c * R * R + (size_t)(el / rr) * R + el % rr];
+            const int rl = s_rank[c - 1], ap = pad(rl), el = e - (s_off[c] - base);
+            const int k = el / ap, a = el - k * ap;
+            buf[u] = a < rl ? gSw[((size_t)c * R * R + (size_t)a * R + k) * W + (w - e * W)] : 0.0;
           }
         }
 #pragma unroll
         for (int u = 0; u < kIntBatch; ++u) {
-          const int e = e0 + u * (int)blockDim.x;
-          if (e < total) stage[e] = buf[u];
+          const int w = w0 + u * (int)blockDim.x;
+          if (w < total) stw[w] = buf[u];
         }
       }
       __syncthreads();
     }
-    // the chain itself runs in wave 0 alone (lane k owns column k of every S_c,
-    // r <= 64), ping-ponging v and v2 in LDS with wave-level ordering only;
-    // every 16 factors v is brought back near 1 by an exact power of two, so
-    // long chains (up to a thousand modes) stay in the double range
+    // the chain itself runs in wave 0 alone: lane k owns column k of every staged
+    // S_c (r <= 64) and v ping-pongs between two LDS vectors with wave-level
+    // ordering only (all 64 entries written, zero above the rank).  A factor's
+    // rank and place are read one factor ahead; a block of its column (contiguous,
+    // zero-padded) and of v (a broadcast) are read at once, and v[a] S_c(a, k) is
+    // summed in four interleaved partial sums (a = 0, 4, 8, .. in the first).
+    // Lanes above the rank read the last column and are zeroed after.  Every 16
+    // factors v is brought back near 1 by an exact power of two, so long chains
+    // (up to a thousand modes) stay in the double range
     if (tid < kWave) {
+      int rl = s_rank[c0 - 1];
+      int rr = (c0 <= m - 2) ? s_rank[c0] : 1, off = 0;
       for (int c = c0; c < c1; ++c) {
-        const int rl = s_rank[c - 1], rr = (c <= m - 2) ? s_rank[c] : 1;
-        const T* Sc = direct ? gS + (size_t)c * R * R : stage + s_off[c - c0];
-        const int ldS = direct ? R : rr;
-        T s = num<T>(0.0);
-        if (tid < rr)
-          for (int a = 0; a < rl; ++a) s = n_mad(v[a], Sc[a * ldS + tid], s);
+        const int rrn = (c + 1 <= m - 2) ? s_rank[c + 1] : 1;
+        const int offn = s_off[c + 1] - base;
+        const T* colp = stage + off + min(tid, rr - 1) * pad(rl);
+        T acc[4] = {num<T>(0.0), num<T>(0.0), num<T>(0.0), num<T>(0.0)};
+        for (int a0 = 0; a0 < rl; a0 += kChainBlk) {
+          T col[kChainBlk], vv[kChainBlk];
+#pragma unroll
+          for (int u = 0; u < kChainBlk; ++u) {
+            col[u] = colp[a0 + u];
+            vv[u] = v[a0 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < kChainBlk; ++u) acc[u & 3] = n_mad(vv[u], col[u], acc[u & 3]);
+        }
+        T s = n_add(n_add(acc[0], acc[1]), n_add(acc[2], acc[3]));
+        if (tid >= rr) s = num<T>(0.0);
         if ((c & 15) == 0) {
-          const double mag = wave_max(fabs(n_hi(s)));   // lanes >= rr hold 0
+          const double mag = wave_max(fabs(n_hi(s)));
           if (mag > 0.0 && isfinite(mag)) {
             const int e = ilogb(mag) + 1;
             s = n_ldexp(s, -e);
             vexp += e;
           }
         }
-        if (tid < rr) v2[tid] = s;
+        v2[tid] = s;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         T* tmp = v;
         v = v2;
         v2 = tmp;
+        rl = rr;
+        rr = rrn;
+        off = offn;
       }
     } else {
       for (int c = c0; c < c1; ++c) {   // the other waves track which buffer holds v
@@ -1337,7 +1391,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_update(ProbDesc* __restrict__ P
 template <class T>
 __global__ __launch_bounds__(kIntBlock) void k_integral(ProbDesc* __restrict__ P, int init) {
   __shared__ IntSmem<T> sm;
-  integral_problem<T>(P[blockIdx.x], init, sm);
+  integral_problem<T, chain_block_size<T, 8>()>(P[blockIdx.x], init, sm);
 }
 
 template <class T, int MAXM, int RMAX>
@@ -1395,7 +1449,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(ProbDesc* __restrict__ P,
     }
     __syncthreads();
     if (s_last) {
-      integral_problem<T>(p, 0, sm.i);
+      integral_problem<T, chain_block_size<T, RMAX>()>(p, 0, sm.i);
       __syncthreads();
       for (int k = tid; k <= m; k += blockDim.x) p.sync[k] = 0;   // every hand-over of this sweep is done
       mark(p, sweep, b, 6);
