@@ -530,7 +530,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); integrals are independent "
-              f"and shard across GPUs without communication, which this build does not run.",
+              f"and would shard across GPUs without communication, but the library drives one "
+              f"device per process and the benchmark measures that one device.",
               file=sys.stderr)
         sys.exit(2)
     r = run_gpu(args)

@@ -34,7 +34,7 @@ times 2^(E - s m).  Both scalings are exact, so for every size that does not
 leave the double range the decisions and the values are those of the unscaled
 computation, bit for bit.
 
-Readings of the paper where it is silent (also listed in the design doc):
+Readings of the paper where it is silent:
   * start: rank 1 at the largest |B| among 1024 SplitMix64 samples of the grid;
   * samples: |R| = min(r_{b-1} n + n r_{b+1}, 1024), uniform over the superblock,
     drawn from SplitMix64 keyed by (seed, sweep, bond, sample);
