@@ -471,26 +471,44 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   if (tid == 0) { sm.e_star = num<T>(0.0); sm.a_star = num<T>(0.0); }
   // C_d's value at (alpha, i, j, beta) depends on the coordinates only through
   // B_d's prefix sum and suffix recurrence, and both compose over a split of the
-  // coordinates.  Each row of the two index sets is summarised once (wave 0 the
-  // left rows, wave 1 the right ones), so a point of the search costs two node
-  // steps and a join instead of a pass over all m coordinates.
+  // coordinates: (P1, q1, s1) then (P2, q2, g2) give (P1 P2, q1 + P1 q2, g2 + P2 s1),
+  // g2 being the recurrence over the second part from zero.  Each row of the two
+  // index sets is summarised once, by 16 lanes that each walk a sixteenth of it
+  // and join their parts in order, so a point of the search costs two node steps
+  // and a join instead of a pass over all m coordinates.
   bool rowsum = false;
   if constexpr (kStream && (FAM == FAM_PAPER || FAM == FAM_ANY)) {
     rowsum = fa.family == TT_ISING_C;
     if (rowsum) {
-      if (tid < rL) {
+      constexpr int kLpr = 16;   // lanes per row
+      const int part = tid % kLpr;
+      for (int row = tid / kLpr; row < rL + rR; row += blockDim.x / kLpr) {
+        const bool left = row < rL;
+        const int idx = left ? row : row - rL;
+        const bool has = left ? b > 0 : b + 1 <= m - 2;
+        const T* ptr = left ? gLx + ((size_t)(b > 0 ? b - 1 : 0) * R + idx) * m
+                            : gRx + ((size_t)(b + 1 <= m - 2 ? b + 1 : 0) * R + idx) * m;
+        const int k0 = left ? 0 : b + 2, k1 = has ? (left ? b : m) : k0;
+        const int chunk = ((k1 - k0 + kLpr - 1) / kLpr + 3) & ~3;
+        const int lo = min(k0 + part * chunk, k1), hi = min(lo + chunk, k1);
         PrefixSuffix ps;
-        if (b > 0) ps.span(gLx + ((size_t)(b - 1) * R + tid) * m, 0, b);
-        sm.sL[tid] = ps.P;
-        sm.sL[TT_MAX_RANK + tid] = ps.q;
-        sm.sL[2 * TT_MAX_RANK + tid] = ps.s;
-      } else if (tid >= kWave && tid - kWave < rR) {
-        const int be = tid - kWave;
-        PrefixSuffix ps;
-        if (b + 1 <= m - 2) ps.span(gRx + ((size_t)(b + 1) * R + be) * m, b + 2, m);
-        sm.sR[be] = ps.P;
-        sm.sR[TT_MAX_RANK + be] = ps.q;
-        sm.sR[2 * TT_MAX_RANK + be] = ps.s;
+        ps.span(ptr, lo, hi);
+#pragma unroll
+        for (int d = 1; d < kLpr; d <<= 1) {   // join part + d onto part, in order
+          const double P2 = __shfl_down(ps.P, d, kLpr), q2 = __shfl_down(ps.q, d, kLpr);
+          const double s2 = __shfl_down(ps.s, d, kLpr);
+          if ((part & (2 * d - 1)) == 0) {
+            ps.q = fma(ps.P, q2, ps.q);
+            ps.s = fma(P2, ps.s, s2);
+            ps.P = ps.P * P2;
+          }
+        }
+        if (part == 0) {
+          double* dst = left ? sm.sL : sm.sR;
+          dst[idx] = ps.P;
+          dst[TT_MAX_RANK + idx] = ps.q;
+          dst[2 * TT_MAX_RANK + idx] = ps.s;
+        }
       }
     }
   }
