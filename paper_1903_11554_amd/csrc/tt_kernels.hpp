@@ -1195,8 +1195,8 @@ constexpr int kIntStageBytes = 49152;   // S staged in LDS at once
 
 template <class T>
 struct IntSmem {
-  static constexpr int kStage = kIntStageBytes / (int)sizeof(T) > TT_MAX_RANK * TT_MAX_RANK
-                                     ? kIntStageBytes / (int)sizeof(T) : TT_MAX_RANK * TT_MAX_RANK;
+  static constexpr int kStage = kIntStageBytes / (int)sizeof(T) > TT_MAX_RANK * (TT_MAX_RANK + 1)
+                                     ? kIntStageBytes / (int)sizeof(T) : TT_MAX_RANK * (TT_MAX_RANK + 1);
   static constexpr int kIntBatch = 6;   // staging loads (of one double) in flight per thread
   T v[kWave], v2[kWave];
   T stage[kStage];
@@ -1257,10 +1257,11 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
   const int nacc = sm.cnt[0];
   maxr = sm.cnt[1];
   // In LDS a factor S_c (r_{c-1} x r_c, r_{m-1} = 1) is held column by column,
-  // each column padded with zeros to a whole number of chain blocks.  s_off[c] is
-  // the summed size of S_c' over 1 <= c' < c: where each factor sits once the
-  // factors are laid out back to back
-  auto pad = [](int r) { return (r + kChainBlk - 1) / kChainBlk * kChainBlk; };
+  // each column padded with zeros to a whole number of chain blocks plus one
+  // entry: the odd stride puts the columns that neighbouring lanes read in
+  // different LDS banks.  s_off[c] is the summed size of S_c' over 1 <= c' < c:
+  // where each factor sits once the factors are laid out back to back
+  auto pad = [](int r) { return (r + kChainBlk - 1) / kChainBlk * kChainBlk + 1; };
   {
     const int nf = m - 1, per = (nf + (int)blockDim.x - 1) / (int)blockDim.x, f0 = tid * per;
     const int f1 = min(f0 + per, nf), lane = tid & (kWave - 1), wid = tid / kWave;
