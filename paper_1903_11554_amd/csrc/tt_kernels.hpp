@@ -422,6 +422,63 @@ struct SearchSmem {
   T e_star, a_star;
 };
 
+// C_d's value depends on the coordinates only through B_d's prefix sum and suffix
+// recurrence, and both compose over a split of the coordinates: (P1, q1, s1) then
+// (P2, q2, g2) give (P1 P2, q1 + P1 q2, g2 + P2 s1), g2 being the recurrence over
+// the second part from zero.  row_summaries writes (P, q, s) over coordinates
+// kL0..kL1-1 of the left rows Lrows[a] (a < nL) to dL[a], dL[TT_MAX_RANK + a],
+// dL[2 TT_MAX_RANK + a], and the same from zero over kR0..kR1-1 of the right rows
+// to dR.  Each row is walked by 16 lanes, a sixteenth each, the parts joined in
+// order.  Called by the whole workgroup; a barrier must follow before dL, dR are
+// read.
+__device__ __forceinline__ void row_summaries(const double* __restrict__ Lrows, int nL, int kL0, int kL1,
+                                              double* dL, const double* __restrict__ Rrows, int nR, int kR0,
+                                              int kR1, double* dR, int m) {
+  constexpr int kLpr = 16;   // lanes per row
+  const int part = threadIdx.x % kLpr;
+  for (int row = threadIdx.x / kLpr; row < nL + nR; row += blockDim.x / kLpr) {
+    const bool left = row < nL;
+    const int idx = left ? row : row - nL;
+    const double* ptr = (left ? Lrows : Rrows) + (size_t)idx * m;
+    const int k0 = left ? kL0 : kR0, k1 = left ? kL1 : kR1;
+    const int chunk = ((k1 - k0 + kLpr - 1) / kLpr + 3) & ~3;
+    const int lo = min(k0 + part * chunk, k1), hi = min(lo + chunk, k1);
+    PrefixSuffix ps;
+    ps.span(ptr, lo, hi);
+#pragma unroll
+    for (int d = 1; d < kLpr; d <<= 1) {   // join part + d onto part, in order
+      const double P2 = __shfl_down(ps.P, d, kLpr), q2 = __shfl_down(ps.q, d, kLpr);
+      const double s2 = __shfl_down(ps.s, d, kLpr);
+      if ((part & (2 * d - 1)) == 0) {
+        ps.q = fma(ps.P, q2, ps.q);
+        ps.s = fma(P2, ps.s, s2);
+        ps.P = ps.P * P2;
+      }
+    }
+    if (part == 0) {
+      double* dst = left ? dL : dR;
+      dst[idx] = ps.P;
+      dst[TT_MAX_RANK + idx] = ps.q;
+      dst[2 * TT_MAX_RANK + idx] = ps.s;
+    }
+  }
+}
+
+// C_d at a point from its left row's summary, one or two nodes and its right
+// row's summary (from zero): the value 2 / ((1 + q)(1 + s)) of B_d's sums.
+__device__ __forceinline__ double ising_c_joined(const double* sL, int al, double t0, double t1, int nM,
+                                                 const double* sR, int be) {
+  PrefixSuffix ps;
+  ps.P = sL[al];
+  ps.q = sL[TT_MAX_RANK + al];
+  ps.s = sL[2 * TT_MAX_RANK + al];
+  ps.one(t0);
+  if (nM > 1) ps.one(t1);
+  const double q = fma(ps.P, sR[TT_MAX_RANK + be], ps.q);
+  const double sfx = fma(sR[be], ps.s, sR[2 * TT_MAX_RANK + be]);
+  return 2.0 / ((1.0 + q) * (1.0 + sfx));
+}
+
 // One step of Alg. 2 on superblock b.  The random samples, every column step and
 // every row step run through the same evaluation loop (one inlined integrand).
 // Decisions (argmax, acceptance) are taken on the leading double of |error|.
@@ -469,48 +526,15 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
     sm.Rw[a] = (b + 1 <= m - 2) ? gRw[(size_t)(b + 1) * R + a] : num<T>(1.0);
   for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = gt[i]; sm.w[i] = gw[i]; }
   if (tid == 0) { sm.e_star = num<T>(0.0); sm.a_star = num<T>(0.0); }
-  // C_d's value at (alpha, i, j, beta) depends on the coordinates only through
-  // B_d's prefix sum and suffix recurrence, and both compose over a split of the
-  // coordinates: (P1, q1, s1) then (P2, q2, g2) give (P1 P2, q1 + P1 q2, g2 + P2 s1),
-  // g2 being the recurrence over the second part from zero.  Each row of the two
-  // index sets is summarised once, by 16 lanes that each walk a sixteenth of it
-  // and join their parts in order, so a point of the search costs two node steps
-  // and a join instead of a pass over all m coordinates.
+  // C_d: every row of the two index sets is summarised once, so a point of the
+  // search costs two node steps and a join instead of a pass over m coordinates
   bool rowsum = false;
   if constexpr (kStream && (FAM == FAM_PAPER || FAM == FAM_ANY)) {
     rowsum = fa.family == TT_ISING_C;
-    if (rowsum) {
-      constexpr int kLpr = 16;   // lanes per row
-      const int part = tid % kLpr;
-      for (int row = tid / kLpr; row < rL + rR; row += blockDim.x / kLpr) {
-        const bool left = row < rL;
-        const int idx = left ? row : row - rL;
-        const bool has = left ? b > 0 : b + 1 <= m - 2;
-        const T* ptr = left ? gLx + ((size_t)(b > 0 ? b - 1 : 0) * R + idx) * m
-                            : gRx + ((size_t)(b + 1 <= m - 2 ? b + 1 : 0) * R + idx) * m;
-        const int k0 = left ? 0 : b + 2, k1 = has ? (left ? b : m) : k0;
-        const int chunk = ((k1 - k0 + kLpr - 1) / kLpr + 3) & ~3;
-        const int lo = min(k0 + part * chunk, k1), hi = min(lo + chunk, k1);
-        PrefixSuffix ps;
-        ps.span(ptr, lo, hi);
-#pragma unroll
-        for (int d = 1; d < kLpr; d <<= 1) {   // join part + d onto part, in order
-          const double P2 = __shfl_down(ps.P, d, kLpr), q2 = __shfl_down(ps.q, d, kLpr);
-          const double s2 = __shfl_down(ps.s, d, kLpr);
-          if ((part & (2 * d - 1)) == 0) {
-            ps.q = fma(ps.P, q2, ps.q);
-            ps.s = fma(P2, ps.s, s2);
-            ps.P = ps.P * P2;
-          }
-        }
-        if (part == 0) {
-          double* dst = left ? sm.sL : sm.sR;
-          dst[idx] = ps.P;
-          dst[TT_MAX_RANK + idx] = ps.q;
-          dst[2 * TT_MAX_RANK + idx] = ps.s;
-        }
-      }
-    }
+    if (rowsum)
+      row_summaries(gLx + (size_t)(b > 0 ? b - 1 : 0) * R * m, rL, 0, b > 0 ? b : 0, sm.sL,
+                    gRx + (size_t)(b + 1 <= m - 2 ? b + 1 : 0) * R * m, rR, b + 2,
+                    b + 1 <= m - 2 ? m : b + 2, sm.sR, m);
   }
   __syncthreads();
   mark(p, sweep, b, 1);
@@ -568,16 +592,8 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
                               : n_mul(n_mul(n_mul(sm.Lw[al], sm.w[i]), sm.w[j]), sm.Rw[be]);
       T a;
       if constexpr (kStream) {
-        if (rowsum) {   // left row, t_i, t_j, then the right row's summary joined on
-          PrefixSuffix ps;
-          ps.P = sm.sL[al];
-          ps.q = sm.sL[TT_MAX_RANK + al];
-          ps.s = sm.sL[2 * TT_MAX_RANK + al];
-          ps.one(sm.t[i]);
-          ps.one(sm.t[j]);
-          const double q = fma(ps.P, sm.sR[TT_MAX_RANK + be], ps.q);
-          const double sfx = fma(sm.sR[be], ps.s, sm.sR[2 * TT_MAX_RANK + be]);
-          a = n_mul(W, 2.0 / ((1.0 + q) * (1.0 + sfx)));
+        if (rowsum) {
+          a = n_mul(W, ising_c_joined(sm.sL, al, sm.t[i], sm.t[j], 2, sm.sR, be));
         } else {
           const T* Lrow = gLx + ((size_t)(b > 0 ? b - 1 : 0) * R + al) * m;
           const T* Rrow = gRx + ((size_t)(b + 1 <= m - 2 ? b + 1 : 0) * R + be) * m;
@@ -679,6 +695,8 @@ struct UpdateSmem {
       T Rx[TT_MAX_RANK * (MAXM + 1)];
       T Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
       T t[TT_MAX_NODES], w[TT_MAX_NODES];
+      // streaming C_d: row summaries of I_<=c-1 and of the new rows of I_>c
+      double sL[MAXM == 0 ? 3 * TT_MAX_RANK : 1], sR[MAXM == 0 ? 3 * TT_MAX_RANK : 1];
     };
     T A[RMAX * (RMAX + 1)];        // the stored LU of the cross, zero-padded to RMAX
   };
@@ -939,6 +957,16 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   const int nA = (rL_new - rL_old) * n * nBc;               // new rows x new columns
   const bool col_done = !init && accR && p.piv[c].col_fresh;
   const int nB = col_done ? 0 : rL_old * n * nBc;           // new column (old rows)
+  bool rowsum = false;   // streaming C_d: the points joined from row summaries
+  if constexpr (kStream && (FAM == FAM_PAPER || FAM == FAM_ANY)) {
+    rowsum = fa.family == TT_ISING_C && nA + nB > 0;
+    if (rowsum) {
+      row_summaries(gLx + (size_t)(hasL ? c - 1 : 0) * R * m, rL_new, 0, hasL ? c : 0, sm.sL,
+                    gRx + ((size_t)(hasR ? c : 0) * R + rR_old) * m, nBc, c + 1, hasR ? m : c + 1,
+                    sm.sR + rR_old, m);
+      __syncthreads();
+    }
+  }
   bool bad = false;
   for (int e = tid; e < nA + nB; e += blockDim.x) {
     int al, i, be;
@@ -957,10 +985,14 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     const T W = n_mul(n_mul(sm.Lw[al], sm.w[i]), sm.Rw[be]);
     T v;
     if constexpr (kStream) {
-      const T* Lrow = gLx + ((size_t)(c > 0 ? c - 1 : 0) * R + al) * m;
-      const T* Rrow = gRx + ((size_t)(c <= m - 2 ? c : 0) * R + be) * m;
-      const Segs sg{Lrow, c, sm.t[i], 0.0, 1, Rrow, m};
-      v = n_mul(W, integrand_seg<FAM>(fa, sg));
+      if (rowsum) {
+        v = n_mul(W, ising_c_joined(sm.sL, al, sm.t[i], 0.0, 1, sm.sR, be));
+      } else {
+        const T* Lrow = gLx + ((size_t)(c > 0 ? c - 1 : 0) * R + al) * m;
+        const T* Rrow = gRx + ((size_t)(c <= m - 2 ? c : 0) * R + be) * m;
+        const Segs sg{Lrow, c, sm.t[i], 0.0, 1, Rrow, m};
+        v = n_mul(W, integrand_seg<FAM>(fa, sg));
+      }
     } else {
       T y[MAXM];
 #pragma unroll
