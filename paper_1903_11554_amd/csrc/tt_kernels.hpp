@@ -1504,8 +1504,8 @@ union SweepSmem {
 //
 // The paper-form streaming kernels of rank 8 and 16 (the large integrals, a
 // thousand superblocks per launch) are compiled for four waves per SIMD (at most
-// 128 VGPRs).  At rank 16 that costs 32 bytes of spill, and the sweeps of C_1024
-// take 13.7 ms instead of 15.8.
+// 128 VGPRs), at a cost of 40 bytes of spill at rank 16.  Measured on C_1024
+// before the row summaries, its sweeps took 13.7 ms instead of 15.8.
 template <class T, int FAM, int MAXM, int RMAX>
 __global__ __launch_bounds__(kSweepBlock, FAM == 0 && MAXM == 0 && RMAX <= 16 ? 4 : 1) void k_sweep(ProbDesc* __restrict__ P,
                                                        const int2* __restrict__ tasks) {
