@@ -19,7 +19,8 @@
  * All compute runs in HIP kernels on the device; the host code only validates,
  * allocates and launches.  Every function returns a tt_status (or a plain value
  * where stated); no C++ exception crosses this boundary, and outputs are left
- * untouched when an error is returned.
+ * untouched when an error is returned (one exception: TT_ENUMERIC from
+ * tt_cross_sweep and tt_cross_run, which still fill the per-integral infos).
  *
  * Ownership: the library owns every device buffer it allocates (index sets,
  * cores, interpolation cores, logs); they live from tt_cross_init to
@@ -74,8 +75,11 @@ typedef enum {
  * All integrals of one job must use the same precision. */
 typedef enum { TT_FP64 = 0, TT_DD = 1 } tt_precision;
 
-/* Stop reasons reported in tt_info.reason. */
-enum { TT_RUNNING = 0, TT_STOP_CONVERGED = 1, TT_STOP_RANK_CAP = 2, TT_STOP_MAX_SWEEPS = 3 };
+/* Stop reasons reported in tt_info.reason.  TT_STOP_ERROR: the integral was
+ * stopped because a sweep raised one of the err_flags bits (its value is not a
+ * result of the stopping rule and must not be used as one). */
+enum { TT_RUNNING = 0, TT_STOP_CONVERGED = 1, TT_STOP_RANK_CAP = 2, TT_STOP_MAX_SWEEPS = 3,
+       TT_STOP_ERROR = 4 };
 
 /* Library limits (a problem beyond them is rejected with TT_EINVAL).
  * Jobs take up to TT_MAX_MODES modes.  Above TT_MAX_REG_MODES the kernels read
@@ -157,10 +161,14 @@ tt_status tt_cross_init(tt_ctx *ctx, const tt_problem *problems, int32_t count, 
 
 /* Enqueue n_sweeps sweeps of Alg. 6 for every integral not yet stopped, then
  * synchronise and fill info[count] (may be NULL).  Returns TT_CONVERGED when
- * every integral has stopped, TT_NOT_CONVERGED otherwise. */
+ * every integral has stopped, TT_NOT_CONVERGED otherwise, and TT_ENUMERIC when
+ * an integral has stopped with reason TT_STOP_ERROR (non-zero err_flags).  With
+ * TT_ENUMERIC, unlike the other errors, info is still filled, so the caller can
+ * see which integral failed and keep the others' results. */
 tt_status tt_cross_sweep(tt_job *job, int32_t n_sweeps, tt_info *info);
 
-/* Sweep until every integral stops (stopping rule or max_sweeps); fills info. */
+/* Sweep until every integral stops (stopping rule, max_sweeps or a numeric
+ * error); fills info.  Status as tt_cross_sweep. */
 tt_status tt_cross_run(tt_job *job, tt_info *info);
 
 /* Enqueue n_sweeps sweeps of Alg. 6 on the context stream and return at once:

@@ -40,7 +40,8 @@ Readings of the paper where it is silent:
     drawn from SplitMix64 keyed by (seed, sweep, bond, sample);
   * rook budget: at most 5 (column, row) pairs;
   * argmax ties go to the lowest index (rows (alpha, i) alpha-major, columns
-    (j, beta) j-major, samples in draw order); a NaN error is an error;
+    (j, beta) j-major, samples in draw order); a non-finite start sample or
+    error (B infinite or NaN) is a numeric error;
   * acceptance: |err*| > tol * scale_b, where scale_b is the largest |B| the
     bond has evaluated so far, r_b < rank_cap, and neither half of the pivot is
     already in its set;
@@ -187,8 +188,8 @@ class TTCross:
                 idx[q, k] = rng.uniform_index(rng.value(self.seed, rng.start_counter(q, k)), n)
         vals = self.B(idx)
         self.evals += self.n_start
-        if np.isnan(vals).any():
-            raise FloatingPointError("NaN in the start samples")
+        if not np.isfinite(vals).all():
+            raise FloatingPointError("non-finite start sample")
         q = int(np.argmax(np.abs(vals)))
         if vals[q] == 0.0:
             raise FloatingPointError("all start samples are zero")
@@ -277,8 +278,8 @@ class TTCross:
             return np.einsum("kr,rk->k", Fb[rows, :], X)
 
         def argmax_abs(e):
-            if np.isnan(e).any():
-                raise FloatingPointError(f"NaN error in superblock {b}")
+            if not np.isfinite(e).all():
+                raise FloatingPointError(f"non-finite error in superblock {b}")
             return int(np.argmax(np.abs(e)))
 
         seen = 0.0

@@ -92,8 +92,8 @@ class TTCrossDD(TTCross):
                 idx[q, k] = rng.uniform_index(rng.value(self.seed, rng.start_counter(q, k)), n)
         vals = self.B(idx)
         self.evals += self.n_start
-        if np.isnan(vals.hi).any():
-            raise FloatingPointError("NaN in the start samples")
+        if not np.isfinite(vals.hi).all():
+            raise FloatingPointError("non-finite start sample")
         q = int(np.argmax(np.abs(vals.hi)))
         if vals.hi[q] == 0.0:
             raise FloatingPointError("all start samples are zero")
@@ -156,8 +156,8 @@ class TTCrossDD(TTCross):
             return dd_sum(Fb[np.asarray(rows), :] * X.T, axis=1)
 
         def argmax_abs(e):
-            if np.isnan(e.hi).any():
-                raise FloatingPointError(f"NaN error in superblock {b}")
+            if not np.isfinite(e.hi).all():
+                raise FloatingPointError(f"non-finite error in superblock {b}")
             return int(np.argmax(np.abs(e.hi)))
 
         seen = 0.0

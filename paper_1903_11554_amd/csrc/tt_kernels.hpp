@@ -302,9 +302,9 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       st->rel = 0.0;
       st->sweeps = 0;
       st->done = 1;
-      st->reason = TT_STOP_CONVERGED;
-      st->evals = (m == 1) ? (unsigned long long)n : 0ull;
       st->err_flags = isfinite(n_hi(val)) ? 0 : 1;
+      st->reason = st->err_flags ? TT_STOP_ERROR : TT_STOP_CONVERGED;
+      st->evals = (m == 1) ? (unsigned long long)n : 0ull;
       st->max_rank = 1;
       signal_done(p);
     }
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
     if (tid == 0) {
       st->err_flags = any_bad ? 1 : 4;
       st->done = 1;
-      st->reason = TT_STOP_CONVERGED;
+      st->reason = TT_STOP_ERROR;
       st->evals = kStart;
       st->sweeps = 0;
       st->max_rank = 0;
@@ -1459,9 +1459,9 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
     done = 1;
     reason = TT_STOP_MAX_SWEEPS;
   }
-  if (st->err_flags) {
+  if (st->err_flags) {   // a numeric failure ends the integral whatever the rule said
     done = 1;
-    if (reason == TT_RUNNING) reason = TT_STOP_CONVERGED;
+    reason = TT_STOP_ERROR;
   }
   if (done) {
     st->reason = reason;

@@ -135,6 +135,18 @@ tt_status enqueue_sweeps(tt_job* j, int n_sweeps) {
   return TT_OK;
 }
 
+// Fill the infos; TT_ENUMERIC if an integral stopped on a numeric error, else
+// TT_CONVERGED once every integral has stopped.
+tt_status sweep_status(const std::vector<ProbState>& st, int nprob, tt_info* info) {
+  bool all = true, failed = false;
+  for (int k = 0; k < nprob; ++k) {
+    if (info) fill_info(st[k], &info[k]);
+    all = all && st[k].done;
+    failed = failed || (st[k].done && st[k].reason == TT_STOP_ERROR);
+  }
+  return failed ? TT_ENUMERIC : all ? TT_CONVERGED : TT_NOT_CONVERGED;
+}
+
 tt_status read_states(tt_job* j, std::vector<ProbState>& st) {
   st.resize(j->nprob);
   TT_HIP(hipMemcpyAsync(st.data(), j->dstate, sizeof(ProbState) * j->nprob, hipMemcpyDeviceToHost,
@@ -428,12 +440,7 @@ tt_status tt_cross_sweep(tt_job* j, int32_t n_sweeps, tt_info* info) {
   std::vector<ProbState> st;
   s = read_states(j, st);
   if (s != TT_OK) return s;
-  bool all = true;
-  for (int k = 0; k < j->nprob; ++k) {
-    if (info) fill_info(st[k], &info[k]);
-    all = all && st[k].done;
-  }
-  return all ? TT_CONVERGED : TT_NOT_CONVERGED;
+  return sweep_status(st, j->nprob, info);
 }
 
 tt_status tt_cross_enqueue(tt_job* j, int32_t n_sweeps) {
@@ -493,12 +500,7 @@ tt_status tt_cross_run(tt_job* j, tt_info* info) {
     tt_status s = read_states(j, st);
     if (s != TT_OK) return s;
   }
-  bool all = true;
-  for (int k = 0; k < j->nprob; ++k) {
-    if (info) fill_info(st[k], &info[k]);
-    all = all && st[k].done;
-  }
-  return all ? TT_CONVERGED : TT_NOT_CONVERGED;
+  return sweep_status(st, j->nprob, info);
 }
 
 tt_status tt_cross_integrate(tt_job* j, double* values, tt_info* info) {

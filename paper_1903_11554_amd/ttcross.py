@@ -19,7 +19,7 @@ FAMILY_IDS = {
     "ising_c_u": 11, "ising_d_u": 12,
     "prod_exp": 21, "sum2_exp_cos": 22,
 }
-STOP_REASONS = {0: "running", 1: "converged", 2: "rank_cap", 3: "max_sweeps"}
+STOP_REASONS = {0: "running", 1: "converged", 2: "rank_cap", 3: "max_sweeps", 4: "error"}
 PRECISION_IDS = {"fp64": 0, "dd": 1}
 
 TT_OK, TT_CONVERGED, TT_NOT_CONVERGED, TT_PENDING = 0, 1, 2, 3
@@ -27,8 +27,12 @@ TT_EINVAL, TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC = -1, -2, -3, -4
 
 
 class TTError(RuntimeError):
-    def __init__(self, status, what):
+    """A negative tt_status.  `infos` holds the per-integral infos when the call filled them
+    (TT_ENUMERIC from tt_cross_sweep / tt_cross_run: an integral stopped on a numeric error)."""
+
+    def __init__(self, status, what, infos=None):
         self.status = status
+        self.infos = infos
         super().__init__(f"{what}: {_status_name(status)} ({status})")
 
 
@@ -270,9 +274,14 @@ class Job:
                      value_lo=i.value_lo, value_mant=i.value_mant, value_exp2=i.value_exp2)
                 for i in infos]
 
+    def _checked_infos(self, status, infos, what):
+        if status == TT_ENUMERIC:
+            raise TTError(status, what, self._info_dicts(infos))
+        return _check(status, what)
+
     def sweep(self, n=1):
         infos = self._infos()
-        st = _check(self._lib.tt_cross_sweep(self.handle, n, infos), "tt_cross_sweep")
+        st = self._checked_infos(self._lib.tt_cross_sweep(self.handle, n, infos), infos, "tt_cross_sweep")
         return st == TT_CONVERGED, self._info_dicts(infos)
 
     def enqueue(self, n=1):
@@ -280,8 +289,9 @@ class Job:
         _check(self._lib.tt_cross_enqueue(self.handle, n), "tt_cross_enqueue")
 
     def run(self):
+        """Sweep to the stopping rule; raises TTError (with .infos) if an integral stopped on an error."""
         infos = self._infos()
-        _check(self._lib.tt_cross_run(self.handle, infos), "tt_cross_run")
+        self._checked_infos(self._lib.tt_cross_run(self.handle, infos), infos, "tt_cross_run")
         return self._info_dicts(infos)
 
     def values(self):

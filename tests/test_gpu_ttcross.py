@@ -388,3 +388,34 @@ def test_zero_start_is_reported_as_a_numeric_error():
     info = job.run()[0]
     assert info["err_flags"] == 0 and info["reason"] in ("converged", "rank_cap")
     job.free()
+
+
+def test_numeric_error_in_a_sweep_stops_the_integral_with_reason_error():
+    """A sweep that meets a non-finite B stops that integral with reason "error" and TT_ENUMERIC.
+
+    The integrand exp(355.1 (x_2 + x_3)) overflows only at the corner where both
+    coordinates take the largest node: the start and the first cores are finite,
+    the first sweep's search meets the overflow (the oracle raises there, see
+    tests/test_oracle_ttcross.py).  tt_cross_run must return TT_ENUMERIC with the
+    infos filled; an integral solved in the same job is unaffected.
+    """
+    from test_oracle_ttcross import OVERFLOW_CASE as c
+
+    from paper_1903_11554_amd.ttcross import TT_ENUMERIC, TTError
+    bad = Problem(c["family"], c["d"], c["n"], c["rank_cap"], c["tol"], seed=c["seed"], params=c["params"])
+    with pytest.raises(FloatingPointError):
+        run_oracle(bad)
+    ctx = gpu_context()
+    good = SMALL[3]
+    alone = ctx.job([good])
+    ainfo = alone.run()[0]
+    alone.free()
+    job = ctx.job([bad, good])
+    with pytest.raises(TTError) as exc:
+        job.run()
+    assert exc.value.status == TT_ENUMERIC
+    ib, ig = exc.value.infos
+    print(f"error stop: {ib}", flush=True)
+    assert ib["reason"] == "error" and ib["err_flags"] & 1 and ib["sweeps"] == 1, ib
+    assert ig["reason"] == ainfo["reason"] and ig["value"] == ainfo["value"] and ig["err_flags"] == 0
+    job.free()

@@ -255,3 +255,25 @@ def test_rank1_product_of_300_modes_through_the_scaled_chain():
     assert 0.5 <= abs(mant) < 1.0 and max(tt.ranks()) == 1
     assert abs(math.log(mant) + e * math.log(2.0) - log_q) < 1e-12 * abs(log_q)
     assert tt.history[-1] == math.ldexp(mant, e)
+
+
+# exp(alpha (x_2 + x_3)) with alpha = 355.1 on 64 Gauss-Legendre nodes overflows
+# exactly when both coordinates sit at the largest node (2 t_63 alpha > log of
+# the largest double); every point with at most one of them there is finite.
+OVERFLOW_CASE = dict(family="prod_exp", d=4, n=64, rank_cap=4, tol=1e-10, seed=9,
+                     params={"a": [0.0, -355.1, -355.1, 0.0], "b": [1.0] * 4})
+
+
+def test_overflow_in_a_sweep_is_a_numeric_error():
+    """A non-finite B met by the search is an error, not a pivot (the start and cores are finite)."""
+    from oracle.gauss import gauss_legendre_01
+    c = OVERFLOW_CASE
+    t, _ = gauss_legendre_01(c["n"])
+    alpha = -c["params"]["a"][1]
+    log_max = math.log(np.finfo(np.float64).max)
+    assert 2 * alpha * t[-1] > log_max + 0.1 and alpha * (t[-1] + t[-2]) < log_max - 0.1
+    tt = ttcross.TTCross(c["family"], c["d"], c["n"], c["rank_cap"], c["tol"], c["seed"],
+                         params=c["params"])
+    assert all(np.isfinite(tt.core(k)).all() for k in range(tt.m)) and math.isfinite(tt.history[0])
+    with pytest.raises(FloatingPointError, match="non-finite"):
+        tt.sweep()
