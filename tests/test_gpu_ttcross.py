@@ -393,7 +393,7 @@ def test_zero_start_is_reported_as_a_numeric_error():
 def test_numeric_error_in_a_sweep_stops_the_integral_with_reason_error():
     """A sweep that meets a non-finite B stops that integral with reason "error" and TT_ENUMERIC.
 
-    The integrand exp(355.1 (x_2 + x_3)) overflows only at the corner where both
+    The integrand exp(355.1 (x_1 + x_2)) overflows only at the corner where both
     coordinates take the largest node: the start and the first cores are finite,
     the first sweep's search meets the overflow (the oracle raises there, see
     tests/test_oracle_ttcross.py).  tt_cross_run must return TT_ENUMERIC with the

@@ -257,11 +257,11 @@ def test_rank1_product_of_300_modes_through_the_scaled_chain():
     assert tt.history[-1] == math.ldexp(mant, e)
 
 
-# exp(alpha (x_2 + x_3)) with alpha = 355.1 on 64 Gauss-Legendre nodes overflows
+# exp(alpha (x_1 + x_2)) with alpha = 355.1 on 64 Gauss-Legendre nodes overflows
 # exactly when both coordinates sit at the largest node (2 t_63 alpha > log of
 # the largest double); every point with at most one of them there is finite.
-OVERFLOW_CASE = dict(family="prod_exp", d=4, n=64, rank_cap=4, tol=1e-10, seed=9,
-                     params={"a": [0.0, -355.1, -355.1, 0.0], "b": [1.0] * 4})
+OVERFLOW_CASE = dict(family="prod_exp", d=2, n=64, rank_cap=4, tol=1e-10, seed=4,
+                     params={"a": [-355.1, -355.1], "b": [1.0] * 2})
 
 
 def test_overflow_in_a_sweep_is_a_numeric_error():
@@ -269,7 +269,7 @@ def test_overflow_in_a_sweep_is_a_numeric_error():
     from oracle.gauss import gauss_legendre_01
     c = OVERFLOW_CASE
     t, _ = gauss_legendre_01(c["n"])
-    alpha = -c["params"]["a"][1]
+    alpha = -c["params"]["a"][0]
     log_max = math.log(np.finfo(np.float64).max)
     assert 2 * alpha * t[-1] > log_max + 0.1 and alpha * (t[-1] + t[-2]) < log_max - 0.1
     tt = ttcross.TTCross(c["family"], c["d"], c["n"], c["rank_cap"], c["tol"], c["seed"],
