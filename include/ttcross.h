@@ -240,6 +240,28 @@ tt_status tt_mc_integrate(tt_ctx *ctx, const tt_problem *problem, int32_t kind, 
                           int32_t n_sets, const int64_t *gen, double *estimates, double *mean,
                           double *rel_err);
 
+/* For callers that cannot allocate device memory: code that runs under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same estimators as tt_mc_integrate (the same kernels, so the same bits for
+ * the same arguments), with no allocation of any kind: the partial sums live
+ * in a static device array of TT_MC_NOALLOC_MAX_PARTIALS doubles (1 MiB) that
+ * the library holds on every GPU it runs on until the process ends, and gen
+ * (host, m values, reduced mod N) and the synthetic parameters are passed by
+ * value in the kernel arguments.  d_out is a device array of n_sets + 2
+ * doubles that receives the estimates, then their mean, then the relative
+ * empirical standard deviation (eq. std).  Asynchronous on the context stream:
+ * no host synchronisation, no event, no memset.  All calls on one GPU share
+ * its static array, so calls that overlap on one GPU (several streams or
+ * contexts) race and must be serialised by the caller; the array holds the
+ * last call's partial sums, and nothing in it needs clearing.
+ * Errors: as tt_mc_integrate, plus TT_EINVAL when d_out is NULL or
+ * n_sets * min(ceil(n_points / 256), 256) > TT_MC_NOALLOC_MAX_PARTIALS
+ * (the partial sums would not fit), and TT_EDEVICE if the static array's
+ * address could not be looked up when the context was created. */
+#define TT_MC_NOALLOC_MAX_PARTIALS 131072
+tt_status tt_mc_integrate_noalloc(tt_ctx *ctx, const tt_problem *problem, int32_t kind, int64_t n_points,
+                                  int32_t n_sets, const int64_t *gen, double *d_out);
+
 /* Optional per-kernel timing with HIP events recorded on the context stream
  * around every launch (adds two event records per launch).  tt_ctx_profile
  * switches it on or off and clears the totals; tt_ctx_kernel_time returns the

@@ -61,6 +61,7 @@ struct tt_ctx {
   std::vector<hipEvent_t> ring_pool;               // timing-less events kept for reuse
   double* mc_buf = nullptr;                        // device scratch of tt_mc_integrate
   size_t mc_cap = 0;
+  double* scratch = nullptr;                       // this device's static scratch (tt_mc_integrate_noalloc)
   size_t arena_bytes_cached = 0;
 };
 

@@ -1658,13 +1658,28 @@ __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa_in, int n,
 // (kind 0) drawn from the counter-based generator, or x_i = frac(i q / N + s_j)
 // for i = 1..N (kind 1), with (i q_k) mod N in exact integer arithmetic.  Each
 // workgroup writes one partial sum; k_mc_finish adds them in a fixed order.
+// The generating vector (reduced mod N) and the synthetic parameters travel by
+// value in the kernel arguments, so the only device buffer besides the output
+// is the partial sums.
+struct McParams {
+  int64_t gen[TT_MAX_REG_MODES];                   // q_k mod N (lattice rules)
+  double a[TT_MAX_REG_MODES], b[TT_MAX_REG_MODES];   // synthetic parameters
+};
+
 template <int FAM, int MAXM>
-__global__ __launch_bounds__(kBlock) void k_mc(FamilyArgs fa, int kind, int64_t N, const int64_t* __restrict__ gen,
-                                               uint64_t seed, double* __restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_mc(FamilyArgs fa, int kind, int64_t N, McParams mp, uint64_t seed,
+                                               double* __restrict__ partial) {
   __shared__ double sshift[TT_MAX_REG_MODES];
+  __shared__ double sa[TT_MAX_REG_MODES], sb[TT_MAX_REG_MODES];
   __shared__ double red[kBlock / kWave];
   const int j = blockIdx.y, m = fa.m, tid = threadIdx.x;
-  if (tid < m) sshift[tid] = uniform_open01(splitmix_at(seed, shift_counter(j, tid)));
+  if (tid < m) {
+    sshift[tid] = uniform_open01(splitmix_at(seed, shift_counter(j, tid)));
+    sa[tid] = mp.a[tid];
+    sb[tid] = mp.b[tid];
+  }
+  fa.a = sa;
+  fa.b = sb;
   __syncthreads();
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + tid; i < N; i += (int64_t)gridDim.x * blockDim.x) {
@@ -1676,7 +1691,7 @@ __global__ __launch_bounds__(kBlock) void k_mc(FamilyArgs fa, int kind, int64_t 
         if (kind == 0) {
           v = uniform_open01(splitmix_at(seed, mc_counter(j, i, m, k)));
         } else {
-          const uint64_t r = ((uint64_t)(i + 1) * (uint64_t)gen[k]) % (uint64_t)N;
+          const uint64_t r = ((uint64_t)(i + 1) * (uint64_t)mp.gen[k]) % (uint64_t)N;
           v = (double)r / (double)N + sshift[k];
           v = (v >= 1.0) ? v - 1.0 : v;
         }

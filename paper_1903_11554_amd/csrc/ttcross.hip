@@ -204,6 +204,85 @@ void eval_fibers_f(tt_ctx* ctx, int mb, dim3 grid, dim3 block, const FamilyArgs&
     default: eval_fibers_k<T, FAM, 32>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out); break;
   }
 }
+
+// Validation and kernel arguments shared by the two Monte Carlo entry points:
+// the integrand class's FamilyArgs (synthetic parameters are set in-kernel from
+// the by-value McParams), the generating vector reduced mod N, and the number of
+// workgroups per estimator.
+tt_status mc_setup(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_t n_points, int32_t n_sets,
+                   const int64_t* gen, FamilyArgs* fa, McParams* mp, int* blocks) {
+  if (!ctx || validate(p) != TT_OK || p->precision != TT_FP64 || modes_of(*p) > TT_MAX_REG_MODES)
+    return TT_EINVAL;
+  if (kind != TT_MC_RANDOM && kind != TT_MC_LATTICE) return TT_EINVAL;
+  if (n_points < 1 || n_points >= (int64_t(1) << 31) || n_sets < 2 || n_sets > 4096) return TT_EINVAL;
+  if (kind == TT_MC_LATTICE && !gen) return TT_EINVAL;
+  const int m = modes_of(*p);
+  if (m < 1) return TT_EINVAL;
+  fa->family = p->integrand;
+  fa->m = m;
+  fa->four_over_mfact = four_over_fact(m);
+  fa->a = fa->b = nullptr;
+  std::memset(mp, 0, sizeof(*mp));
+  for (int k = 0; k < m; ++k) {
+    if (kind == TT_MC_LATTICE) mp->gen[k] = ((gen[k] % n_points) + n_points) % n_points;
+    if (is_synthetic(p->integrand)) {
+      mp->a[k] = p->params[k];
+      mp->b[k] = p->params[m + k];
+    }
+  }
+  *blocks = (int)std::min<int64_t>((n_points + kBlock - 1) / kBlock, 256);
+  return TT_OK;
+}
+
+// Enqueue the estimators (partial sums into `partial`, S x blocks) and the
+// finish (estimates, mean and relative error into `out`, S + 2) on the stream.
+void mc_launch(tt_ctx* ctx, const tt_problem* p, int kind, int64_t n_points, int n_sets, const FamilyArgs& fa,
+               const McParams& mp, int blocks, double* partial, double* out) {
+  const dim3 grid((unsigned)blocks, (unsigned)n_sets), block(kBlock);
+  const int fam = fam_of(p->integrand), mb = bucket_m(fa.m);
+#define TT_MC(F, M) \
+  hipLaunchKernelGGL((k_mc<F, M>), grid, block, 0, ctx->stream, fa, kind, n_points, mp, p->seed, partial)
+#define TT_MC_M(F)               \
+  switch (mb) {                  \
+    case 8: TT_MC(F, 8); break;   \
+    case 16: TT_MC(F, 16); break; \
+    default: TT_MC(F, 32); break; \
+  }
+  if (fam == FAM_PAPER) { TT_MC_M(FAM_PAPER) }
+  else if (fam == FAM_UFORM) { TT_MC_M(FAM_UFORM) }
+  else { TT_MC_M(FAM_SYNTH) }
+#undef TT_MC_M
+#undef TT_MC
+  hipLaunchKernelGGL(k_mc_finish, dim3(1), block, 0, ctx->stream, partial, blocks, n_sets, n_points, out);
+}
+
+// Scratch of tt_mc_integrate_noalloc: the partial sums of one call in a static
+// device array, so that the entry point allocates nothing.  Every GPU the
+// library runs on holds its own copy until the process ends; host code must use
+// the address hipGetSymbolAddress returns for the device (kept per device
+// below, looked up by tt_ctx_create), never this name.
+static __device__ __align__(256) double scratch[TT_MC_NOALLOC_MAX_PARTIALS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (which must be `device`).
+tt_status scratch_address(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return TT_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      last_hip_error() = e;
+      return TT_EDEVICE;
+    }
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return TT_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -231,6 +310,10 @@ tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
   tt_ctx* c = new (std::nothrow) tt_ctx;
   if (!c) return TT_ENOMEM;
   c->device = device;
+  if (scratch_address(device, &c->scratch) != TT_OK) {
+    delete c;
+    return TT_EDEVICE;
+  }
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -738,22 +821,16 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
 
 tt_status tt_mc_integrate(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_t n_points, int32_t n_sets,
                           const int64_t* gen, double* estimates, double* mean, double* rel_err) {
-  if (!ctx || validate(p) != TT_OK || p->precision != TT_FP64 || modes_of(*p) > TT_MAX_REG_MODES)
-    return TT_EINVAL;
-  if (kind != TT_MC_RANDOM && kind != TT_MC_LATTICE) return TT_EINVAL;
-  if (n_points < 1 || n_points >= (int64_t(1) << 31) || n_sets < 2 || n_sets > 4096) return TT_EINVAL;
-  if (kind == TT_MC_LATTICE && !gen) return TT_EINVAL;
+  FamilyArgs fa;
+  McParams mp;
+  int blocks = 0;
+  tt_status s = mc_setup(ctx, p, kind, n_points, n_sets, gen, &fa, &mp, &blocks);
+  if (s != TT_OK) return s;
   if (!estimates || !mean || !rel_err) return TT_EINVAL;
-  const int m = modes_of(*p);
-  if (m < 1) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   TT_HIP(hipSetDevice(ctx->device));
-  FamilyArgs fa;
-  tt_status s = family_for(ctx, p, &fa);
-  if (s != TT_OK) return s;
-  const int blocks = (int)std::min<int64_t>((n_points + kBlock - 1) / kBlock, 256);
-  // scratch: partial sums [S x blocks], results [S + 2], generating vector [m]
-  const size_t need = sizeof(double) * ((size_t)n_sets * blocks + n_sets + 2) + sizeof(int64_t) * TT_MAX_REG_MODES;
+  // partial sums [S x blocks], then the results [S + 2]
+  const size_t need = sizeof(double) * ((size_t)n_sets * blocks + n_sets + 2);
   if (need > ctx->mc_cap) {
     TT_HIP(hipStreamSynchronize(ctx->stream));
     if (ctx->mc_buf) TT_HIP(hipFree(ctx->mc_buf));
@@ -764,31 +841,9 @@ tt_status tt_mc_integrate(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_
   }
   double* partial = ctx->mc_buf;
   double* out = partial + (size_t)n_sets * blocks;
-  int64_t* dgen = (int64_t*)(out + n_sets + 2);
-  if (kind == TT_MC_LATTICE) {
-    int64_t g[TT_MAX_REG_MODES];
-    for (int k = 0; k < m; ++k) g[k] = ((gen[k] % n_points) + n_points) % n_points;
-    TT_HIP(hipStreamSynchronize(ctx->stream));   // the earlier upload source is a stack array
-    TT_HIP(hipMemcpy(dgen, g, sizeof(int64_t) * m, hipMemcpyHostToDevice));
-  }
-  const dim3 grid((unsigned)blocks, (unsigned)n_sets), block(kBlock);
-  const int fam = fam_of(p->integrand), mb = bucket_m(m);
   {
     Timed tm(ctx, KK_MC);
-#define TT_MC(F, M) \
-  hipLaunchKernelGGL((k_mc<F, M>), grid, block, 0, ctx->stream, fa, kind, n_points, dgen, p->seed, partial)
-#define TT_MC_M(F)               \
-  switch (mb) {                  \
-    case 8: TT_MC(F, 8); break;   \
-    case 16: TT_MC(F, 16); break; \
-    default: TT_MC(F, 32); break; \
-  }
-    if (fam == FAM_PAPER) { TT_MC_M(FAM_PAPER) }
-    else if (fam == FAM_UFORM) { TT_MC_M(FAM_UFORM) }
-    else { TT_MC_M(FAM_SYNTH) }
-#undef TT_MC_M
-#undef TT_MC
-    hipLaunchKernelGGL(k_mc_finish, dim3(1), block, 0, ctx->stream, partial, blocks, n_sets, n_points, out);
+    mc_launch(ctx, p, kind, n_points, n_sets, fa, mp, blocks, partial, out);
   }
   TT_HIP(hipGetLastError());
   std::vector<double> h(n_sets + 2);
@@ -797,6 +852,22 @@ tt_status tt_mc_integrate(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_
   for (int j = 0; j < n_sets; ++j) estimates[j] = h[j];
   *mean = h[n_sets];
   *rel_err = h[n_sets + 1];
+  return TT_OK;
+}
+
+tt_status tt_mc_integrate_noalloc(tt_ctx* ctx, const tt_problem* p, int32_t kind, int64_t n_points,
+                                  int32_t n_sets, const int64_t* gen, double* d_out) {
+  FamilyArgs fa;
+  McParams mp;
+  int blocks = 0;
+  tt_status s = mc_setup(ctx, p, kind, n_points, n_sets, gen, &fa, &mp, &blocks);
+  if (s != TT_OK) return s;
+  if (!d_out || (int64_t)n_sets * blocks > TT_MC_NOALLOC_MAX_PARTIALS) return TT_EINVAL;
+  if (!ctx->scratch) return TT_EDEVICE;   // the symbol lookup at tt_ctx_create failed
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  TT_HIP(hipSetDevice(ctx->device));
+  mc_launch(ctx, p, kind, n_points, n_sets, fa, mp, blocks, ctx->scratch, d_out);
+  TT_HIP(hipGetLastError());
   return TT_OK;
 }
 

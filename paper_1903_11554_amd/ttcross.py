@@ -75,6 +75,7 @@ EXPORTS = [
     "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
     "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
     "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue", "tt_mc_integrate",
+    "tt_mc_integrate_noalloc",
 ]
 
 KERNEL_KINDS = {"sweep": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
@@ -127,6 +128,7 @@ def load_library():
         "tt_server_destroy": (None, [vp]),
         "tt_cross_enqueue": (i32, [vp, i32]),
         "tt_mc_integrate": (i32, [vp, P(_Problem), i32, i64, i32, P(i64), P(dbl), P(dbl), P(dbl)]),
+        "tt_mc_integrate_noalloc": (i32, [vp, P(_Problem), i32, i64, i32, P(i64), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -217,6 +219,17 @@ class Context:
                                          n_sets, g, est, ctypes.byref(mean), ctypes.byref(err)),
                "tt_mc_integrate")
         return list(est), mean.value, err.value
+
+    def mc_integrate_noalloc(self, p: Problem, n_points, n_sets, out_dev, kind=MC_RANDOM, gen=None):
+        """The estimators of mc_integrate with no allocation: estimates, mean and relative error
+        are written to the device array out_dev (n_sets + 2 doubles) on the context stream."""
+        keep = []
+        g = None
+        if gen is not None:
+            g = (ctypes.c_int64 * len(gen))(*[int(v) for v in gen])
+        _check(self._lib.tt_mc_integrate_noalloc(self.handle, ctypes.byref(_c_problem(p, keep)), kind,
+                                                 n_points, n_sets, g, ctypes.c_void_p(out_dev)),
+               "tt_mc_integrate_noalloc")
 
     def server(self, max_bytes=1 << 30, max_active=256):
         return Server(self, max_bytes, max_active)
