@@ -234,3 +234,123 @@ def test_dd_d32_against_printed_value():
     print(f"D_32 double-double: {info} rel err {rel:.3e}", flush=True)
     assert info["err_flags"] == 0
     assert rel < 1e-15    # double rounding alone leaves about 1e-16 per operation, 1e-13 at this size
+
+
+def mp256_cases():
+    """The 256-bit oracle's D_d runs stored by tests/golden/make_mp_reference.py."""
+    import os
+    out = []
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mp256_ising_small.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            d, n, v, sweeps, reason, ranks, t2 = line.split()
+            out.append((int(d), int(n), v, int(sweeps), reason, [int(r) for r in ranks.split(",")], t2))
+    return out
+
+
+@pytest.mark.parametrize("case", mp256_cases(), ids=lambda c: f"D{c[0]}_n{c[1]}")
+def test_dd_matches_the_256_bit_oracle(case):
+    """The double-double GPU cross against the 256-bit oracle (oracle/ttcross_mp.py) at 1e-20.
+
+    D_d at n = 3..6 nodes, rank cap 64, tol 1e-21, against a reference whose
+    own rounding is near 1e-75.  Where both runs end on the same ranks the
+    value must agree to 1e-20 relative.  The decisions may differ where
+    rounding decides them: with so few nodes a search can see only entries of
+    the cross itself, whose error is exactly 0 at 256 bits (the argmax then
+    takes the lowest index and the search stops) and rounding noise in
+    double-double (the argmax follows the noise and may leave the cross).
+    Then the GPU run must have gone at least as far (ranks no lower) and be no
+    further from the brute-force sum over the same nodes (T2, 256 bits) than
+    the 256-bit cross is, within 1e-20.  Runs of more than 30 sweeps reach the
+    rank-64 double-double sweep kernel (rows of the interpolation core worked
+    on in memory).
+    """
+    d, n, v, sweeps, reason, ranks, t2 = case
+    ctx = gpu_context()
+    p = Problem("ising_d", d, n, 64, 1e-21, seed=d, precision="dd")
+    job = ctx.job([p])
+    info = job.run()[0]
+    granks = [len(s[0]) for s in job.index_sets(0)]
+    job.free()
+    with mp.workdps(80):
+        rel = dd_rel(info["value"], info["value_lo"], mp.mpf(v), 0)
+        rel_t2 = dd_rel(info["value"], info["value_lo"], mp.mpf(t2), 0)
+        ref_t2 = float(abs(mp.mpf(v) / mp.mpf(t2) - 1))
+    print(f"D_{d} n={n}: gpu ranks {granks} sweeps {info['sweeps']} {info['reason']} | 256-bit ranks "
+          f"{ranks} sweeps {sweeps} {reason} | rel to 256-bit cross {rel:.3e}, to T2 {rel_t2:.3e} "
+          f"(256-bit cross to T2 {ref_t2:.3e})", flush=True)
+    assert info["err_flags"] == 0 and info["reason"] in ("converged", "rank_cap")
+    if granks == ranks:
+        assert rel <= 1e-20
+    else:
+        assert all(g >= r for g, r in zip(granks, ranks)), (granks, ranks)
+        assert rel_t2 <= ref_t2 + 1e-20
+
+
+def dd_config3_reference():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dd_d8_n128_r64.txt")
+    ref = {"hist": [], "piv": {}}
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "stop":
+            ref["stop"], ref["sweeps"] = f[1], int(f[3])
+            ref["ranks"] = [int(r) for r in f[7].split(",")]
+        elif f[0] == "hist":
+            ref["hist"].append((float(f[2]), float(f[3])))
+        elif f[0] == "piv":
+            s, b = int(f[1]), int(f[2])
+            ref["piv"][(s, b)] = dict(row=int(f[3]), col=int(f[4]), accepted=bool(int(f[5])), iters=int(f[6]),
+                                      err=float(f[7]), err_lo=float(f[8]), value=float(f[9]),
+                                      col_fresh=bool(int(f[10])))
+    return ref
+
+
+def test_dd_config3_full_size_against_the_stored_oracle_run():
+    """D_8 in double-double at the precision workload's full size against the double-double oracle.
+
+    128 nodes, rank cap 64, tol 1e-21, seed 8: the oracle's run (pivot log and
+    history) is stored by tests/golden/make_dd_config3.py.  The GPU runs the
+    same job through its double-double sweep kernels up to the rank-64 bucket
+    (rows of the interpolation core in memory).  Accepted pivots must agree in
+    position and in error to 1e-24 of the bond's scale; rejections need only be
+    rejections (their position is an argmax over rounding noise); the history
+    must agree to 1e-20 relative while the logs agree, and the final value
+    within 10 tol if a near-tie decision diverges.
+    """
+    ref = dd_config3_reference()
+    ctx = gpu_context()
+    p = Problem("ising_d", 8, 128, 64, 1e-21, seed=8, precision="dd")
+    job = ctx.job([p])
+    info = job.run()[0]
+    glog = job.pivot_log(0)
+    ghi, glo = job.history_dd(0)
+    granks = [len(s[0]) for s in job.index_sets(0)]
+    job.free()
+    print(f"D_8 dd full size: gpu {info} ranks {granks}; oracle {ref['stop']} {ref['sweeps']} sweeps "
+          f"ranks {ref['ranks']}", flush=True)
+    assert info["err_flags"] == 0 and max(granks) == 64
+    divergence = None
+    nb = p.modes() - 1
+    for s in range(min(len(glog), ref["sweeps"])):
+        scale = max(abs(ref["piv"][(t, b)]["value"]) for t in range(s + 1) for b in range(nb))
+        for b in range(nb):
+            g, o = glog[s][b], ref["piv"][(s, b)]
+            if g["accepted"] and o["accepted"]:
+                if (g["row"], g["col"]) != (o["row"], o["col"]):
+                    divergence = ("tie", s, b, g, o)
+                    break
+                assert abs(g["err"] - o["err"]) <= 1e-24 * scale + 4e-16 * abs(o["err"]), (s, b, g, o)
+            elif g["accepted"] != o["accepted"]:
+                divergence = ("threshold", s, b, g, o)
+                break
+        if divergence:
+            break
+        assert dd_rel(ghi[s + 1], glo[s + 1], *ref["hist"][s + 1]) <= 1e-20, s
+    if divergence is None:
+        assert (info["sweeps"], info["reason"], granks) == (ref["sweeps"], ref["stop"], ref["ranks"])
+    else:
+        print(f"first divergence {divergence}", flush=True)
+        assert dd_rel(ghi[-1], glo[-1], *ref["hist"][-1]) <= 10 * p.tol
