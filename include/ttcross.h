@@ -118,7 +118,9 @@ typedef struct {
   double  value_lo;    /* TT_DD: the low double of the estimate (value + value_lo); else 0 */
   double  value_mant;  /* the estimate is value_mant * 2^value_exp2 exactly (TT_DD: its    */
   int32_t value_exp2;  /*   leading double), 1/2 <= |value_mant| < 1 or 0; value and       */
-  int32_t reserved;    /*   value_lo are 0 or +-inf when the estimate leaves the double range */
+  int32_t recomputes;  /*   value_lo are 0 or +-inf when the estimate leaves the double range;
+                          recomputes: interpolation cores rebuilt from F_c with a pivoted
+                          solve so far (double jobs whose crosses lost dominance)        */
 } tt_info;
 
 /* One accepted-or-rejected pivot search of one superblock in one sweep.
@@ -171,6 +173,13 @@ tt_status tt_cross_sweep(tt_job *job, int32_t n_sweeps, tt_info *info);
  * error); fills info.  Status as tt_cross_sweep. */
 tt_status tt_cross_run(tt_job *job, tt_info *info);
 
+/* A batch of count integrals solved together in one call: tt_cross_init,
+ * tt_cross_run and tt_cross_free of one job (every kernel launch serves all of
+ * them), info[count] filled with each integral's result.  Status as
+ * tt_cross_run (TT_CONVERGED; TT_ENUMERIC with info filled if an integral
+ * stopped on a numeric error), or an error of tt_cross_init. */
+tt_status tt_batch_run(tt_ctx *ctx, const tt_problem *problems, int32_t count, tt_info *info);
+
 /* Enqueue n_sweeps sweeps of Alg. 6 on the context stream and return at once:
  * no host synchronisation, no allocation, no memset, so the call may run while
  * the caller captures that stream into a HIP graph.  Every enqueued sweep uses
@@ -199,6 +208,16 @@ tt_status tt_job_history(tt_job *job, int32_t k, double *values, double *values_
                          int64_t capacity, int64_t *written);
 tt_status tt_job_index_sets(tt_job *job, int32_t k, int32_t *ranks, int32_t *nodes,
                             int64_t capacity, int64_t *written);
+/* Core c (0 <= c < m) of integral k at the current ranks, for tests: F_c =
+ * B(I_<=c-1 x nodes, I_>c) as an (r_{c-1} n) x r_c row-major host array (row
+ * alpha*n + i, the index sets in insertion order, B with the job's weights),
+ * and for c < m-1 the interpolation core C_c = F_c M_c^-1 (M_c the rows I_<=c
+ * of F_c) in the same layout; C may be NULL, and is left untouched for the last
+ * core.  TT_DD: leading doubles.  *rows and *cols receive r_{c-1} n and r_c.
+ * Errors: TT_EINVAL (bad k or c, NULL F/rows/cols, capacity below rows*cols). */
+tt_status tt_job_core(tt_job *job, int32_t k, int32_t c, double *F, double *C, int64_t capacity,
+                      int32_t *rows, int32_t *cols);
+
 /* Gauss--Legendre nodes and weights of integral k as generated on the device, n
  * each: t and w rounded to double; t_lo and w_lo (may be NULL) receive the low
  * doubles of the double-double tables (t + t_lo, w + w_lo), for any precision. */

@@ -245,7 +245,7 @@ inline void fill_info(const ProbState& s, tt_info* out) {
   out->value_lo = std::ldexp(s.value_lo, s.vexp);
   out->value_mant = s.value;
   out->value_exp2 = s.vexp;
-  out->reserved = 0;
+  out->recomputes = s.recomputes;
 }
 
 // Node tables for n, generated on first use (defined in ttcross.hip).  With

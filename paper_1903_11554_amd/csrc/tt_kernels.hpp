@@ -39,7 +39,7 @@ static_assert(sizeof(PivRec) == sizeof(tt_pivot), "PivRec must mirror tt_pivot")
 // mantissa for double-double jobs), 1/2 <= |value| < 1 or value = 0.
 struct ProbState {
   int32_t sweeps, done, reason, err_flags;
-  int32_t nacc, max_rank, vexp, pad1;
+  int32_t nacc, max_rank, vexp, recomputes;   // recomputes: interpolation cores rebuilt from F_c
   unsigned long long evals;
   double value, rel, value_lo;
 };
@@ -101,6 +101,7 @@ __device__ __forceinline__ void signal_done(const ProbDesc& p) {
     dst->nacc = src->nacc;
     dst->max_rank = src->max_rank;
     dst->vexp = src->vexp;
+    dst->recomputes = src->recomputes;
     dst->evals = src->evals;
     dst->value = src->value;
     dst->rel = src->rel;
@@ -303,6 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       st->sweeps = 0;
       st->done = 1;
       st->err_flags = isfinite(n_hi(val)) ? 0 : 1;
+      st->recomputes = 0;
       st->reason = st->err_flags ? TT_STOP_ERROR : TT_STOP_CONVERGED;
       st->evals = (m == 1) ? (unsigned long long)n : 0ull;
       st->max_rank = 1;
@@ -349,6 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   if (any_bad || !(best.v > 0.0)) {
     if (tid == 0) {
       st->err_flags = any_bad ? 1 : 4;
+      st->recomputes = 0;
       st->done = 1;
       st->reason = TT_STOP_ERROR;
       st->evals = kStart;
@@ -400,6 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
     st->done = 0;
     st->reason = TT_RUNNING;
     st->err_flags = 0;
+    st->recomputes = 0;
     st->evals = kStart;
     st->max_rank = 1;
     st->rel = __builtin_huge_val();
@@ -708,8 +712,11 @@ struct UpdateSmem {
   T delta;
 };
 
-// |C_c| above which a core's interpolation core is recomputed (see update_core)
-constexpr double kDominance = 1024.0;
+// |C_c| above which a core's interpolation core is recomputed (see update_core):
+// an incremental step amplifies the rounding already in C_c by about |C_c|^2, so
+// at 16 a step adds at most ~256 eps; the Ising crosses of the benchmark stay
+// below 5, while C_d with few nodes reaches 1e10.
+constexpr double kDominance = 16.0;
 
 // running max of |x| for the dominance test; a non-finite x counts as infinite
 __device__ __forceinline__ double cmax_of(double cmax, double x) {
@@ -734,6 +741,7 @@ __device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, con
   const int tid = threadIdx.x;
   if (tid == 0) {
     p.rfl[c] = 1;
+    atomicAdd(&p.st->recomputes, 1);
     if (prow >= 0) sm.rowidx[r0] = prow;
   }
   if (tid < RMAX) sm.perm[tid] = tid;

@@ -586,6 +586,16 @@ tt_status tt_cross_run(tt_job* j, tt_info* info) {
   return sweep_status(st, j->nprob, info);
 }
 
+tt_status tt_batch_run(tt_ctx* ctx, const tt_problem* problems, int32_t count, tt_info* info) {
+  if (!info) return TT_EINVAL;
+  tt_job* j = nullptr;
+  tt_status s = tt_cross_init(ctx, problems, count, &j);
+  if (s != TT_OK) return s;
+  s = tt_cross_run(j, info);
+  tt_cross_free(j);
+  return s;
+}
+
 tt_status tt_cross_integrate(tt_job* j, double* values, tt_info* info) {
   if (!j || !values) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(j->ctx->mu);
@@ -735,6 +745,50 @@ tt_status tt_job_nodes(tt_job* j, int32_t k, double* t, double* w, double* t_lo,
       for (int i = 0; i < d.n; ++i) w_lo[i] = h[i].lo;
     }
   }
+  return TT_OK;
+}
+
+tt_status tt_job_core(tt_job* j, int32_t k, int32_t c, double* F, double* C, int64_t capacity, int32_t* rows,
+                      int32_t* cols) {
+  if (!j || k < 0 || k >= j->nprob || !F || !rows || !cols) return TT_EINVAL;
+  const ProbDesc& d = j->hdesc[k];
+  if (c < 0 || c >= d.m) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  TT_HIP(hipStreamSynchronize(j->ctx->stream));
+  const int m = d.m, n = d.n, R = d.R;
+  int rl = 1, rr = 1;
+  if (c >= 1) TT_HIP(hipMemcpy(&rl, d.rank + (c - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (c <= m - 2) TT_HIP(hipMemcpy(&rr, d.rank + c, sizeof(int32_t), hipMemcpyDeviceToHost));
+  const int64_t nr = (int64_t)rl * n;
+  if (nr * rr > capacity) return TT_EINVAL;
+  const int rowcap = c == 0 ? 1 : R, colcap = c == m - 1 ? 1 : R;
+  const size_t es = j->dd ? sizeof(dd) : sizeof(double);
+  // offsets of core c and interpolation core c inside the job's arrays (host copies of the tables)
+  std::vector<int64_t> foff(m), coff(std::max(m - 1, 1));
+  {
+    Layout pl;
+    const ProbOffsets o = layout_problem(j->probs[k], pl);
+    for (int q = 0; q < m; ++q) foff[q] = o.foff[q];
+    for (int q = 0; q < m - 1; ++q) coff[q] = o.coff[q];
+  }
+  std::vector<char> fbuf((size_t)rowcap * n * colcap * es);
+  TT_HIP(hipMemcpy(fbuf.data(), (char*)d.F + foff[c] * es, fbuf.size(), hipMemcpyDeviceToHost));
+  auto lead = [&](const char* base, size_t idx) {
+    double v;
+    std::memcpy(&v, base + idx * es, sizeof(double));   // the leading double of a dd value comes first
+    return v;
+  };
+  for (int64_t row = 0; row < nr; ++row)
+    for (int q = 0; q < rr; ++q) F[row * rr + q] = lead(fbuf.data(), (size_t)row * colcap + q);
+  if (C && c <= m - 2) {
+    const size_t ldC = (size_t)rowcap * n;   // stored transposed: C[q][row]
+    std::vector<char> cbuf((size_t)R * ldC * es);
+    TT_HIP(hipMemcpy(cbuf.data(), (char*)d.C + coff[c] * es, cbuf.size(), hipMemcpyDeviceToHost));
+    for (int64_t row = 0; row < nr; ++row)
+      for (int q = 0; q < rr; ++q) C[row * rr + q] = lead(cbuf.data(), (size_t)q * ldC + row);
+  }
+  *rows = (int32_t)nr;
+  *cols = rr;
   return TT_OK;
 }
 

@@ -50,7 +50,7 @@ class _Info(ctypes.Structure):
                 ("evals", ctypes.c_int64), ("value", ctypes.c_double),
                 ("rel_change", ctypes.c_double), ("value_lo", ctypes.c_double),
                 ("value_mant", ctypes.c_double), ("value_exp2", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("recomputes", ctypes.c_int32)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -75,7 +75,7 @@ EXPORTS = [
     "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
     "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
     "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue", "tt_mc_integrate",
-    "tt_mc_integrate_noalloc",
+    "tt_mc_integrate_noalloc", "tt_job_core", "tt_batch_run",
 ]
 
 KERNEL_KINDS = {"sweep": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
@@ -129,6 +129,8 @@ def load_library():
         "tt_cross_enqueue": (i32, [vp, i32]),
         "tt_mc_integrate": (i32, [vp, P(_Problem), i32, i64, i32, P(i64), P(dbl), P(dbl), P(dbl)]),
         "tt_mc_integrate_noalloc": (i32, [vp, P(_Problem), i32, i64, i32, P(i64), vp]),
+        "tt_job_core": (i32, [vp, i32, i32, P(dbl), P(dbl), i64, P(i32), P(i32)]),
+        "tt_batch_run": (i32, [vp, P(_Problem), i32, P(_Info)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -231,6 +233,17 @@ class Context:
                                                  n_points, n_sets, g, ctypes.c_void_p(out_dev)),
                "tt_mc_integrate_noalloc")
 
+    def batch_run(self, problems):
+        """tt_batch_run: solve the problems together in one call; the infos of all of them."""
+        keep = []
+        arr = (_Problem * len(problems))(*[_c_problem(p, keep) for p in problems])
+        infos = (_Info * len(problems))()
+        st = self._lib.tt_batch_run(self.handle, arr, len(problems), infos)
+        if st == TT_ENUMERIC:
+            raise TTError(st, "tt_batch_run", Job._info_dicts(infos))
+        _check(st, "tt_batch_run")
+        return Job._info_dicts(infos)
+
     def server(self, max_bytes=1 << 30, max_active=256):
         return Server(self, max_bytes, max_active)
 
@@ -284,7 +297,8 @@ class Job:
     def _info_dicts(infos):
         return [dict(sweeps=i.sweeps, max_rank=i.max_rank, reason=STOP_REASONS.get(i.reason, i.reason),
                      err_flags=i.err_flags, evals=i.evals, value=i.value, rel_change=i.rel_change,
-                     value_lo=i.value_lo, value_mant=i.value_mant, value_exp2=i.value_exp2)
+                     value_lo=i.value_lo, value_mant=i.value_mant, value_exp2=i.value_exp2,
+                     recomputes=i.recomputes)
                 for i in infos]
 
     def _checked_infos(self, status, infos, what):
@@ -389,6 +403,20 @@ class Job:
             return None
         arr = np.array(buf[:written.value], dtype=np.int64).reshape(-1, nb, 16)
         return arr, mhz.value
+
+    def core(self, k, c):
+        """(F_c, C_c) of integral k at the current ranks as (r_{c-1} n) x r_c arrays (C_c None for the last core)."""
+        p = self.problems[k]
+        cap = p.rank_cap * p.n * p.rank_cap
+        F = (ctypes.c_double * cap)()
+        C = (ctypes.c_double * cap)()
+        rows, cols = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.tt_job_core(self.handle, k, c, F, C, cap, ctypes.byref(rows), ctypes.byref(cols)),
+               "tt_job_core")
+        nr, nc = rows.value, cols.value
+        f = np.array(F[:nr * nc]).reshape(nr, nc)
+        cc = np.array(C[:nr * nc]).reshape(nr, nc) if c < p.modes() - 1 else None
+        return f, cc
 
     def nodes(self, k):
         """(t, w) rounded to double."""

@@ -39,7 +39,7 @@ LARGE = [
 ]
 
 
-def compare_large(job, p, ref):
+def compare_large(job, p, ref, check_value=True):
     """GPU run against the oracle run of the same problem, where rounding decides late pivots.
 
     These superblocks are resolved to near the rounding level within a few
@@ -88,7 +88,8 @@ def compare_large(job, p, ref):
     for b in range(m - 2):
         for right in sets[b][1]:
             assert tuple(right[1:]) in {tuple(x) for x in sets[b + 1][1]}
-    assert abs(info["value"] - ref.history[-1]) <= 10 * p.tol * abs(ref.history[-1]), (info, ref.history[-1])
+    if check_value:
+        assert abs(info["value"] - ref.history[-1]) <= 10 * p.tol * abs(ref.history[-1]), (info, ref.history[-1])
     return len(pts)
 
 
@@ -230,4 +231,82 @@ def test_c_d_with_few_nodes_stays_accurate(d, rank, tol, bound):
     assert info["err_flags"] == 0 and info["reason"] == "converged"
     assert abs(info["value"] / c_inf - 1) < bound
     assert max(abs(h / c_inf - 1) for h in hist[5:]) < 1e-3   # no excursion on the way
+    job.free()
+
+
+def oracle_on_gpu_sets(p, sets):
+    """The oracle's tensor, cores and quadrature on the GPU's own index sets (its start only is run)."""
+    ref = oracle_tt.TTCross(p.family, p.d, p.n, p.rank_cap, p.tol, p.seed, max_sweeps=1, params=p.params)
+    ref.left = [[tuple(x) for x in s[0]] for s in sets]
+    ref.right = [[tuple(x) for x in s[1]] for s in sets]
+    return ref
+
+
+def check_cores_on_own_sets(job, p, value_tol):
+    """Entry by entry: every F_c the GPU holds equals the oracle's B on the GPU's own index sets;
+    every interpolation core solves C_c M_c = F_c to a backward-stable residual; the GPU's integral
+    is the oracle's TT quadrature of those sets within value_tol (relative)."""
+    sets = job.index_sets(0)
+    ref = oracle_on_gpu_sets(p, sets)
+    m = p.modes()
+    eps = 2.0 ** -52
+    worst = 0.0
+    for c in range(m):
+        F, C = job.core(0, c)
+        want = ref.core(c).reshape(F.shape)
+        np.testing.assert_allclose(F, want, rtol=1e-13, atol=0, err_msg=f"core {c}")
+        if C is not None:
+            M = ref.cross_matrix(c)
+            r = M.shape[0]
+            resid = np.abs(C @ M - want).max()
+            scale = np.abs(C).max() * np.abs(M).max() * r
+            worst = max(worst, resid / scale)
+            assert resid <= 1e4 * r * eps * scale, (c, resid, scale)
+    # the two sides compute the quadrature of the same sets through different factorisations of
+    # the crosses, so they may differ by rounding amplified by the crosses' condition numbers
+    kappa = max(np.linalg.cond(ref.cross_matrix(c)) for c in range(m - 1))
+    value = job.values()[0][0]
+    own = ref.integral()
+    bound = max(value_tol, 64 * eps * kappa)
+    assert abs(value - own) <= bound * abs(own), (value, own, kappa)
+    return worst
+
+
+# rank caps of 12-16 at 33-60 modes: the later sweeps run the rank-16 streaming sweep kernel
+LARGE_R16 = [
+    Problem("ising_c", 41, 8, 14, 1e-12, seed=41, max_sweeps=12),
+    Problem("ising_d", 34, 8, 14, 1e-13, seed=34, max_sweeps=10),
+]
+
+
+@pytest.mark.parametrize("k", range(len(LARGE_R16)))
+def test_large_parity_rank16_kernel(k):
+    p = LARGE_R16[k]
+    print(f"large rank-16 parity {p}", flush=True)
+    ctx = gpu_context()
+    job = ctx.job([p])
+    info = job.run()[0]
+    assert info["sweeps"] >= 8 and info["max_rank"] > 8, info   # ranks above 8 reached: the rank-16 kernel ran
+    ref = run_oracle(p)
+    # with the run stopped by max_sweeps, late decisions taken at the rounding level leave the two runs
+    # on different sets: the value is compared with the oracle's quadrature of the GPU's own sets
+    npts = compare_large(job, p, ref, check_value=info["reason"] == "converged")
+    worst = check_cores_on_own_sets(job, p, 1e-12)
+    print(f"  {npts} pivot entries, every core entry checked; worst C M - F residual {worst:.2e}", flush=True)
+    job.free()
+
+
+@pytest.mark.parametrize("d,rank,tol", [(32, 16, 1e-12), (48, 12, 1e-11)])
+def test_recomputed_interpolation_cores_against_the_oracle(d, rank, tol):
+    """C_d with 33 nodes, where the crosses lose dominance and the interpolation cores are rebuilt
+    from F_c (the count is reported in the info): the cores the GPU ends with are checked entry by
+    entry on its own index sets, and its value against the oracle's quadrature of those sets."""
+    p = Problem("ising_c", d, 33, rank, tol, seed=d)
+    ctx = gpu_context()
+    job = ctx.job([p])
+    info = job.run()[0]
+    print(f"C_{d}: {info}", flush=True)
+    assert info["err_flags"] == 0 and info["recomputes"] > 0, info
+    worst = check_cores_on_own_sets(job, p, 1e-9)
+    print(f"  worst C M - F residual {worst:.2e}", flush=True)
     job.free()

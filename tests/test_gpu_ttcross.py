@@ -419,3 +419,16 @@ def test_numeric_error_in_a_sweep_stops_the_integral_with_reason_error():
     assert ib["reason"] == "error" and ib["err_flags"] & 1 and ib["sweeps"] == 1, ib
     assert ig["reason"] == ainfo["reason"] and ig["value"] == ainfo["value"] and ig["err_flags"] == 0
     job.free()
+
+
+def test_batch_run_entry_point_equals_the_job_api():
+    """tt_batch_run (init, run and free in one call) gives what a job of the same integrals gives."""
+    ctx = gpu_context()
+    probs = [SMALL[i] for i in (3, 4, 6)]
+    infos = ctx.batch_run(probs)
+    job = ctx.job(probs)
+    ref = job.run()
+    job.free()
+    for a, b in zip(infos, ref):
+        for key in ("value", "value_lo", "evals", "sweeps", "reason", "max_rank", "err_flags"):
+            assert a[key] == b[key], (key, a, b)
