@@ -483,6 +483,271 @@ __device__ __forceinline__ double synthetic_seg(int family, const Segs& s, const
   return e + c;
 }
 
+// ------------------------------------------ paper form from row summaries
+// Points that share a left index-set row (coordinates y_0..y_{p-1}) and a right
+// one (y_o..y_{m-1}, o = p + nM) around nM = 1 or 2 nodes: every run y_a..y_b of
+// A_d lies inside the left row, inside the right row, or contains a node.  The
+// runs inside a row, and B_d's sums over its coordinates, are the same for every
+// point with that row, so they are formed once per row; a point multiplies only
+// the runs through its nodes, (p + 1)(m - p) of them for one node instead of
+// m(m + 1)/2.  The integral is unchanged; the rounding differs from the one-pass
+// evaluation only in how each run's product is associated.
+//
+// A row summary: MAXM run products, then kSumScalars scalars:
+//   run[k]  left row: y_k..y_{p-1} (k < p);  right row: y_o..y_k (o <= k < m)
+//   an, ad  prod over the runs inside the row of (1 - run) and (1 + run)
+//   q       left: sum_{b<p} y_0..y_b;   right: sum_{b>=o} y_o..y_b
+//   P       product of the row's coordinates (1 for an empty row)
+//   S       left: sum_{a<p} y_a..y_{p-1};   right: sum_{a>=o} y_a..y_{m-1}
+//   W       product of the row's weights
+constexpr int kSumScalars = 6;
+enum { RS_AN = 0, RS_AD = 1, RS_Q = 2, RS_P = 3, RS_S = 4, RS_W = 5 };
+
+// Summary of coordinates y[k0..k1) (y indexed by absolute coordinate) into out,
+// as a left row (run[k] = suffix products) or a right row (run[k] = prefix
+// products).  One thread per row.
+template <class T, int MAXM>
+__device__ __forceinline__ void summarise_row(int family, const T (&y)[MAXM], int k0, int k1, bool left, T w,
+                                              T* __restrict__ out) {
+  const T zero = num<T>(0.0), one = num<T>(1.0);
+  const bool need_a = family != TT_ISING_C;
+  T z[MAXM];
+#pragma unroll
+  for (int k = 0; k < MAXM; ++k) z[k] = (k >= k0 && k < k1) ? y[k] : zero;
+  T an = one, ad = one, q = zero, pre = one;
+#pragma unroll
+  for (int b = 0; b < MAXM; ++b) {
+    if (b >= k0 && b < k1) {
+      const T yb = z[b];
+#pragma unroll
+      for (int a = 0; a < b; ++a)
+        if (a >= k0) z[a] = n_mul(z[a], yb);            // z[a] = y_a..y_b
+      pre = n_mul(pre, yb);                              // y_k0..y_b, as z[k0]
+      q = n_add(q, pre);
+      if (!left) out[b] = pre;
+      if (need_a) {
+#pragma unroll
+        for (int a = 0; a <= b; ++a)
+          if (a >= k0) {
+            an = n_nmad(an, z[a], an);
+            ad = n_mad(ad, z[a], ad);
+          }
+      }
+    }
+  }
+  T S = zero;
+#pragma unroll
+  for (int a = 0; a < MAXM; ++a) {
+    if (a >= k0 && a < k1) {
+      S = n_add(S, z[a]);
+      if (left) out[a] = z[a];                           // suffix product y_a..y_{p-1}
+    }
+  }
+  out[MAXM + RS_AN] = an;
+  out[MAXM + RS_AD] = ad;
+  out[MAXM + RS_Q] = q;
+  out[MAXM + RS_P] = pre;
+  out[MAXM + RS_S] = S;
+  out[MAXM + RS_W] = w;
+}
+
+// A left and a right row summary held in registers for the points that share
+// them: the left row's suffix products y_a..y_{p-1} (a < p), the right row's
+// prefix products y_o..y_{o+j} (j < nr = m - o), and the scalars of both.
+template <class T, int MAXM>
+struct RowPair {
+  T lsuf[MAXM], rpre[MAXM];
+  T an, ad, Lq, LP, LS, Rq, RP, Rs;
+};
+
+template <class T, int MAXM>
+__device__ __forceinline__ void load_row_pair(RowPair<T, MAXM>& rp, const T* __restrict__ L,
+                                              const T* __restrict__ R, int p, int o, int nr) {
+#pragma unroll
+  for (int a = 0; a < MAXM; ++a) rp.lsuf[a] = L[a < p ? a : 0];
+#pragma unroll
+  for (int j = 0; j < MAXM; ++j) rp.rpre[j] = R[o + (j < nr ? j : 0)];
+  rp.an = n_mul(L[MAXM + RS_AN], R[MAXM + RS_AN]);
+  rp.ad = n_mul(L[MAXM + RS_AD], R[MAXM + RS_AD]);
+  rp.Lq = L[MAXM + RS_Q];
+  rp.LP = L[MAXM + RS_P];
+  rp.LS = L[MAXM + RS_S];
+  rp.Rq = R[MAXM + RS_Q];
+  rp.RP = R[MAXM + RS_P];
+  rp.Rs = R[MAXM + RS_S];
+}
+
+// The paper-form integrand (factor 2 included) at a point joined from a row pair
+// (left coordinates 0..p-1, right coordinates o..m-1, o = p + nM) and nM = 1 or
+// 2 nodes t0, t1 at coordinates p, p+1.  Every run through a node is
+// (y_a..y_{p-1}) t0 [t1] (y_o..y_b); the loops are unrolled over the mode bound
+// with wave-uniform guards, so every product is read from registers.
+template <class T, int MAXM>
+__device__ __forceinline__ T ising_joined(int family, int m, int p, int nM, const RowPair<T, MAXM>& rp, T t0, T t1) {
+  const T one = num<T>(1.0);
+  const int nr = m - p - nM;
+  T nm = num<T>(2.0), den = one;
+  if (family != TT_ISING_E) {   // B_d: q and s joined around the nodes
+    T q, sfx;
+    if (nM == 2) {
+      q = n_mad(n_mul(rp.LP, t0), n_mad(t1, n_add(one, rp.Rq), one), rp.Lq);
+      sfx = n_mad(n_mul(t1, rp.RP), n_mad(t0, n_add(one, rp.LS), one), rp.Rs);
+    } else {
+      q = n_mad(n_mul(rp.LP, t0), n_add(one, rp.Rq), rp.Lq);
+      sfx = n_mad(n_mul(t0, rp.RP), n_add(one, rp.LS), rp.Rs);
+    }
+    den = n_mul(n_add(one, q), n_add(one, sfx));
+  }
+  if (family != TT_ISING_C) {   // A_d: the runs inside the rows, then the runs through the nodes
+    T pn = rp.an, pd = rp.ad;
+#pragma unroll
+    for (int a = 0; a < MAXM; ++a) {          // runs from coordinate a <= p through the first node
+      if (a <= p) {
+        T u = (a < p) ? n_mul(rp.lsuf[a], t0) : t0;
+        pn = n_nmad(pn, u, pn);
+        pd = n_mad(pd, u, pd);
+        if (nM == 2) {
+          u = n_mul(u, t1);
+          pn = n_nmad(pn, u, pn);
+          pd = n_mad(pd, u, pd);
+        }
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+          if (j < nr) {
+            const T v = n_mul(u, rp.rpre[j]);
+            pn = n_nmad(pn, v, pn);
+            pd = n_mad(pd, v, pd);
+          }
+        }
+      }
+    }
+    if (nM == 2) {                            // runs from the second node
+      pn = n_nmad(pn, t1, pn);
+      pd = n_mad(pd, t1, pd);
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) {
+        if (j < nr) {
+          const T v = n_mul(t1, rp.rpre[j]);
+          pn = n_nmad(pn, v, pn);
+          pd = n_mad(pd, v, pd);
+        }
+      }
+    }
+    if (m <= 31) {                            // pd^2 <= 2^(m(m+1)) stays finite
+      nm = n_mul(n_mul(nm, pn), pn);
+      den = n_mul(den, n_mul(pd, pd));
+    } else {
+      const T r = n_div(pn, pd);
+      nm = n_mul(n_mul(nm, r), r);
+    }
+  }
+  return n_div(nm, den);
+}
+
+// Two points of one row pair at nodes ta and tb (one node each, nM = 1): the
+// same operations as ising_joined for each, with the two points' products
+// interleaved so that four independent chains are in flight.
+template <class T, int MAXM>
+__device__ __forceinline__ void ising_joined2(int family, int m, int p, const RowPair<T, MAXM>& rp, T ta, T tb,
+                                              T& fa, T& fb) {
+  const T one = num<T>(1.0);
+  const int nr = m - p - 1;
+  T nma = num<T>(2.0), nmb = num<T>(2.0), dena = one, denb = one;
+  if (family != TT_ISING_E) {
+    const T rq1 = n_add(one, rp.Rq), ls1 = n_add(one, rp.LS);
+    const T qa = n_mad(n_mul(rp.LP, ta), rq1, rp.Lq), qb = n_mad(n_mul(rp.LP, tb), rq1, rp.Lq);
+    const T sa = n_mad(n_mul(ta, rp.RP), ls1, rp.Rs), sb = n_mad(n_mul(tb, rp.RP), ls1, rp.Rs);
+    dena = n_mul(n_add(one, qa), n_add(one, sa));
+    denb = n_mul(n_add(one, qb), n_add(one, sb));
+  }
+  if (family != TT_ISING_C) {
+    T pna = rp.an, pda = rp.ad, pnb = rp.an, pdb = rp.ad;
+#pragma unroll
+    for (int a = 0; a < MAXM; ++a) {
+      if (a <= p) {
+        const T ua = (a < p) ? n_mul(rp.lsuf[a], ta) : ta;
+        const T ub = (a < p) ? n_mul(rp.lsuf[a], tb) : tb;
+        pna = n_nmad(pna, ua, pna);
+        pda = n_mad(pda, ua, pda);
+        pnb = n_nmad(pnb, ub, pnb);
+        pdb = n_mad(pdb, ub, pdb);
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+          if (j < nr) {
+            const T va = n_mul(ua, rp.rpre[j]), vb = n_mul(ub, rp.rpre[j]);
+            pna = n_nmad(pna, va, pna);
+            pda = n_mad(pda, va, pda);
+            pnb = n_nmad(pnb, vb, pnb);
+            pdb = n_mad(pdb, vb, pdb);
+          }
+        }
+      }
+    }
+    if (m <= 31) {
+      nma = n_mul(n_mul(nma, pna), pna);
+      dena = n_mul(dena, n_mul(pda, pda));
+      nmb = n_mul(n_mul(nmb, pnb), pnb);
+      denb = n_mul(denb, n_mul(pdb, pdb));
+    } else {
+      const T ra = n_div(pna, pda), rb = n_div(pnb, pdb);
+      nma = n_mul(n_mul(nma, ra), ra);
+      nmb = n_mul(n_mul(nmb, rb), rb);
+    }
+  }
+  fa = n_div(nma, dena);
+  fb = n_div(nmb, denb);
+}
+
+// ising_joined2 for a mode count M and a node position P known at compile time:
+// every loop bound is a constant, so the runs through the node are straight-line
+// code (the same operations in the same order as ising_joined2, hence the same
+// bits).
+template <class T, int M, int P>
+__device__ __forceinline__ void ising_joined2_fixed(int family, const RowPair<T, M>& rp, T ta, T tb, T& fa, T& fb) {
+  constexpr int NR = M - P - 1;
+  const T one = num<T>(1.0);
+  T nma = num<T>(2.0), nmb = num<T>(2.0), dena = one, denb = one;
+  if (family != TT_ISING_E) {
+    const T rq1 = n_add(one, rp.Rq), ls1 = n_add(one, rp.LS);
+    const T qa = n_mad(n_mul(rp.LP, ta), rq1, rp.Lq), qb = n_mad(n_mul(rp.LP, tb), rq1, rp.Lq);
+    const T sa = n_mad(n_mul(ta, rp.RP), ls1, rp.Rs), sb = n_mad(n_mul(tb, rp.RP), ls1, rp.Rs);
+    dena = n_mul(n_add(one, qa), n_add(one, sa));
+    denb = n_mul(n_add(one, qb), n_add(one, sb));
+  }
+  if (family != TT_ISING_C) {
+    T pna = rp.an, pda = rp.ad, pnb = rp.an, pdb = rp.ad;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+      const T ua = (a < P) ? n_mul(rp.lsuf[a], ta) : ta;
+      const T ub = (a < P) ? n_mul(rp.lsuf[a], tb) : tb;
+      pna = n_nmad(pna, ua, pna);
+      pda = n_mad(pda, ua, pda);
+      pnb = n_nmad(pnb, ub, pnb);
+      pdb = n_mad(pdb, ub, pdb);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        const T va = n_mul(ua, rp.rpre[j]), vb = n_mul(ub, rp.rpre[j]);
+        pna = n_nmad(pna, va, pna);
+        pda = n_mad(pda, va, pda);
+        pnb = n_nmad(pnb, vb, pnb);
+        pdb = n_mad(pdb, vb, pdb);
+      }
+    }
+    if (M <= 31) {
+      nma = n_mul(n_mul(nma, pna), pna);
+      dena = n_mul(dena, n_mul(pda, pda));
+      nmb = n_mul(n_mul(nmb, pnb), pnb);
+      denb = n_mul(denb, n_mul(pdb, pdb));
+    } else {
+      const T ra = n_div(pna, pda), rb = n_div(pnb, pdb);
+      nma = n_mul(n_mul(nma, ra), ra);
+      nmb = n_mul(n_mul(nmb, rb), rb);
+    }
+  }
+  fa = n_div(nma, dena);
+  fb = n_div(nmb, denb);
+}
+
 // --------------------------------------------------------------- reductions
 // argmax of |e| with ties to the lowest index; NaN never wins (comparisons are false).
 struct ArgMax {

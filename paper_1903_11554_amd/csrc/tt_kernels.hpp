@@ -1660,6 +1660,132 @@ __global__ __launch_bounds__(kBlock) void k_eval_fibers(FamilyArgs fa_in, int n,
   }
 }
 
+constexpr int kFibreNodesPerLane = 4;
+constexpr int kRowsMaxModes = 16;   // the row-summary fibre kernel serves exact mode counts up to 16
+
+// The point loop of k_eval_fibers_rows: work item q = (alpha, node chunk, beta),
+// beta fastest; the row pair is loaded once per item and the nodes of the chunk
+// are taken two at a time.  With P >= 0 the node position is the compile-time P.
+template <class T, int MAXM, int P>
+__device__ __forceinline__ void fibre_rows_items(int family, int m, int n, int pos_rt, const int32_t* __restrict__ left,
+                                                 int rl, const int32_t* __restrict__ right, int rr, T* sL, T* sR,
+                                                 const T* st, const T* sw, T* __restrict__ out, uint32_t total,
+                                                 uint32_t nchunk, uint32_t stride) {
+  constexpr int RS = MAXM + kSumScalars;
+  const int pos = P >= 0 ? P : pos_rt;   // a constant where the caller fixed it: every guard folds
+  const int nr = m - pos - 1;
+  const int tid = threadIdx.x;
+  // the left rows of this workgroup's first stride of items (the right rows are all needed)
+  const bool one_pass = stride >= total;   // every lane takes at most one item
+  const uint32_t q_first = blockIdx.x * blockDim.x;
+  const int al_lo = one_pass ? (int)(q_first / ((uint32_t)rr * nchunk)) : 0;
+  const int al_hi = one_pass ? min(rl, (int)((min(q_first + blockDim.x, total) - 1) / ((uint32_t)rr * nchunk)) + 1) : rl;
+  const int nl = q_first < total ? al_hi - al_lo : 0;
+  for (int r = tid; r < nl + rr; r += blockDim.x) {   // one thread per row
+    const bool isl = r < nl;
+    const int a = isl ? al_lo + r : r - nl;
+    T y[MAXM];
+    T ww = num<T>(1.0);
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) y[k] = num<T>(0.0);
+    if (isl) {
+#pragma unroll
+      for (int k = 0; k < MAXM; ++k)
+        if (k < pos) {
+          const int ik = left[a * pos + k];
+          y[k] = st[ik];
+          ww = n_mul(ww, sw[ik]);
+        }
+      summarise_row<T, MAXM>(family, y, 0, pos, true, ww, sL + a * RS);
+    } else {
+#pragma unroll
+      for (int k = MAXM - 1; k >= 0; --k)            // weights multiplied from the right end
+        if (k > pos && k < m) {
+          const int ik = right[a * nr + (k - pos - 1)];
+          y[k] = st[ik];
+          ww = n_mul(sw[ik], ww);
+        }
+      summarise_row<T, MAXM>(family, y, pos + 1, m, false, ww, sR + a * RS);
+    }
+  }
+  __syncthreads();
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
+    const int be = (int)(q % (uint32_t)rr);
+    const uint32_t rest = q / (uint32_t)rr;
+    const int c = (int)(rest % nchunk), al = (int)(rest / nchunk);
+    const T* L = sL + al * RS;
+    const T* R = sR + be * RS;
+    RowPair<T, MAXM> rp;
+    load_row_pair<T, MAXM>(rp, L, R, pos, pos + 1, nr);
+    const T WL = L[MAXM + RS_W], WR = R[MAXM + RS_W];
+    const int i0 = c * kFibreNodesPerLane;
+#pragma unroll 1
+    for (int k = 0; k < kFibreNodesPerLane; k += 2) {
+      const int ia = i0 + k;
+      if (ia >= n) break;
+      const int ib = ia + 1 < n ? ia + 1 : ia;
+      T fa, fb;
+      if constexpr (P >= 0)
+        ising_joined2_fixed<T, MAXM, P>(family, rp, st[ia], st[ib], fa, fb);
+      else
+        ising_joined2<T, MAXM>(family, m, pos, rp, st[ia], st[ib], fa, fb);
+      out[((size_t)al * n + ia) * rr + be] = n_mul(n_mul(n_mul(WL, sw[ia]), WR), fa);
+      if (ia + 1 < n) out[((size_t)al * n + ib) * rr + be] = n_mul(n_mul(n_mul(WL, sw[ib]), WR), fb);
+    }
+  }
+}
+
+// dispatch on the node position: compile-time P for exact mode counts up to 16
+template <class T, int MAXM, bool EXACT, int P = 0>
+__device__ __forceinline__ void fibre_rows_points(int family, int m, int n, int pos, const int32_t* left, int rl,
+                                                  const int32_t* right, int rr, T* sL, T* sR, const T* st,
+                                                  const T* sw, T* __restrict__ out, uint32_t total, uint32_t nchunk,
+                                                  uint32_t stride) {
+  if constexpr (EXACT && MAXM <= 16) {
+    if constexpr (P < MAXM) {
+      if (pos == P)
+        fibre_rows_items<T, MAXM, P>(family, m, n, pos, left, rl, right, rr, sL, sR, st, sw, out, total, nchunk,
+                                     stride);
+      else
+        fibre_rows_points<T, MAXM, EXACT, P + 1>(family, m, n, pos, left, rl, right, rr, sL, sR, st, sw, out,
+                                                 total, nchunk, stride);
+    }
+  } else {
+    fibre_rows_items<T, MAXM, -1>(family, m, n, pos, left, rl, right, rr, sL, sR, st, sw, out, total, nchunk,
+                                  stride);
+  }
+}
+
+// The fibre set I_left x [n] x I_right of the paper-form integrands (eqs. c, d,
+// e) from row summaries: each left and right row is summarised once per
+// workgroup into LDS (the runs inside it, B_d's sums over it, its weight), and
+// a lane takes one (alpha, beta) pair and kFibreNodesPerLane consecutive nodes,
+// joining the two summaries around each node (ising_joined).  Lanes are ordered
+// (alpha, node chunk, beta), beta fastest, so the stores of one node are
+// consecutive across lanes.  The grid is bounded and strides over the work
+// items.  EXACT = true compiles for exactly MAXM modes.
+
+
+template <class T, int MAXM, bool EXACT>
+__global__ __launch_bounds__(kBlock) void k_eval_fibers_rows(FamilyArgs fa_in, int n, const T* __restrict__ t,
+                                                             const T* __restrict__ w, int pos,
+                                                             const int32_t* __restrict__ left, int rl,
+                                                             const int32_t* __restrict__ right, int rr,
+                                                             T* __restrict__ out) {
+  constexpr int RS = MAXM + kSumScalars;
+  __shared__ T sL[TT_MAX_RANK * RS], sR[TT_MAX_RANK * RS];
+  __shared__ T st[TT_MAX_NODES], sw[TT_MAX_NODES];
+  const int family = fa_in.family;
+  const int m = EXACT ? MAXM : fa_in.m, tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) { st[i] = t[i]; sw[i] = w[i]; }
+  __syncthreads();
+  const uint32_t nchunk = (uint32_t)(n + kFibreNodesPerLane - 1) / kFibreNodesPerLane;
+  const uint32_t total = (uint32_t)rl * nchunk * (uint32_t)rr;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  fibre_rows_points<T, MAXM, EXACT>(family, m, n, pos, left, rl, right, rr, sL, sR, st, sw, out, total, nchunk,
+                                    stride);
+}
+
 // ------------------------------------------------- equal-weight quadrature
 // Monte Carlo (eq. mc) and randomly shifted rank-1 lattice rules (eq. qmc),
 // Sec. 4.2.  Estimator j = blockIdx.y sums f over its N points: random points

@@ -180,15 +180,30 @@ void eval_fibers_k(tt_ctx* ctx, dim3 grid, dim3 block, const FamilyArgs& fa, int
                      d_right, r_right, reinterpret_cast<T*>(d_out));
 }
 
+// The paper form from row summaries (k_eval_fibers_rows).
+template <class T, int MAXM, bool EXACT>
+void eval_fibers_rows(tt_ctx* ctx, dim3 grid, dim3 block, const FamilyArgs& fa, int n, const double* t,
+                      const double* w, int pos, const int32_t* d_left, int r_left, const int32_t* d_right,
+                      int r_right, double* d_out) {
+  hipLaunchKernelGGL((k_eval_fibers_rows<T, MAXM, EXACT>), grid, block, 0, ctx->stream, fa, n,
+                     reinterpret_cast<const T*>(t), reinterpret_cast<const T*>(w), pos, d_left, r_left, d_right,
+                     r_right, reinterpret_cast<T*>(d_out));
+}
+
 // Paper form in double: one kernel per exact number of modes (1..TT_MAX_REG_MODES).
 template <int M>
 void eval_fibers_exact(tt_ctx* ctx, int m, dim3 grid, dim3 block, const FamilyArgs& fa, int n, const double* t,
                        const double* w, int pos, const int32_t* d_left, int r_left, const int32_t* d_right,
                        int r_right, double* d_out) {
   if constexpr (M <= TT_MAX_REG_MODES) {
-    if (m == M)
-      eval_fibers_k<double, FAM_PAPER, M, true>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right,
-                                                r_right, d_out);
+    if (m == M) {
+      if constexpr (M <= kRowsMaxModes)
+        eval_fibers_rows<double, M, true>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right,
+                                          d_out);
+      else
+        eval_fibers_k<double, FAM_PAPER, M, true>(ctx, grid, block, fa, n, t, w, pos, d_left, r_left, d_right,
+                                                  r_right, d_out);
+    }
     else
       eval_fibers_exact<M + 1>(ctx, m, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out);
   }
@@ -853,12 +868,15 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
   FamilyArgs fa;
   s = family_for(ctx, p, &fa);
   if (s != TT_OK) return s;
-  const int64_t total = (int64_t)r_left * p->n_nodes * r_right;   // < 2^31 by the rank and node limits
+  const int fam = fam_of(p->integrand);
+  // work items: points, or for the row-summary kernel (alpha, node chunk, beta) triples
+  const bool rows = fam == FAM_PAPER && !use_dd && m <= kRowsMaxModes;
+  const int64_t chunks = rows ? (p->n_nodes + kFibreNodesPerLane - 1) / kFibreNodesPerLane : p->n_nodes;
+  const int64_t total = (int64_t)r_left * chunks * r_right;   // < 2^31 by the rank and node limits
   const int64_t blocks64 = std::min<int64_t>((total + kBlock - 1) / kBlock, 1024);
   const dim3 grid((unsigned)blocks64), block(kBlock);
   const int n = p->n_nodes, mb = bucket_m(m);
   Timed tm(ctx, KK_EVAL_FIBERS);
-  const int fam = fam_of(p->integrand);
   if (use_dd)
     eval_fibers_f<dd, FAM_PAPER>(ctx, mb, grid, block, fa, n, t, w, pos, d_left, r_left, d_right, r_right, d_out);
   else if (fam == FAM_PAPER)

@@ -98,6 +98,42 @@ def test_eval_fibers_matches_oracle(family, d, n, pos, rl, rr):
                                atol=np.abs(want).max() * 1e-290)
 
 
+@pytest.mark.parametrize("family", ["ising_d", "ising_c", "ising_e"])
+def test_eval_fibers_every_mode_count_and_position(family):
+    """The paper form's fibre kernels at every mode count 1..18 and every node position.
+
+    Up to 16 modes the row-summary kernel serves (a compile-time node position per
+    case), above that the one-pass kernel; 9 nodes leave a ragged last chunk of
+    the four nodes a lane takes, and the set sizes are odd.
+    """
+    torch = require_gpu()
+    ctx = gpu_context()
+    n = 9
+    t, w = gauss_legendre_01(n)
+    for d in range(2, 20):
+        p = Problem(family, d, n, 8, 1e-10)
+        m = p.modes()
+        for pos in range(m):
+            rl = 5 if pos > 0 else 1
+            rr = 3 if pos < m - 1 else 1
+            left = random_index_set(rl, pos, n, seed=d * 100 + pos) if pos > 0 else np.zeros((1, 0), np.int32)
+            right = (random_index_set(rr, m - pos - 1, n, seed=d * 100 + pos + 50) if pos < m - 1
+                     else np.zeros((1, 0), np.int32))
+            print(f"eval_fibers {family} d={d} pos={pos} rl={rl} rr={rr}", flush=True)
+            ld = torch.from_numpy(np.ascontiguousarray(left)).cuda() if pos > 0 else None
+            rd = torch.from_numpy(np.ascontiguousarray(right)).cuda() if pos < m - 1 else None
+            out = torch.full((rl * n * rr,), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.eval_fibers(p, pos, ld.data_ptr() if ld is not None else 0, rl,
+                            rd.data_ptr() if rd is not None else 0, rr, out.data_ptr())
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            idx = np.array([list(left[a]) + [i] + list(right[b]) for a in range(rl) for i in range(n)
+                            for b in range(rr)], dtype=np.int64)
+            want = weighted_values(family, idx, t, w)
+            np.testing.assert_allclose(got, want, rtol=eps_bound(op_count(family, m)),
+                                       atol=np.abs(want).max() * 1e-290, err_msg=f"d={d} pos={pos}")
+
+
 def test_eval_fibers_graph_replay_matches_eager():
     """Library launches captured in a HIP graph replay to the eager result, replay after replay."""
     torch = require_gpu()
