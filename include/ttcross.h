@@ -121,6 +121,12 @@ typedef struct {
   int32_t recomputes;  /*   value_lo are 0 or +-inf when the estimate leaves the double range;
                           recomputes: interpolation cores rebuilt from F_c with a pivoted
                           solve so far (double jobs whose crosses lost dominance)        */
+  int32_t value_scale; /* E: above 32 modes every value of B the job forms (pivot log,
+                          cores) is f W 2^(s m) 2^E, E fixed at the start so that its B
+                          lies in [1/2, 1) (D_d falls below the double range from about
+                          d = 512, Sec. 5.5); 0 up to 32 modes. value_mant/value_exp2
+                          are unscaled.                                                   */
+  int32_t reserved;
 } tt_info;
 
 /* One accepted-or-rejected pivot search of one superblock in one sweep.
@@ -130,8 +136,8 @@ typedef struct {
   int32_t row, col;    /* pivot position in the superblock (-1: not searched)            */
   int32_t accepted;    /* 1 if appended to the index sets                                 */
   int32_t iters;       /* rook (column,row) pairs used, 1..5; 0 if not searched            */
-  double  err;         /* B - B~ at the pivot, B with the job's weights (times 2^(s m));
-                          signed; TT_DD: leading double                                   */
+  double  err;         /* B - B~ at the pivot, B with the job's weights (times 2^(s m)
+                          2^E, E = tt_info.value_scale); signed; TT_DD: leading double   */
   double  value;       /* B at the pivot (same scale; TT_DD: leading double)              */
   int32_t col_fresh;   /* 1 if the last column step of the rook loop was at `col`: its
                           values are the new column of the core left of the bond       */

@@ -184,6 +184,49 @@ def weighted_values(family, idx, t, w, params=None):
     return wt * f_values(family, x, params)
 
 
+def log2_weighted_values(family, idx, t, w):
+    """log2 of B at integer multi-indices idx (npts, m) for the paper-form integrands.
+
+    The same formulas (eqs. c, d, e) taken through logarithms of their factors,
+    so that values far below the double range (D_d near 10^(-0.7 d), Sec. 5.5)
+    are represented:
+        ln f = ln 2 + 2 sum_{runs} [ln(1 - p) - ln(1 + p)] - ln(1 + q) - ln(1 + s),
+    each run product p = x_{i+1}..x_j recomputed from its factors (a product that
+    underflows to 0 contributes ln 1 = 0, below the double rounding of the sum),
+    plus the logarithms of the weights.  The absolute error of the result is
+    about |log2 B| times the double rounding unit.
+    """
+    idx = np.asarray(idx, dtype=np.int64)
+    if idx.ndim != 2:
+        raise ValueError("idx must be 2-D (npts, m)")
+    if family not in PAPER_FORM:
+        raise ValueError(f"no log-scale path for {family}")
+    npts, m = idx.shape
+    d = m + 1
+    x = t[idx] if m > 0 else np.zeros((npts, 0))
+
+    def prod_range(a, b):  # x_a * ... * x_b  (a <= b, 2 <= a, b <= d)
+        return np.prod(x[:, a - 2:b - 1], axis=1)
+
+    lf = np.full(npts, math.log(2.0))
+    if family in ("ising_c", "ising_d"):
+        s_left = np.ones(npts)
+        s_right = np.ones(npts)
+        for k in range(2, d + 1):
+            s_left = s_left + prod_range(2, k)
+            s_right = s_right + prod_range(k, d)
+        lf = lf - np.log(s_left) - np.log(s_right)
+    if family in ("ising_d", "ising_e"):
+        acc = np.zeros(npts)
+        for i in range(1, d):
+            for j in range(i + 1, d + 1):
+                p = prod_range(i + 1, j)
+                acc = acc + (np.log1p(-p) - np.log1p(p))
+        lf = lf + 2.0 * acc
+    lw = np.sum(np.log(w[idx]), axis=1) if m > 0 else np.zeros(npts)
+    return (lf + lw) / math.log(2.0)
+
+
 def exact_synthetic(family, params, d):
     """Exact integral over [0,1]^d of the synthetic families."""
     a = np.asarray(params["a"], dtype=np.float64)[:d]

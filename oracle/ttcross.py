@@ -36,6 +36,15 @@ computation, bit for bit.
 
 Readings of the paper where it is silent:
   * start: rank 1 at the largest |B| among 1024 SplitMix64 samples of the grid;
+    above 32 modes, for D_d and E_d, the n constant multi-indices (every mode
+    at node j) are candidates too, after the random ones, since a random
+    point's B falls far below the double range for D_d from about d = 128 on
+    (Sec. 5.5) while the constant points reach the largest entries (C_d and the
+    synthetic families stay near 1).  Above 32 modes the candidates are
+    compared by magnitude in (mantissa, exponent) form, and every B of the job
+    is taken as B 2^E, E = -(the exponent of the chosen start's B), so that
+    the start's B lies in [1/2, 1); the integral is unscaled by 2^-E.  The
+    scaling is exact wherever the unscaled value is a normal double;
   * samples: |R| = min(r_{b-1} n + n r_{b+1}, 1024), uniform over the superblock,
     drawn from SplitMix64 keyed by (seed, sweep, bond, sample);
   * rook budget: at most 5 (column, row) pairs;
@@ -61,11 +70,13 @@ import numpy as np
 
 from . import rng
 from .gauss import gauss_legendre_01
-from .integrands import n_modes, weighted_values
+from .integrands import PAPER_FORM, log2_weighted_values, n_modes, weighted_values
 
 T_ROOK = 5
 MAX_SAMPLES = 1024
 N_START = 1024
+SCALED_START_MODES = 32   # above this many modes: constant start candidates and the scale 2^E
+DBL_MIN = 2.0 ** -1022
 
 
 def weight_shift(n):
@@ -123,7 +134,8 @@ class TTCross:
     """Alg. 6 (one superblock per process) over the weighted tensor B."""
 
     def __init__(self, family, d, n, rank_cap, tol, seed, max_sweeps=0, params=None,
-                 t_rook=T_ROOK, max_samples=MAX_SAMPLES, n_start=N_START, scale_weights=True):
+                 t_rook=T_ROOK, max_samples=MAX_SAMPLES, n_start=N_START, scale_weights=True,
+                 value_scale=True):
         self.family, self.d, self.n = family, d, n
         self.wshift = weight_shift(n) if scale_weights else 0
         self.rank_cap, self.tol, self.seed = rank_cap, tol, seed
@@ -136,6 +148,8 @@ class TTCross:
         self.left = [[] for _ in range(nb)]    # left[b]:  I_<=b, tuples (i_0..i_b)
         self.right = [[] for _ in range(nb)]   # right[b]: I_>b,  tuples (i_b+1..i_m-1)
         self.scale = [0.0] * nb
+        self.escale = 0         # E: every B of the job is taken times 2^E (above 32 modes)
+        self.value_scale = value_scale   # False keeps E = 0 (the candidates stay the same)
         self.sweeps = 0
         self.evals = 0
         self.history = []       # integral after the start and after every sweep
@@ -152,9 +166,34 @@ class TTCross:
         return t, np.ldexp(w, self.wshift)
 
     def B(self, idx):
+        """B at the multi-indices idx, times 2^E."""
         idx = np.asarray(idx, dtype=np.int64)
         idx = idx.reshape(-1, self.m) if self.m > 0 else idx.reshape(idx.shape[0], 0)
-        return weighted_values(self.family, idx, self.t, self.w, self.params)
+        vals = weighted_values(self.family, idx, self.t, self.w, self.params)
+        if self.escale == 0:
+            return vals
+        out = np.ldexp(vals, self.escale)
+        low = np.abs(vals) < DBL_MIN   # zero or subnormal before scaling: take it through logarithms
+        if low.any():
+            if self.family not in PAPER_FORM:
+                raise FloatingPointError("values below the double range outside the paper form")
+            out[low] = np.exp2(log2_weighted_values(self.family, idx[low], self.t, self.w) + self.escale)
+        return out
+
+    def magnitudes(self, idx):
+        """Unscaled |B| at idx as (mantissa in [1/2, 1), exponent) arrays; mantissa 0 for B = 0."""
+        idx = np.asarray(idx, dtype=np.int64).reshape(-1, self.m)
+        vals = weighted_values(self.family, idx, self.t, self.w, self.params)
+        if not np.isfinite(vals).all():
+            raise FloatingPointError("non-finite start sample")
+        mant, ex = np.frexp(np.abs(vals))
+        low = np.abs(vals) < DBL_MIN
+        if low.any() and self.family in PAPER_FORM:
+            l2 = log2_weighted_values(self.family, idx[low], self.t, self.w)
+            e = np.floor(l2).astype(np.int64) + 1
+            mant[low] = np.exp2(l2 - e)
+            ex[low] = e
+        return mant, ex.astype(np.int64)
 
     def left_set(self, b):
         return [()] if b < 0 else self.left[b]
@@ -186,19 +225,33 @@ class TTCross:
         for q in range(self.n_start):
             for k in range(m):
                 idx[q, k] = rng.uniform_index(rng.value(self.seed, rng.start_counter(q, k)), n)
-        vals = self.B(idx)
-        self.evals += self.n_start
-        if not np.isfinite(vals).all():
-            raise FloatingPointError("non-finite start sample")
-        q = int(np.argmax(np.abs(vals)))
-        if vals[q] == 0.0:
-            raise FloatingPointError("all start samples are zero")
+        if m > SCALED_START_MODES:
+            if self.family in ("ising_d", "ising_e"):
+                idx = np.vstack([idx, np.repeat(np.arange(n, dtype=np.int64)[:, None], m, axis=1)])
+            mant, ex = self.magnitudes(idx)
+            self.evals += len(idx)
+            if not (mant > 0).any():
+                raise FloatingPointError("all start samples are zero")
+            etop = int(ex[mant > 0].max())
+            keys = np.where(mant > 0, np.ldexp(mant, ex - etop), 0.0)
+            q = int(np.argmax(keys))   # ties: the lowest candidate index
+            self.escale = -etop if self.value_scale else 0
+            start_value = math.ldexp(float(keys[q]), etop + self.escale)
+        else:
+            vals = self.B(idx)
+            self.evals += self.n_start
+            if not np.isfinite(vals).all():
+                raise FloatingPointError("non-finite start sample")
+            q = int(np.argmax(np.abs(vals)))
+            if vals[q] == 0.0:
+                raise FloatingPointError("all start samples are zero")
+            start_value = abs(float(vals[q]))
         i0 = tuple(int(v) for v in idx[q])
         self.start_index = i0
         for b in range(m - 1):
             self.left[b].append(i0[:b + 1])
             self.right[b].append(i0[b + 1:])
-            self.scale[b] = abs(float(vals[q]))
+            self.scale[b] = start_value
         self._count_new_core_entries()
         self._record(self.integral_scaled())
 
@@ -243,7 +296,7 @@ class TTCross:
                 v = np.linalg.solve(M.T, v.T).T                      # v [M]^-1
                 v, e = renormalise(v @ self.core(c).sum(axis=1), e)  # r_{c-1} x r_c
         mant, k = math.frexp(float(v[0, 0]))
-        return mant, e + k - self.wshift * self.m
+        return mant, e + k - self.wshift * self.m - self.escale
 
     def integral(self):
         return scaled_ldexp(*self.integral_scaled())

@@ -267,6 +267,7 @@ struct FamilyArgs {
   double four_over_mfact;    // u-form prefactor 4/m!
   const double* a;           // synthetic parameters (device)
   const double* b;
+  int escale = 0;            // streaming integrands return f times 2^escale
 };
 
 template <int MAXM>
@@ -293,10 +294,22 @@ __device__ __forceinline__ double integrand(const FamilyArgs& fa, const double (
 // A_d over the runs y_a..y_b by their first index a; a run is left as soon as
 // its product p falls below 2^-54, since from there on p only decreases and
 // pn (1 - p), pd (1 + p) round back to pn and pd (the FMA's exact product is
-// below half an ulp), so stopping changes no bit.  pn and pd are brought back
-// by the same exact power of two every 32 factors and after every run.
+// below half an ulp), so stopping changes no bit.  pn and pd are each brought
+// back near 1 by an exact power of two every 32 factors and after every run, and
+// the difference x of the two exponents taken out is kept: the value is
+// (2 (pn/pd)^2 / den) 2^(2x), returned as that mantissa with *ex = 2x.  Far
+// below the double range (D_d near 10^(-0.7 d), Sec. 5.5) the mantissa stays
+// exact; where nothing leaves the range the result equals the one-scale
+// evaluation bit for bit, since every scaling is by a power of two.
+__device__ __forceinline__ void pair_renorm(double& pn, double& pd, int& x) {
+  const int en = ilogb(pn), ed = ilogb(pd);
+  pn = ldexp(pn, -en);
+  pd = ldexp(pd, -ed);
+  x += en - ed;
+}
+
 template <class Y>
-__device__ __forceinline__ double ising_paper_stream(int family, int m, const Y& y) {
+__device__ __forceinline__ double ising_paper_stream_me(int family, int m, const Y& y, int* ex) {
   double den = 1.0;
   if (family != TT_ISING_E) {
     double P = 1.0, q = 0.0, s = 0.0;
@@ -309,6 +322,7 @@ __device__ __forceinline__ double ising_paper_stream(int family, int m, const Y&
     den = (1.0 + q) * (1.0 + s);
   }
   double nm = 2.0;
+  int x = 0;
   if (family != TT_ISING_C) {
     double pn = 1.0, pd = 1.0;
     for (int a = 0; a < m; ++a) {
@@ -318,20 +332,22 @@ __device__ __forceinline__ double ising_paper_stream(int family, int m, const Y&
         if (p < 0x1.0p-54) break;
         pn = fma(-pn, p, pn);
         pd = fma(pd, p, pd);
-        if (((b - a) & 31) == 31) {
-          const int e = ilogb(pd);
-          pn = ldexp(pn, -e);
-          pd = ldexp(pd, -e);
-        }
+        if (((b - a) & 31) == 31) pair_renorm(pn, pd, x);
       }
-      const int e = ilogb(pd);
-      pn = ldexp(pn, -e);
-      pd = ldexp(pd, -e);
+      pair_renorm(pn, pd, x);
     }
     const double r = pn / pd;
     nm = nm * r * r;
   }
+  *ex = 2 * x;
   return nm / den;
+}
+
+template <class Y>
+__device__ __forceinline__ double ising_paper_stream(int family, int m, const Y& y, int escale) {
+  int ex;
+  const double v = ising_paper_stream_me(family, m, y, &ex);
+  return ldexp(v, ex + escale);
 }
 
 template <class Y>
@@ -374,17 +390,14 @@ __device__ __forceinline__ void seg_each(const Segs& s, F&& f) {
 // the factors after the first such p leave pn and pd unchanged (see above).
 struct PairRun {
   double pn, pd, p;
+  int x;   // pn / pd is the pair product times 2^-x (see ising_paper_stream_me)
   __device__ __forceinline__ void step(double y) {
     p = p * y;
     pn = fma(-pn, p, pn);
     pd = fma(pd, p, pd);
   }
   __device__ __forceinline__ bool done() const { return p < 0x1.0p-54; }
-  __device__ __forceinline__ void renorm() {
-    const int e = ilogb(pd);
-    pn = ldexp(pn, -e);
-    pd = ldexp(pd, -e);
-  }
+  __device__ __forceinline__ void renorm() { pair_renorm(pn, pd, x); }
   // factors ptr[k0..k1); returns true once the run is over
   __device__ __forceinline__ bool span(const double* __restrict__ ptr, int k0, int k1) {
     int k = k0;
@@ -436,7 +449,7 @@ struct PrefixSuffix {
   }
 };
 
-__device__ __forceinline__ double ising_paper_seg(int family, const Segs& s) {
+__device__ __forceinline__ double ising_paper_seg(int family, const Segs& s, int escale) {
   const int m = s.m;
   double den = 1.0;
   if (family != TT_ISING_E) {
@@ -448,8 +461,9 @@ __device__ __forceinline__ double ising_paper_seg(int family, const Segs& s) {
     den = (1.0 + ps.q) * (1.0 + ps.s);
   }
   double nm = 2.0;
+  int ex = 0;
   if (family != TT_ISING_C) {
-    PairRun run{1.0, 1.0, 1.0};
+    PairRun run{1.0, 1.0, 1.0, 0};
     const int mid = s.nL, right = s.nL + s.nM;
     for (int a = 0; a < m; ++a) {
       run.p = 1.0;
@@ -468,8 +482,9 @@ __device__ __forceinline__ double ising_paper_seg(int family, const Segs& s) {
     }
     const double r = run.pn / run.pd;
     nm = nm * r * r;
+    ex = 2 * run.x;
   }
-  return nm / den;
+  return ldexp(nm / den, ex + escale);
 }
 
 __device__ __forceinline__ double synthetic_seg(int family, const Segs& s, const double* __restrict__ a,

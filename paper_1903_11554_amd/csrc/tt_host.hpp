@@ -246,6 +246,8 @@ inline void fill_info(const ProbState& s, tt_info* out) {
   out->value_mant = s.value;
   out->value_exp2 = s.vexp;
   out->recomputes = s.recomputes;
+  out->value_scale = s.escale;
+  out->reserved = 0;
 }
 
 // Node tables for n, generated on first use (defined in ttcross.hip).  With

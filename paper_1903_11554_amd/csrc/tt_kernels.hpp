@@ -40,6 +40,7 @@ static_assert(sizeof(PivRec) == sizeof(tt_pivot), "PivRec must mirror tt_pivot")
 struct ProbState {
   int32_t sweeps, done, reason, err_flags;
   int32_t nacc, max_rank, vexp, recomputes;   // recomputes: interpolation cores rebuilt from F_c
+  int32_t escale, pad0;                       // streaming path: every B is f W 2^escale
   unsigned long long evals;
   double value, rel, value_lo;
 };
@@ -102,6 +103,7 @@ __device__ __forceinline__ void signal_done(const ProbDesc& p) {
     dst->max_rank = src->max_rank;
     dst->vexp = src->vexp;
     dst->recomputes = src->recomputes;
+    dst->escale = src->escale;
     dst->evals = src->evals;
     dst->value = src->value;
     dst->rel = src->rel;
@@ -140,17 +142,21 @@ __device__ __forceinline__ T integrand_fam(const FamilyArgs& fa, const T (&y)[MA
 }
 
 // Streaming path (MAXM = 0, any number of modes, double precision): the
-// paper-form and synthetic integrands over an accessor y(k).
+// paper-form and synthetic integrands over an accessor y(k), as f 2^escale.
+// integrand_stream_me returns a mantissa and its exponent (f = v 2^ex) for the
+// start, which fixes escale.
 template <int FAM, class Y>
-__device__ __forceinline__ double integrand_stream(const FamilyArgs& fa, const Y& y) {
+__device__ __forceinline__ double integrand_stream_me(const FamilyArgs& fa, const Y& y, int* ex) {
   static_assert(FAM == FAM_PAPER || FAM == FAM_SYNTH || FAM == FAM_ANY, "no streaming u-form");
   if constexpr (FAM == FAM_PAPER) {
-    return ising_paper_stream(fa.family, fa.m, y);
+    return ising_paper_stream_me(fa.family, fa.m, y, ex);
   } else if constexpr (FAM == FAM_SYNTH) {
+    *ex = 0;
     return synthetic_stream(fa.family, fa.m, y, fa.a, fa.b);
   } else {
     if (fa.family == TT_ISING_C || fa.family == TT_ISING_D || fa.family == TT_ISING_E)
-      return ising_paper_stream(fa.family, fa.m, y);
+      return ising_paper_stream_me(fa.family, fa.m, y, ex);
+    *ex = 0;
     return synthetic_stream(fa.family, fa.m, y, fa.a, fa.b);
   }
 }
@@ -159,13 +165,13 @@ template <int FAM>
 __device__ __forceinline__ double integrand_seg(const FamilyArgs& fa, const Segs& sg) {
   static_assert(FAM == FAM_PAPER || FAM == FAM_SYNTH || FAM == FAM_ANY, "no streaming u-form");
   if constexpr (FAM == FAM_PAPER) {
-    return ising_paper_seg(fa.family, sg);
+    return ising_paper_seg(fa.family, sg, fa.escale);
   } else if constexpr (FAM == FAM_SYNTH) {
-    return synthetic_seg(fa.family, sg, fa.a, fa.b);
+    return ldexp(synthetic_seg(fa.family, sg, fa.a, fa.b), fa.escale);
   } else {
     if (fa.family == TT_ISING_C || fa.family == TT_ISING_D || fa.family == TT_ISING_E)
-      return ising_paper_seg(fa.family, sg);
-    return synthetic_seg(fa.family, sg, fa.a, fa.b);
+      return ising_paper_seg(fa.family, sg, fa.escale);
+    return ldexp(synthetic_seg(fa.family, sg, fa.a, fa.b), fa.escale);
   }
 }
 
@@ -187,7 +193,7 @@ __device__ __forceinline__ int rowcap(const ProbDesc& p, int c) { return c == 0 
 __device__ __forceinline__ int colcap(const ProbDesc& p, int c) { return c == p.m - 1 ? 1 : p.R; }
 
 __device__ __forceinline__ FamilyArgs family_args(const ProbDesc& p) {
-  return FamilyArgs{p.family, p.m, p.four_over_mfact, p.pa, p.pb};
+  return FamilyArgs{p.family, p.m, p.four_over_mfact, p.pa, p.pb, p.st->escale};
 }
 
 // ------------------------------------------------------------------ GL rule
@@ -263,13 +269,15 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   constexpr bool kStream = MAXM == 0;   // coordinates one at a time, any number of modes
   const ProbDesc p = P[blockIdx.x];
   const int m = p.m, n = p.n, tid = threadIdx.x;
-  const FamilyArgs fa = family_args(p);
+  const FamilyArgs fa{p.family, p.m, p.four_over_mfact, p.pa, p.pb};   // unscaled: the start fixes the scale
   const T* __restrict__ tt = tp<T>(p.t);
   const T* __restrict__ ww = tp<T>(p.w);
   __shared__ double sv[kBlock / kWave + 1];
   __shared__ int si[kBlock / kWave + 1];
   __shared__ int s_i0[kStream ? TT_MAX_MODES : MAXM];
   __shared__ T s_buf[TT_MAX_NODES];
+  __shared__ double s_cm[kStream ? kStart + TT_MAX_NODES : 1];   // streaming start candidates: mantissa
+  __shared__ int s_ce[kStream ? kStart + TT_MAX_NODES : 1];      // and exponent
   ProbState* st = p.st;
 
   if constexpr (!kStream) if (m <= 1) {   // no bond: the tensor is a vector (or a scalar for m = 0)
@@ -305,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
       st->done = 1;
       st->err_flags = isfinite(n_hi(val)) ? 0 : 1;
       st->recomputes = 0;
+      st->escale = 0;
       st->reason = st->err_flags ? TT_STOP_ERROR : TT_STOP_CONVERGED;
       st->evals = (m == 1) ? (unsigned long long)n : 0ull;
       st->max_rank = 1;
@@ -315,17 +324,57 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
 
   ArgMax best{-1.0, 0x7fffffff};
   bool bad = false;
-  for (int q = tid; q < kStart; q += blockDim.x) {
-    double v;
-    if constexpr (kStream) {
+  int escale = 0;
+  if constexpr (kStream) {
+    // More than 32 modes: the candidates are the kStart random multi-indices and,
+    // for D_d and E_d, the n constant ones (every mode at node q - kStart).  A
+    // random point's B falls far below the double range for D_d from about
+    // d = 128 on, while the constant points reach the largest entries (C_d and
+    // the synthetic families stay near 1 and keep the random candidates only).
+    // Each candidate is formed as a mantissa and an exponent (the weight product
+    // renormalised every 16 factors, the integrand by ising_paper_stream_me),
+    // compared at the largest exponent, and escale = -(that exponent) brings the
+    // chosen start's B into [1/2, 1).  Every later B of the job is f W 2^escale.
+    const int ncand = kStart + (p.family == TT_ISING_D || p.family == TT_ISING_E ? n : 0);
+    constexpr int kOff = 1 << 24;   // exponents offset to positive keys; zero values get no key
+    ArgMax emax{-1.0, 0x7fffffff};
+    for (int q = tid; q < ncand; q += blockDim.x) {
       auto node = [&](int k) {
-        return (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n);
+        return q < kStart ? (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n)
+                          : q - kStart;
       };
-      T W = num<T>(1.0);
-      for (int k = 0; k < m; ++k) W = n_mul(W, ww[node(k)]);
-      v = n_hi(n_mul(W, integrand_stream<FAM>(fa, [&](int k) { return tt[node(k)]; })));
-    } else {
-      T y[kStream ? 1 : MAXM];
+      double Wm = 1.0;
+      int We = 0;
+      for (int k = 0; k < m; ++k) {
+        Wm = Wm * n_hi(ww[node(k)]);
+        if ((k & 15) == 15) {
+          int e;
+          Wm = frexp(Wm, &e);
+          We += e;
+        }
+      }
+      int fe;
+      const double fv = integrand_stream_me<FAM>(fa, [&](int k) { return n_hi(tt[node(k)]); }, &fe);
+      int e;
+      const double mant = frexp(Wm * fv, &e);
+      if (!isfinite(mant)) bad = true;
+      s_cm[q] = mant;
+      s_ce[q] = e + We + fe;
+      if (mant != 0.0 && isfinite(mant) && better((double)(s_ce[q] + kOff), q, emax.v, emax.idx)) {
+        emax.v = (double)(s_ce[q] + kOff);
+        emax.idx = q;
+      }
+    }
+    emax = block_argmax(emax, sv, si);   // its barriers also publish s_cm, s_ce
+    const int etop = emax.v > 0.0 ? (int)emax.v - kOff : 0;
+    escale = -etop;
+    for (int q = tid; q < ncand; q += blockDim.x) {
+      const double v = s_cm[q] != 0.0 && isfinite(s_cm[q]) ? ldexp(fabs(s_cm[q]), s_ce[q] - etop) : 0.0;
+      if (better(v, q, best.v, best.idx)) { best.v = v; best.idx = q; }
+    }
+  } else {
+    for (int q = tid; q < kStart; q += blockDim.x) {
+      T y[MAXM];
       T W = num<T>(1.0);
 #pragma unroll
       for (int k = 0; k < MAXM; ++k) {
@@ -337,21 +386,22 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
           y[k] = num<T>(0.0);
         }
       }
-      v = n_hi(n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y)));
+      const double v = n_hi(n_mul(W, integrand_fam<T, FAM, MAXM>(fa, y)));
+      if (!isfinite(v)) bad = true;
+      if (better(fabs(v), q, best.v, best.idx)) { best.v = fabs(v); best.idx = q; }
     }
-    if (!isfinite(v)) bad = true;
-    if (better(fabs(v), q, best.v, best.idx)) { best.v = fabs(v); best.idx = q; }
   }
   best = block_argmax(best, sv, si);
   int any_bad = __syncthreads_or(bad);
   const int q = best.idx;
   for (int k = tid; k < m; k += blockDim.x)
-    s_i0[k] = (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n);
+    s_i0[k] = q < kStart ? (int)uniform_below(splitmix_at(p.seed, start_counter(q, k)), (uint32_t)n) : q - kStart;
   __syncthreads();
   if (any_bad || !(best.v > 0.0)) {
     if (tid == 0) {
       st->err_flags = any_bad ? 1 : 4;
       st->recomputes = 0;
+      st->escale = 0;
       st->done = 1;
       st->reason = TT_STOP_ERROR;
       st->evals = kStart;
@@ -404,7 +454,8 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
     st->reason = TT_RUNNING;
     st->err_flags = 0;
     st->recomputes = 0;
-    st->evals = kStart;
+    st->escale = escale;
+    st->evals = kStream && (p.family == TT_ISING_D || p.family == TT_ISING_E) ? kStart + n : kStart;
     st->max_rank = 1;
     st->rel = __builtin_huge_val();
   }
@@ -469,9 +520,10 @@ __device__ __forceinline__ void row_summaries(const double* __restrict__ Lrows, 
 }
 
 // C_d at a point from its left row's summary, one or two nodes and its right
-// row's summary (from zero): the value 2 / ((1 + q)(1 + s)) of B_d's sums.
+// row's summary (from zero): the value 2 / ((1 + q)(1 + s)) of B_d's sums, times
+// 2^escale.
 __device__ __forceinline__ double ising_c_joined(const double* sL, int al, double t0, double t1, int nM,
-                                                 const double* sR, int be) {
+                                                 const double* sR, int be, int escale) {
   PrefixSuffix ps;
   ps.P = sL[al];
   ps.q = sL[TT_MAX_RANK + al];
@@ -480,7 +532,7 @@ __device__ __forceinline__ double ising_c_joined(const double* sL, int al, doubl
   if (nM > 1) ps.one(t1);
   const double q = fma(ps.P, sR[TT_MAX_RANK + be], ps.q);
   const double sfx = fma(sR[be], ps.s, sR[2 * TT_MAX_RANK + be]);
-  return 2.0 / ((1.0 + q) * (1.0 + sfx));
+  return ldexp(2.0 / ((1.0 + q) * (1.0 + sfx)), escale);
 }
 
 // One step of Alg. 2 on superblock b.  The random samples, every column step and
@@ -597,7 +649,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
       T a;
       if constexpr (kStream) {
         if (rowsum) {
-          a = n_mul(W, ising_c_joined(sm.sL, al, sm.t[i], sm.t[j], 2, sm.sR, be));
+          a = n_mul(W, ising_c_joined(sm.sL, al, sm.t[i], sm.t[j], 2, sm.sR, be, fa.escale));
         } else {
           const T* Lrow = gLx + ((size_t)(b > 0 ? b - 1 : 0) * R + al) * m;
           const T* Rrow = gRx + ((size_t)(b + 1 <= m - 2 ? b + 1 : 0) * R + be) * m;
@@ -994,7 +1046,7 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     T v;
     if constexpr (kStream) {
       if (rowsum) {
-        v = n_mul(W, ising_c_joined(sm.sL, al, sm.t[i], 0.0, 1, sm.sR, be));
+        v = n_mul(W, ising_c_joined(sm.sL, al, sm.t[i], 0.0, 1, sm.sR, be, fa.escale));
       } else {
         const T* Lrow = gLx + ((size_t)(c > 0 ? c - 1 : 0) * R + al) * m;
         const T* Rrow = gRx + ((size_t)(c <= m - 2 ? c : 0) * R + be) * m;
@@ -1433,7 +1485,7 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
   // the integral as mantissa * 2^exponent; the folded weights carried 2^wshift per mode
   int e;
   const T value = normalise(v[0], e);
-  const int vx = vexp + e - p.wshift * m;
+  const int vx = vexp + e - p.wshift * m - st->escale;
   st->max_rank = maxr;
   if (!isfinite(n_hi(value))) st->err_flags |= 1;
   if (init) {

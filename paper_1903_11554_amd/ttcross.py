@@ -50,7 +50,8 @@ class _Info(ctypes.Structure):
                 ("evals", ctypes.c_int64), ("value", ctypes.c_double),
                 ("rel_change", ctypes.c_double), ("value_lo", ctypes.c_double),
                 ("value_mant", ctypes.c_double), ("value_exp2", ctypes.c_int32),
-                ("recomputes", ctypes.c_int32)]
+                ("recomputes", ctypes.c_int32), ("value_scale", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -298,7 +299,7 @@ class Job:
         return [dict(sweeps=i.sweeps, max_rank=i.max_rank, reason=STOP_REASONS.get(i.reason, i.reason),
                      err_flags=i.err_flags, evals=i.evals, value=i.value, rel_change=i.rel_change,
                      value_lo=i.value_lo, value_mant=i.value_mant, value_exp2=i.value_exp2,
-                     recomputes=i.recomputes)
+                     recomputes=i.recomputes, value_scale=i.value_scale)
                 for i in infos]
 
     def _checked_infos(self, status, infos, what):

@@ -11,9 +11,14 @@ device memory one at a time.  Checked here:
     the limit 2 exp(-2 gamma) (Sec. 5.3), which C_1024 equals far below the
     double rounding level (the gap is below 4e-19 already at d = 64, by the
     one-dimensional Bessel-moment form of C_d);
-  * D_64 and D_128 against the values the paper prints (Sec. 5.5), which it
-    computed in quadruple precision with 129 nodes.
+  * D_64 .. D_1024 against the values the paper prints (Sec. 5.5), which it
+    computed in quadruple precision with 129 nodes (65 for D_512 and D_1024),
+    and the constant Delta of eq. (Delta) from D_128 and D_256;
+  * the start above 32 modes (constant candidates for D_d and E_d, values in
+    mantissa-exponent form, B scaled by 2^E) against the oracle's.
 """
+from fractions import Fraction
+from decimal import Decimal
 import math
 import os
 
@@ -159,29 +164,63 @@ def test_c1024_double_precision():
     job.free()
 
 
-def printed(d):
+def printed_exact(d):
+    """The printed D_d as an exact rational (D_512 and D_1024 lie below the double range)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ising_printed.txt")
     for line in open(path):
         if line.strip() and not line.startswith("#"):
             k, v = line.split()
             if int(k) == d:
-                return float(v)
+                return Fraction(Decimal(v))
     raise KeyError(d)
 
 
-@pytest.mark.parametrize("d,rank,tol,bound", [(64, 16, 1e-9, 1e-8), (128, 12, 1e-8, 1e-6)])
-def test_d_large_against_printed_values(d, rank, tol, bound):
-    # double precision with 33 nodes against the paper's 30-digit quadruple-precision values
+def printed(d):
+    return float(printed_exact(d))
+
+
+def exact_value(info):
+    """The job's integral value_mant 2^value_exp2 as an exact rational."""
+    return Fraction(info["value_mant"]) * Fraction(2) ** info["value_exp2"]
+
+
+def run_d(d, rank, tol):
     p = Problem("ising_d", d, 33, rank, tol, seed=d)
     print(f"D_{d} {p}", flush=True)
     ctx = gpu_context()
     job = ctx.job([p])
     info = job.run()[0]
-    rel = abs(info["value"] / printed(d) - 1)
-    print(f"D_{d} = {info['value']!r} rel err {rel:.2e} sweeps {info['sweeps']} rank {info['max_rank']}", flush=True)
-    assert info["err_flags"] == 0 and info["reason"] == "converged"
-    assert rel < bound
     job.free()
+    rel = abs(float(exact_value(info) / printed_exact(d) - 1))
+    print(f"D_{d} = {info['value_mant']!r} * 2^{info['value_exp2']} (scale 2^{info['value_scale']}) rel err "
+          f"{rel:.2e} sweeps {info['sweeps']} rank {info['max_rank']}", flush=True)
+    assert info["err_flags"] == 0 and info["reason"] == "converged"
+    return exact_value(info), rel
+
+
+@pytest.mark.parametrize("d,rank,tol,bound", [(64, 16, 1e-9, 1e-8), (128, 24, 1e-11, 1e-11),
+                                              (256, 24, 1e-11, 1e-11), (512, 16, 1e-10, 1e-8),
+                                              (1024, 16, 1e-10, 3e-8)])
+def test_d_large_against_printed_values(d, rank, tol, bound):
+    # double precision with 33 nodes against the paper's quadruple-precision values;
+    # D_512 and D_1024 lie below the double range and are compared as mantissa 2^exponent
+    _, rel = run_d(d, rank, tol)
+    assert rel < bound
+
+
+def test_delta_from_d128_and_d256():
+    # Sec. 5.5, eq. (Delta): D_d ~ Delta^-d, estimated from D_128 and D_256 as
+    # Delta = (D_128 / D_256)^(1/128).  With each value within 1e-11 of the printed
+    # one, Delta's relative error is at most about 2e-11 / 128.
+    v128, _ = run_d(128, 24, 1e-11)
+    v256, _ = run_d(256, 24, 1e-11)
+    from mpmath import mp, mpf
+    with mp.workprec(200):
+        delta = (mpf(v128.numerator) / v128.denominator / (mpf(v256.numerator) / v256.denominator)) ** (mpf(1) / 128)
+        want = mpf("5.0792202086636783360436879567820")
+        rel = float(abs(delta / want - 1))
+    print(f"Delta = {mp.nstr(delta, 20)} rel err {rel:.2e}", flush=True)
+    assert rel < 2e-13
 
 
 def test_large_jobs_outside_the_streaming_path_are_rejected():
@@ -309,4 +348,30 @@ def test_recomputed_interpolation_cores_against_the_oracle(d, rank, tol):
     assert info["err_flags"] == 0 and info["recomputes"] > 0, info
     worst = check_cores_on_own_sets(job, p, 1e-9)
     print(f"  worst C M - F residual {worst:.2e}", flush=True)
+    job.free()
+
+
+@pytest.mark.parametrize("family,d,n,seed", [("ising_d", 129, 33, 129), ("ising_e", 97, 17, 97)])
+def test_scaled_start_matches_the_oracle(family, d, n, seed):
+    # above 32 modes D_d and E_d also try the constant multi-indices; at D_129 most
+    # random candidates lie below the double range, and the chosen start is compared
+    # in mantissa-exponent form.  The start index, the scale E and the rank-1
+    # integral after the start must be the oracle's.
+    p = Problem(family, d, n, 4, 1e-8, seed=seed)
+    print(f"scaled start {p}", flush=True)
+    ctx = gpu_context()
+    job = ctx.job([p])
+    _, infos = job.sweep(0)
+    info = infos[0]
+    left, right = job.index_sets(0)[0]
+    ref = oracle_tt.TTCross(family, d, n, 4, 1e-8, seed)
+    print(f"  gpu start {left[0][0]}.. scale {info['value_scale']}, oracle {ref.start_index[0]}.. "
+          f"scale {ref.escale}", flush=True)
+    assert left[0] + right[0] == ref.start_index
+    assert info["value_scale"] == ref.escale and ref.escale > 0
+    gm, ge = job.history_scaled(0)[0]
+    rm, re_ = ref.history_scaled[0]
+    got, want = Fraction(gm) * Fraction(2) ** ge, Fraction(rm) * Fraction(2) ** re_
+    assert abs(float(got / want - 1)) < 1e-12
+    assert info["evals"] == ref.evals
     job.free()
