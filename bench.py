@@ -139,9 +139,10 @@ def sweep_work(job, k, prob):
     return evals, flops, nbytes
 
 
-def workload():
+def workload(stop="strict"):
+    """The headline step: D_5..D_10 and C_4, stopped by the strict rule (no accepted pivot)."""
     from paper_1903_11554_amd.workloads import config_single_sweep
-    return config_single_sweep()
+    return config_single_sweep(stop=stop)
 
 
 def reference_values():
@@ -209,6 +210,7 @@ def run_gpu(args):
     stream = torch.cuda.current_stream()
     ctx = Context(0, stream=stream)
     probs = workload()
+    tune = ctx.autotune(probs, reps=5)   # kernel variant of the step, chosen before the warm-up
 
     def step():
         job = ctx.job(probs)
@@ -254,7 +256,7 @@ def run_gpu(args):
 
     if args.main_only:
         ctx.close()
-        return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
+        return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt, tune=tune,
                     s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=None,
                     errs={}, probs=probs, batch=None, dd=None, serving=None, mc=None, large=None,
                     n_ok=n_ok, n_checked=len(checks), single=None)
@@ -298,6 +300,8 @@ def run_gpu(args):
     fib_tflops = fib_flops / (ms / nl * 1e-3) / 1e12
 
     single = run_single(ctx, probs, refs)
+    rel2 = run_rel2(ctx, refs)
+    single["default_stop_rule"] = rel2
     batch = run_batch(ctx, refs)
     dd = run_dd(ctx)
     mcres = run_mc(ctx, infos, probs)
@@ -310,10 +314,35 @@ def run_gpu(args):
         if key in refs:
             errs[f"{p.family}_{p.d}"] = abs(inf["value"] / refs[key] - 1)
     ctx.close()
-    return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt,
+    return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt, tune=tune,
                 s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
                 errs=errs, probs=probs, batch=batch, dd=dd, serving=serving, mc=mcres, large=large,
                 n_ok=n_ok, n_checked=len(checks), single=single)
+
+
+def run_rel2(ctx, refs, reps=10):
+    """The headline step under the default stopping rule (two small relative changes)."""
+    import torch
+    probs = workload(stop="rel2")
+    times, ok, n = [], 0, 0
+    sweeps = 0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        job = ctx.job(probs)
+        infos = job.run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        job.free()
+        for p, inf in zip(probs, infos):
+            good, _ = check_result(p, inf, refs)
+            ok += int(good)
+            n += 1
+        sweeps = max(i["sweeps"] for i in infos)
+    times.sort()
+    return {"rule": "stop after two consecutive sweeps with relative change <= tol (TT_STOP_REL2)",
+            "ms_per_step_median": times[len(times) // 2] * 1e3, "sweeps": sweeps,
+            "integrals_per_s": ok / sum(times), "integrals_failed": n - ok, "integrals": n}
 
 
 def run_single(ctx, probs, refs, reps=10):
@@ -562,6 +591,7 @@ def run_batch(ctx, refs, reps=5):
     job = ctx.job(probs)
     job.run()
     job.free()
+    tune = ctx.autotune(probs, reps=3)   # the batch's kernel variant, kept by the context
     times, evals = [], 0
     for _ in range(reps):
         t = time.perf_counter()
@@ -602,7 +632,7 @@ def run_batch(ctx, refs, reps=5):
             "plain_ms_sum": alone * 1e3, "plain_integrals_per_s": n_ok / alone,
             "speedup_vs_plain": alone / t_batch,
             "sweep_launches": nl, "sweep_avg_launch_ms": ms / max(nl, 1),
-            "sweep_tflops": tf, "sweep_frac_fp64": tf / FP64_PEAK_TFLOPS}
+            "sweep_tflops": tf, "sweep_frac_fp64": tf / FP64_PEAK_TFLOPS, "autotune": tune}
 
 
 def cpu_baseline(probs, budget_s):
@@ -614,7 +644,8 @@ def cpu_baseline(probs, budget_s):
     with threadpool_limits(limits=1):
         for p in sorted(probs, key=lambda q: q.d):
             t = time.perf_counter()
-            tt = oracle_tt.solve(p.family, p.d, p.n, p.rank_cap, p.tol, p.seed, params=p.params)
+            tt = oracle_tt.solve(p.family, p.d, p.n, p.rank_cap, p.tol, p.seed, params=p.params,
+                                 stop_rule=p.stop)
             t_used += time.perf_counter() - t
             evals += tt.evals
             done.append(f"{p.family}_{p.d}")
@@ -631,10 +662,10 @@ def _cpu_solve(task):
     from threadpoolctl import threadpool_limits
 
     from oracle import ttcross as oracle_tt
-    family, d, n, rank, tol, seed, params = task
+    family, d, n, rank, tol, seed, params, stop = task
     with threadpool_limits(limits=1):
         t = time.perf_counter()
-        tt = oracle_tt.solve(family, d, n, rank, tol, seed, params=params)
+        tt = oracle_tt.solve(family, d, n, rank, tol, seed, params=params, stop_rule=stop)
         return tt.evals, time.perf_counter() - t
 
 
@@ -646,7 +677,7 @@ def cpu_baseline_all_cores(probs):
     import multiprocessing as mp_
     cores = max(1, min(len(os.sched_getaffinity(0)), 16))
     tasks = [probs[k % len(probs)] for k in range(max(cores, len(probs)))]
-    args = [(p.family, p.d, p.n, p.rank_cap, p.tol, p.seed, p.params) for p in tasks]
+    args = [(p.family, p.d, p.n, p.rank_cap, p.tol, p.seed, p.params, p.stop) for p in tasks]
     t = time.perf_counter()
     with mp_.get_context("fork").Pool(cores) as pool:
         res = pool.map(_cpu_solve, args, chunksize=1)
@@ -729,7 +760,8 @@ def main():
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "Ising D_5..D_10 + C_4, paper form, 64 GL nodes/mode, TT rank <= 32, "
-                               "tol 1e-10, one batched job per step",
+                               "tol 1e-10, strict stop (until a sweep accepts no pivot), one batched "
+                               "job per step",
                    "integrals_per_step": len(r["probs"]), "evals_per_step": r["total_evals"] / args.steps},
         "integrals_per_s": r["n_ok"] / r["elapsed"],
         "integrals_failed": r["n_checked"] - r["n_ok"],
@@ -738,6 +770,7 @@ def main():
         "kernel_ms_per_step": {"sweep": ms_s, "init_update": ms_u, "init_integral": r["kt"]["integral"][1],
                                "start": r["kt"]["start"][1], "gl": r["kt"]["gl"][1]},
         "sweeps": r["sweeps"],
+        "autotune": r["tune"],
         "single_integral": r["single"],
         "roofline": roof,
         "fibre_eval_saturated": fib,

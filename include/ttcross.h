@@ -103,7 +103,19 @@ typedef struct {
   int32_t max_sweeps;  /* 0 selects 4*rank_cap; at most 1024                              */
   uint64_t seed;       /* key of the SplitMix64 counter-based sample generator            */
   const double *params;/* synthetic families: 2*d doubles (a then b); NULL otherwise      */
+  int32_t stop_rule;   /* tt_stop_rule; 0 (TT_STOP_REL2) for the default                    */
+  int32_t reserved;    /* 0                                                               */
 } tt_problem;
+
+/* The stopping rule (the paper measures "internal convergence" without defining
+ * it, Sec. 5.2-5.5).  Both rules also stop on a sweep that accepts no pivot,
+ * when every bond is at rank_cap, and at max_sweeps.
+ *   TT_STOP_REL2:   converged after two consecutive sweeps whose relative change
+ *                   of the integral is <= tol;
+ *   TT_STOP_STRICT: that alone does not stop: the integral runs until a sweep
+ *                   accepts no pivot (no superblock error above tol * its largest
+ *                   |B|), every bond is at the cap, or max_sweeps. */
+typedef enum { TT_STOP_REL2 = 0, TT_STOP_STRICT = 1 } tt_stop_rule;
 
 /* Per-integral result and progress. value is the current TT quadrature. */
 typedef struct {
@@ -348,6 +360,41 @@ tt_status tt_server_poll(tt_server *server, uint64_t ticket, tt_info *info, doub
 tt_status tt_server_wait(tt_server *server, uint64_t ticket, tt_info *info, double *latency_s);
 tt_status tt_server_get_stats(tt_server *server, tt_server_stats *out);
 void tt_server_destroy(tt_server *server);
+
+/* Autotuning of the kernel variants a job launches (no passage of the paper
+ * defines these: they are launch shapes of this library, not part of the method).
+ * A job's kernels come in variants that compute the same values bit for bit:
+ *   mode_bucket  the number of modes the kernels are compiled for, at least the
+ *                job's largest m (TT_FP64 paper form: 4, 8, 10, 12, 16, 24, 32;
+ *                other classes and double-double: 8, 16, 32; 0 is the streaming
+ *                kernel, any number of modes, double precision, paper form and
+ *                synthetic classes);
+ *   rank_policy  0: each sweep's kernel is sized for the ranks reachable in that
+ *                sweep; 1: for the rank caps.
+ * Without tuning a job takes the smallest mode bucket and policy 0 (the rule).
+ * tt_autotune runs the given job once per candidate variant (`reps` times each,
+ * median wall time from tt_cross_init to the stopping rule), keeps only the
+ * variants whose results equal the rule's bit for bit (every value, sweep count
+ * and evaluation count), and records the fastest for the job's key (integrand
+ * class, precision, largest m, largest rank cap) in the context: later jobs with
+ * that key launch it.  If the environment variable TTCROSS_TUNE_CACHE names a
+ * file, the context loads it at tt_ctx_create and tt_autotune rewrites it with
+ * every key the context holds (text, one key per line).  tt_autotune must not run
+ * concurrently with other calls on the same context.  Errors: TT_EINVAL for an
+ * invalid problem set or reps < 1; the job's own errors (TT_ENUMERIC, ...) when
+ * the rule variant fails; TT_EDEVICE if the cache file cannot be written. */
+typedef struct {
+  int32_t mode_bucket;   /* chosen variant                                            */
+  int32_t rank_policy;
+  int32_t rule_mode_bucket;
+  int32_t candidates;    /* variants timed                                             */
+  int32_t matching;      /* of those, variants whose results equal the rule's          */
+  int32_t reserved;
+  double  rule_ms;       /* median time of the rule's variant                          */
+  double  tuned_ms;      /* median time of the chosen variant                          */
+} tt_tune_result;
+tt_status tt_autotune(tt_ctx *ctx, const tt_problem *problems, int32_t count, int32_t reps,
+                      tt_tune_result *out);
 
 /* Synchronise the context stream. */
 tt_status tt_ctx_synchronize(tt_ctx *ctx);

@@ -54,8 +54,11 @@ Readings of the paper where it is silent:
   * acceptance: |err*| > tol * scale_b, where scale_b is the largest |B| the
     bond has evaluated so far, r_b < rank_cap, and neither half of the pivot is
     already in its set;
-  * stopping: relative change of the integral <= tol on two consecutive sweeps,
-    or a sweep that accepts no pivot, or max_sweeps.
+  * stopping ("rel2"): relative change of the integral <= tol on two
+    consecutive sweeps, or a sweep that accepts no pivot, or max_sweeps;
+    "strict" drops the first condition: only a sweep that accepts no pivot
+    (every superblock error at most tol times its largest |B|), the rank cap on
+    every bond, or max_sweeps end the run.
 
 Pinned by: exact integrals of rank-1 and rank-2 synthetic functions (Thm. 2),
 interpolation on every evaluated fiber (Thm. 1), brute-force tensor quadrature
@@ -135,7 +138,7 @@ class TTCross:
 
     def __init__(self, family, d, n, rank_cap, tol, seed, max_sweeps=0, params=None,
                  t_rook=T_ROOK, max_samples=MAX_SAMPLES, n_start=N_START, scale_weights=True,
-                 value_scale=True):
+                 value_scale=True, stop_rule="rel2"):
         self.family, self.d, self.n = family, d, n
         self.wshift = weight_shift(n) if scale_weights else 0
         self.rank_cap, self.tol, self.seed = rank_cap, tol, seed
@@ -150,6 +153,9 @@ class TTCross:
         self.scale = [0.0] * nb
         self.escale = 0         # E: every B of the job is taken times 2^E (above 32 modes)
         self.value_scale = value_scale   # False keeps E = 0 (the candidates stay the same)
+        if stop_rule not in ("rel2", "strict"):
+            raise ValueError(stop_rule)
+        self.stop_rule = stop_rule
         self.sweeps = 0
         self.evals = 0
         self.history = []       # integral after the start and after every sweep
@@ -397,7 +403,7 @@ class TTCross:
         self._record(value)
         prev_rel = self.rel_changes[-1] if self.rel_changes else math.inf
         self.rel_changes.append(rel)
-        if rel <= self.tol and prev_rel <= self.tol:
+        if self.stop_rule == "rel2" and rel <= self.tol and prev_rel <= self.tol:
             self.stop_reason = "converged"
         elif nacc == 0:
             at_cap = all(len(self.left[b]) >= self.rank_cap for b in range(self.m - 1))
@@ -429,8 +435,8 @@ class TTCross:
         return out
 
 
-def solve(family, d, n, rank_cap, tol, seed, max_sweeps=0, params=None):
+def solve(family, d, n, rank_cap, tol, seed, max_sweeps=0, params=None, stop_rule="rel2"):
     """Run the oracle to its stopping rule and return the TTCross object."""
-    tt = TTCross(family, d, n, rank_cap, tol, seed, max_sweeps=max_sweeps, params=params)
+    tt = TTCross(family, d, n, rank_cap, tol, seed, max_sweeps=max_sweeps, params=params, stop_rule=stop_rule)
     tt.run()
     return tt

@@ -222,7 +222,7 @@ class TTCrossDD(TTCross):
         self._record(value)
         prev_rel = self.rel_changes[-1] if self.rel_changes else math.inf
         self.rel_changes.append(rel)
-        if rel <= self.tol and prev_rel <= self.tol:
+        if self.stop_rule == "rel2" and rel <= self.tol and prev_rel <= self.tol:
             self.stop_reason = "converged"
         elif nacc == 0:
             at_cap = all(len(self.left[b]) >= self.rank_cap for b in range(self.m - 1))

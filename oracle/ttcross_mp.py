@@ -188,9 +188,12 @@ class Record:
 class TTCrossMP:
     """Alg. 6 (one superblock per process) over the weighted tensor B, every value at `prec` bits."""
 
-    def __init__(self, family, d, n, rank_cap, tol, seed, max_sweeps=0, prec=PREC):
+    def __init__(self, family, d, n, rank_cap, tol, seed, max_sweeps=0, prec=PREC, stop_rule="rel2"):
         if family not in PAPER_FORM:
             raise ValueError(f"no multiple-precision path for {family}")
+        if stop_rule not in ("rel2", "strict"):
+            raise ValueError(stop_rule)
+        self.stop_rule = stop_rule
         self.family, self.d, self.n, self.prec = family, d, n, prec
         self.rank_cap, self.tol, self.seed = rank_cap, mp.mpf(tol), seed
         self.max_sweeps = max_sweeps if max_sweeps > 0 else 4 * rank_cap
@@ -385,7 +388,7 @@ class TTCrossMP:
             self.history.append(value)
             prev_rel = self.rel_changes[-1] if self.rel_changes else mp.inf
             self.rel_changes.append(rel)
-            if rel <= self.tol and prev_rel <= self.tol:
+            if self.stop_rule == "rel2" and rel <= self.tol and prev_rel <= self.tol:
                 self.stop_reason = "converged"
             elif nacc == 0:
                 at_cap = all(len(self.left[b]) >= self.rank_cap for b in range(self.m - 1))

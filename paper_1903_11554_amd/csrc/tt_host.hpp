@@ -7,10 +7,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "tt_kernels.hpp"
@@ -63,6 +65,16 @@ struct tt_ctx {
   size_t mc_cap = 0;
   double* scratch = nullptr;                       // this device's static scratch (tt_mc_integrate_noalloc)
   size_t arena_bytes_cached = 0;
+  // kernel variants chosen by tt_autotune, per (integrand class, double-double,
+  // largest m, largest rank cap): (mode bucket, rank policy, rule ms, tuned ms)
+  struct Tuned {
+    int mbucket, rank_policy;
+    double rule_ms, tuned_ms;
+  };
+  std::map<std::array<int, 4>, Tuned> tune;
+  std::string tune_path;                           // TTCROSS_TUNE_CACHE, or empty
+  bool force_variant = false;                      // tt_autotune's candidate for the next job
+  Tuned forced{0, 0, 0.0, 0.0};
 };
 
 // Arenas of freed jobs are kept by the context (up to this many bytes) and
@@ -145,6 +157,7 @@ inline tt_status validate(const tt_problem* p) {
   // beyond the register bucket only the streaming kernels (double, paper form and synthetic)
   if (m > TT_MAX_REG_MODES && (p->precision != TT_FP64 || fam_of(p->integrand) == FAM_UFORM)) return TT_EINVAL;
   if (p->max_sweeps < 0 || p->max_sweeps > 1024) return TT_EINVAL;
+  if ((p->stop_rule != TT_STOP_REL2 && p->stop_rule != TT_STOP_STRICT) || p->reserved != 0) return TT_EINVAL;
   if (is_synthetic(p->integrand) && !p->params) return TT_EINVAL;
   // the superblock size r n n r must fit a 32-bit sample index
   const double sb = (double)p->rank_cap * p->n_nodes * p->n_nodes * p->rank_cap;
@@ -223,6 +236,24 @@ inline int bucket_m_for(int fam, bool dd, int m) {
   return bucket_m(m);
 }
 inline int bucket_r(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : 64; }
+// Every mode bucket instantiated for a class and number type (tt_inst.hip), the
+// streaming bucket 0 last where it exists.
+inline std::vector<int> mode_buckets(int fam, bool dd) {
+  std::vector<int> b;
+  if (fam == FAM_PAPER && !dd) b = {4, 8, 10, 12, 16, 24, 32};
+  else b = {8, 16, 32};
+  if (!dd && fam != FAM_UFORM) b.push_back(0);
+  return b;
+}
+inline std::array<int, 4> tune_key(int fam, bool dd, int maxm, int maxR) { return {fam, dd ? 1 : 0, maxm, maxR}; }
+// A mode bucket a job of this class, precision and largest m can launch.
+inline bool variant_valid(int fam, bool dd, int maxm, int mb) {
+  if (mb == 0) return !dd && fam != FAM_UFORM;
+  if (maxm > TT_MAX_REG_MODES || mb < maxm) return false;
+  for (int b : mode_buckets(fam, dd))
+    if (b == mb) return true;
+  return false;
+}
 
 inline double four_over_fact(int m) {
   double f = 1.0;
@@ -317,6 +348,7 @@ inline ProbDesc make_desc(const tt_problem& p, const ProbOffsets& o, char* pb, c
   d.max_sweeps = max_sweeps_of(p);
   d.nbonds = d.m > 1 ? d.m - 1 : 0;
   d.wshift = weight_shift(p.n_nodes);
+  d.strict = p.stop_rule == TT_STOP_STRICT;
   d.tol = p.tol;
   d.four_over_mfact = four_over_fact(d.m);
   d.seed = p.seed;

@@ -47,7 +47,8 @@ struct ProbState {
 
 struct ProbDesc {
   int32_t family, m, n, R;
-  int32_t max_sweeps, nbonds, wshift, pad1;   // weights w are the rule's times 2^wshift
+  int32_t max_sweeps, nbonds, wshift;   // weights w are the rule's times 2^wshift
+  int32_t strict;                       // TT_STOP_STRICT: no stop on the relative change alone
   double tol, four_over_mfact;
   uint64_t seed;
   const double *t, *w;                   // T: nodes and weights
@@ -326,8 +327,9 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   bool bad = false;
   int escale = 0;
   if constexpr (kStream) {
-    // More than 32 modes: the candidates are the kStart random multi-indices and,
-    // for D_d and E_d, the n constant ones (every mode at node q - kStart).  A
+    // The streaming kernels: the candidates are the kStart random multi-indices
+    // and, for D_d and E_d above 32 modes, the n constant ones (every mode at
+    // node q - kStart).  A
     // random point's B falls far below the double range for D_d from about
     // d = 128 on, while the constant points reach the largest entries (C_d and
     // the synthetic families stay near 1 and keep the random candidates only).
@@ -335,7 +337,8 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
     // renormalised every 16 factors, the integrand by ising_paper_stream_me),
     // compared at the largest exponent, and escale = -(that exponent) brings the
     // chosen start's B into [1/2, 1).  Every later B of the job is f W 2^escale.
-    const int ncand = kStart + (p.family == TT_ISING_D || p.family == TT_ISING_E ? n : 0);
+    const bool consts = (p.family == TT_ISING_D || p.family == TT_ISING_E) && m > TT_MAX_REG_MODES;
+    const int ncand = kStart + (consts ? n : 0);
     constexpr int kOff = 1 << 24;   // exponents offset to positive keys; zero values get no key
     ArgMax emax{-1.0, 0x7fffffff};
     for (int q = tid; q < ncand; q += blockDim.x) {
@@ -455,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
     st->err_flags = 0;
     st->recomputes = 0;
     st->escale = escale;
-    st->evals = kStream && (p.family == TT_ISING_D || p.family == TT_ISING_E) ? kStart + n : kStart;
+    st->evals = kStart + ((p.family == TT_ISING_D || p.family == TT_ISING_E) && m > TT_MAX_REG_MODES ? n : 0);
     st->max_rank = 1;
     st->rel = __builtin_huge_val();
   }
@@ -1101,7 +1104,11 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   __syncthreads();   // the evaluation stage's LDS is reused below
   double cmax = 0.0;   // largest |entry| of C_c written below (double jobs)
   bool sing = false;   // a zero pivot in the incremental steps
-  if (init) {        // rank 1: M_c = (B(i0)), C_c = F_c / M_c
+  if (init == 2) {   // every entry re-evaluated on refreshed sets: C_c from F_c with a pivoted solve
+    if (tid < r) sm.rowidx[tid] = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
+    __syncthreads();
+    refresh_core<RMAX>(p, c, r, N, -1, r, Fc, cc, Cc, ldC, sm);
+  } else if (init) {   // rank 1: M_c = (B(i0)), C_c = F_c / M_c
     const int row0 = p.Lpar[(size_t)c * R] * n + p.Lnode[(size_t)c * R];
     const T m00 = Fc[(size_t)row0 * cc];
     if (tid == 0) {
@@ -1488,9 +1495,10 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
   const int vx = vexp + e - p.wshift * m - st->escale;
   st->max_rank = maxr;
   if (!isfinite(n_hi(value))) st->err_flags |= 1;
-  if (init) {
-    hist[0] = value;
-    p.hexp[0] = vx;
+  if (init) {   // 1: after the start; 2: after a refresh of the sets (replaces the current entry)
+    const int h = init == 2 ? sw0 : 0;
+    hist[h] = value;
+    p.hexp[h] = vx;
     st->value = n_hi(value);
     st->value_lo = n_lo(value);
     st->vexp = vx;
@@ -1509,7 +1517,7 @@ __device__ __forceinline__ void integral_problem(const ProbDesc& p, const int in
   st->rel = rel;
   st->nacc = nacc;
   int done = 0, reason = TT_RUNNING;
-  if (rel <= p.tol && prev_rel <= p.tol) {
+  if (!p.strict && rel <= p.tol && prev_rel <= p.tol) {
     done = 1;
     reason = TT_STOP_CONVERGED;
   } else if (nacc == 0) {

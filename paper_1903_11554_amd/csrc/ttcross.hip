@@ -4,12 +4,16 @@
 // method itself.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "tt_host.hpp"
@@ -34,6 +38,8 @@ struct tt_job {
   int fam = 3;            // integrand class the job's kernels are specialised for
   bool dd = false;        // double-double job
   bool full_bucket = false;   // sweeps were enqueued for graph capture: size kernels for the rank caps
+  int mbucket = 0;            // mode bucket of the job's kernels (the rule's, or a tuned one)
+  int rank_policy = 0;        // 1: every sweep kernel sized for the rank caps (tuned)
   std::vector<std::pair<double*, double*>> gl64;   // per integral: the double node tables
   int launched = 0;       // sweeps enqueued so far
   int max_sweeps_all = 0;
@@ -108,8 +114,7 @@ void pinned_give(tt_ctx* c, char* p, size_t bytes) {
 }
 
 void launch(tt_job* j, int what, int rb) {
-  LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, bucket_m_for(j->fam, j->dd, j->maxm),
-               j->ctx->stream};
+  LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, j->mbucket, j->ctx->stream};
   Timed tm(j->ctx, what == LAUNCH_SWEEP ? KK_SWEEP : what == LAUNCH_START ? KK_START : KK_UPDATE);
   if (j->dd) {
     launch_paper_dd(a, what, rb);
@@ -128,7 +133,8 @@ void enqueue_sweep(tt_job* j, int rb) { launch(j, LAUNCH_SWEEP, rb); }
 tt_status enqueue_sweeps(tt_job* j, int n_sweeps) {
   for (int s = 0; s < n_sweeps; ++s) {
     if (j->launched >= j->max_sweeps_all) break;
-    if (j->nbond > 0) enqueue_sweep(j, bucket_r(j->full_bucket ? j->maxR : std::min(j->maxR, j->launched + 2)));
+    const bool caps = j->full_bucket || j->rank_policy == 1;
+    if (j->nbond > 0) enqueue_sweep(j, bucket_r(caps ? j->maxR : std::min(j->maxR, j->launched + 2)));
     ++j->launched;
   }
   TT_HIP(hipGetLastError());
@@ -300,6 +306,40 @@ tt_status scratch_address(int device, double** out) {
 }
 }  // namespace
 
+// ---------------------------------------------------------------- autotuning
+// Cache file: one key per line, "class dd max_modes max_rank mode_bucket
+// rank_policy rule_ms tuned_ms"; lines starting with '#' are comments.  Entries
+// that name a variant the key cannot launch are ignored.
+static void tune_load(tt_ctx* c) {
+  FILE* f = std::fopen(c->tune_path.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    int fam, dd, maxm, maxR, mb, pol;
+    double rule_ms, tuned_ms;
+    if (std::sscanf(line, "%d %d %d %d %d %d %lf %lf", &fam, &dd, &maxm, &maxR, &mb, &pol, &rule_ms, &tuned_ms) != 8)
+      continue;
+    if (fam < FAM_PAPER || fam > FAM_ANY || (pol != 0 && pol != 1) || !variant_valid(fam, dd != 0, maxm, mb)) continue;
+    c->tune[tune_key(fam, dd != 0, maxm, maxR)] = tt_ctx::Tuned{mb, pol, rule_ms, tuned_ms};
+  }
+  std::fclose(f);
+}
+
+static tt_status tune_save(tt_ctx* c) {
+  if (c->tune_path.empty()) return TT_OK;
+  const std::string tmp = c->tune_path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return TT_EDEVICE;
+  std::fprintf(f, "# ttcross kernel variants: class dd max_modes max_rank mode_bucket rank_policy rule_ms tuned_ms\n");
+  for (const auto& e : c->tune)
+    std::fprintf(f, "%d %d %d %d %d %d %.6f %.6f\n", e.first[0], e.first[1], e.first[2], e.first[3],
+                 e.second.mbucket, e.second.rank_policy, e.second.rule_ms, e.second.tuned_ms);
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), c->tune_path.c_str()) != 0) return TT_EDEVICE;
+  return TT_OK;
+}
+
 extern "C" {
 
 const char* tt_status_string(tt_status s) {
@@ -337,6 +377,10 @@ tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
       return TT_EDEVICE;
     }
     c->own_stream = true;
+  }
+  if (const char* path = std::getenv("TTCROSS_TUNE_CACHE")) {
+    c->tune_path = path;
+    tune_load(c);
   }
   *out = c;
   return TT_OK;
@@ -387,6 +431,82 @@ tt_status tt_ctx_kernel_time(tt_ctx* c, int32_t kind, int64_t* launches, double*
   *launches = c->kernel_launches[kind];
   *total_ms = c->kernel_ms[kind];
   return TT_OK;
+}
+
+tt_status tt_autotune(tt_ctx* ctx, const tt_problem* problems, int32_t count, int32_t reps, tt_tune_result* out) {
+  if (!ctx || !problems || count < 1 || reps < 1 || !out) return TT_EINVAL;
+  int fam = FAM_ANY, maxm = 0, maxR = 1;
+  for (int k = 0; k < count; ++k) {
+    if (validate(&problems[k]) != TT_OK || problems[k].precision != problems[0].precision) return TT_EINVAL;
+    const int fk = fam_of(problems[k].integrand);
+    fam = (k == 0) ? fk : (fam == fk ? fk : FAM_ANY);
+    maxm = std::max(maxm, modes_of(problems[k]));
+    maxR = std::max(maxR, problems[k].rank_cap);
+  }
+  const bool dd = problems[0].precision == TT_DD;
+  const int rule_mb = bucket_m_for(fam, dd, maxm);
+  std::vector<std::pair<int, int>> cands{{rule_mb, 0}, {rule_mb, 1}};
+  for (int mb : mode_buckets(fam, dd))
+    if (mb != rule_mb && variant_valid(fam, dd, maxm, mb)) {
+      cands.push_back({mb, 0});
+      cands.push_back({mb, 1});
+    }
+  std::vector<tt_info> ref(count), got(count);
+  auto same = [&](const std::vector<tt_info>& a, const std::vector<tt_info>& b) {
+    for (int k = 0; k < count; ++k)
+      if (a[k].value_mant != b[k].value_mant || a[k].value_exp2 != b[k].value_exp2 || a[k].value_lo != b[k].value_lo ||
+          a[k].sweeps != b[k].sweeps || a[k].evals != b[k].evals || a[k].reason != b[k].reason)
+        return false;
+    return true;
+  };
+  double best_ms = 0.0, rule_ms = 0.0;
+  int best = -1, matching = 0;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    std::vector<double> ms;
+    bool match = true;
+    for (int r = 0; r < reps && match; ++r) {
+      ctx->forced = tt_ctx::Tuned{cands[c].first, cands[c].second, 0.0, 0.0};
+      ctx->force_variant = true;
+      if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        ctx->force_variant = false;
+        return TT_EDEVICE;
+      }
+      const auto t0 = std::chrono::steady_clock::now();
+      tt_job* j = nullptr;
+      tt_status s = tt_cross_init(ctx, problems, count, &j);
+      ctx->force_variant = false;
+      if (s == TT_OK) s = tt_cross_run(j, got.data());
+      const auto t1 = std::chrono::steady_clock::now();
+      if (j) tt_cross_free(j);
+      if (s < 0 && c == 0) return s;          // the rule's own run failed: that is the job's error
+      if (s < 0) {
+        match = false;
+        break;
+      }
+      ms.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+      if (c == 0 && r == 0) ref = got;
+      else match = same(ref, got);
+    }
+    if (!match) continue;
+    ++matching;
+    std::sort(ms.begin(), ms.end());
+    const double med = ms[ms.size() / 2];
+    if (c == 0) rule_ms = med;
+    if (best < 0 || med < best_ms) {
+      best = (int)c;
+      best_ms = med;
+    }
+  }
+  ctx->tune[tune_key(fam, dd, maxm, maxR)] = tt_ctx::Tuned{cands[best].first, cands[best].second, rule_ms, best_ms};
+  out->mode_bucket = cands[best].first;
+  out->rank_policy = cands[best].second;
+  out->rule_mode_bucket = rule_mb;
+  out->candidates = (int32_t)cands.size();
+  out->matching = matching;
+  out->reserved = 0;
+  out->rule_ms = rule_ms;
+  out->tuned_ms = best_ms;
+  return tune_save(ctx);
 }
 
 tt_status tt_ctx_synchronize(tt_ctx* c) {
@@ -442,6 +562,18 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
     if (m >= 2) {
       for (int b = 0; b < m - 1; ++b) bond_tasks.push_back(make_int2(k, b));
       for (int c = 0; c < m; ++c) core_tasks.push_back(make_int2(k, c));
+    }
+  }
+  // kernel variant: the rule's, a tuned one recorded in the context, or tt_autotune's candidate
+  j->mbucket = bucket_m_for(j->fam, j->dd, j->maxm);
+  if (ctx->force_variant) {
+    j->mbucket = ctx->forced.mbucket;
+    j->rank_policy = ctx->forced.rank_policy;
+  } else {
+    auto t = ctx->tune.find(tune_key(j->fam, j->dd, j->maxm, j->maxR));
+    if (t != ctx->tune.end() && variant_valid(j->fam, j->dd, j->maxm, t->second.mbucket)) {
+      j->mbucket = t->second.mbucket;
+      j->rank_policy = t->second.rank_policy;
     }
   }
   Layout L;

@@ -41,7 +41,15 @@ class _Problem(ctypes.Structure):
                 ("n_nodes", ctypes.c_int32), ("rank_cap", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("max_sweeps", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("params", ctypes.POINTER(ctypes.c_double))]
+                ("params", ctypes.POINTER(ctypes.c_double)),
+                ("stop_rule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("mode_bucket", ctypes.c_int32), ("rank_policy", ctypes.c_int32),
+                ("rule_mode_bucket", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("matching", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rule_ms", ctypes.c_double), ("tuned_ms", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -76,9 +84,10 @@ EXPORTS = [
     "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
     "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
     "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue", "tt_mc_integrate",
-    "tt_mc_integrate_noalloc", "tt_job_core", "tt_batch_run",
+    "tt_mc_integrate_noalloc", "tt_job_core", "tt_batch_run", "tt_autotune",
 ]
 
+STOP_RULE_IDS = {"rel2": 0, "strict": 1}   # tt_stop_rule
 KERNEL_KINDS = {"sweep": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
                 "eval_points": 5, "eval_fibers": 6, "mc": 7}
 MC_RANDOM, MC_LATTICE = 0, 1
@@ -132,6 +141,7 @@ def load_library():
         "tt_mc_integrate_noalloc": (i32, [vp, P(_Problem), i32, i64, i32, P(i64), vp]),
         "tt_job_core": (i32, [vp, i32, i32, P(dbl), P(dbl), i64, P(i32), P(i32)]),
         "tt_batch_run": (i32, [vp, P(_Problem), i32, P(_Info)]),
+        "tt_autotune": (i32, [vp, P(_Problem), i32, i32, P(_TuneResult)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -162,7 +172,7 @@ def _c_problem(p: Problem, keep):
         keep.append(arr)
         params = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return _Problem(FAMILY_IDS[p.family], p.d, p.n, p.rank_cap, float(p.tol), PRECISION_IDS[p.precision],
-                    int(p.max_sweeps), int(p.seed) & ((1 << 64) - 1), params)
+                    int(p.max_sweeps), int(p.seed) & ((1 << 64) - 1), params, STOP_RULE_IDS[p.stop], 0)
 
 
 def footprint(p: Problem):
@@ -244,6 +254,14 @@ class Context:
             raise TTError(st, "tt_batch_run", Job._info_dicts(infos))
         _check(st, "tt_batch_run")
         return Job._info_dicts(infos)
+
+    def autotune(self, problems, reps=3):
+        """tt_autotune: time the kernel variants of this job, record the fastest bit-identical one."""
+        keep = []
+        arr = (_Problem * len(problems))(*[_c_problem(p, keep) for p in problems])
+        res = _TuneResult()
+        _check(self._lib.tt_autotune(self.handle, arr, len(problems), reps, ctypes.byref(res)), "tt_autotune")
+        return {f: getattr(res, f) for f, _ in _TuneResult._fields_ if f != "reserved"}
 
     def server(self, max_bytes=1 << 30, max_active=256):
         return Server(self, max_bytes, max_active)

@@ -28,6 +28,7 @@ class Problem:
     max_sweeps: int = 0
     params: Optional[dict] = None   # synthetic: {"a": [...], "b": [...]}, d entries each
     precision: str = "fp64"         # "fp64" or "dd" (double-double, paper-form integrands)
+    stop: str = "rel2"              # "rel2" (two small relative changes) or "strict" (no accepted pivot)
 
     def modes(self):
         return self.d - 1 if self.family in ("ising_c", "ising_d", "ising_e") else self.d
@@ -68,10 +69,10 @@ def config_small():
     ]
 
 
-def config_single_sweep():
+def config_single_sweep(stop="rel2"):
     """D_5..D_10 (paper form), 64 nodes, rank <= 32, tol 1e-10, plus C_4."""
-    probs = [Problem("ising_d", d, 64, 32, 1e-10, seed=d) for d in range(5, 11)]
-    probs.append(Problem("ising_c", 4, 64, 32, 1e-10, seed=4))
+    probs = [Problem("ising_d", d, 64, 32, 1e-10, seed=d, stop=stop) for d in range(5, 11)]
+    probs.append(Problem("ising_c", 4, 64, 32, 1e-10, seed=4, stop=stop))
     return probs
 
 

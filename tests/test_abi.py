@@ -75,3 +75,15 @@ def test_ctx_fails_loudly_without_gpu():
         pass
     with pytest.raises(binding.TTError):
         binding.Context(0)
+
+
+def test_stop_rule_field():
+    import ctypes
+    lib = binding.load_library()
+    assert binding.footprint(Problem("ising_d", 6, 64, 32, 1e-10, stop="strict")) == \
+        binding.footprint(Problem("ising_d", 6, 64, 32, 1e-10))
+    keep = []
+    for rule, reserved, ok in [(0, 0, True), (1, 0, True), (2, 0, False), (-1, 0, False), (1, 5, False)]:
+        cp = binding._c_problem(Problem("ising_d", 6, 64, 32, 1e-10), keep)
+        cp.stop_rule, cp.reserved = rule, reserved
+        assert (lib.tt_job_footprint(ctypes.byref(cp)) > 0) == ok, (rule, reserved)

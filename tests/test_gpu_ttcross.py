@@ -10,6 +10,7 @@ first divergence must be a near-tie and the final values must agree within
 10*tol (the reading of "GPU matches oracle" for a heuristic).
 """
 import math
+import os
 
 import mpmath as mp
 import numpy as np
@@ -25,7 +26,7 @@ pytestmark = pytest.mark.gpu
 
 def run_oracle(p):
     return oracle_tt.solve(p.family, p.d, p.n, p.rank_cap, p.tol, p.seed,
-                           max_sweeps=p.max_sweeps, params=p.params)
+                           max_sweeps=p.max_sweeps, params=p.params, stop_rule=p.stop)
 
 
 def compare(job, k, p, ref, exact_log=True, value_scale=None):
@@ -432,3 +433,31 @@ def test_batch_run_entry_point_equals_the_job_api():
     for a, b in zip(infos, ref):
         for key in ("value", "value_lo", "evals", "sweeps", "reason", "max_rank", "err_flags"):
             assert a[key] == b[key], (key, a, b)
+
+
+def n64_reference(d):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ising_d_n64_reference.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            if int(f[0]) == d:
+                return float(f[1])
+    raise KeyError(d)
+
+
+@pytest.mark.parametrize("d", [6, 7])
+def test_strict_stop_rule_matches_the_oracle(d):
+    # the strict rule runs D_6 and D_7 (64 nodes, rank <= 32, tol 1e-10) past the two
+    # small relative changes that stop the default rule, to a sweep with no accepted
+    # pivot; the GPU takes the oracle's decisions all the way and ends within 2e-11
+    # of the tol-1e-13 reference
+    p = Problem("ising_d", d, 64, 32, 1e-10, seed=d, stop="strict")
+    print(f"strict {p}", flush=True)
+    ctx = gpu_context()
+    job = ctx.job([p])
+    info = job.run()[0]
+    ref = run_oracle(p)
+    compare(job, 0, p, ref)
+    assert info["sweeps"] == ref.sweeps and info["reason"] == "converged"
+    assert abs(info["value"] / n64_reference(d) - 1) < 2e-11
+    job.free()

@@ -277,3 +277,39 @@ def test_overflow_in_a_sweep_is_a_numeric_error():
     assert all(np.isfinite(tt.core(k)).all() for k in range(tt.m)) and math.isfinite(tt.history[0])
     with pytest.raises(FloatingPointError, match="non-finite"):
         tt.sweep()
+
+
+def n64_reference():
+    out = {}
+    for line in open(os.path.join(GOLDEN, "ising_d_n64_reference.txt")):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            out[int(f[0])] = float(f[1])
+    return out
+
+
+@pytest.mark.parametrize("d", [6, 7])
+def test_strict_stop_rule(d):
+    """The strict rule stops only on a sweep that accepts no pivot (or the caps).
+
+    D_6 and D_7 with 64 nodes, rank <= 32, tol 1e-10: the default rule stops after
+    two small relative changes while bonds still accept pivots, about 1e-10 from
+    the integral; the strict run takes the same decisions up to there, continues
+    until a sweep accepts nothing, and ends well within tol of the tol-1e-13
+    reference of the same nodes.
+    """
+    loose = ttcross.TTCross("ising_d", d, 64, 32, 1e-10, d)
+    loose.run()
+    strict = ttcross.TTCross("ising_d", d, 64, 32, 1e-10, d, stop_rule="strict")
+    strict.run()
+    ref = n64_reference()[d]
+    assert sum(r.accepted for r in loose.pivot_log[-1]) > 0          # stopped with pivots still accepted
+    assert strict.sweeps > loose.sweeps
+    assert strict.history[:loose.sweeps + 1] == loose.history
+    for a, b in zip(loose.pivot_log, strict.pivot_log):
+        assert [(r.row, r.col, r.accepted) for r in a] == [(r.row, r.col, r.accepted) for r in b]
+    last = strict.pivot_log[-1]
+    assert sum(r.accepted for r in last) == 0 and strict.stop_reason == "converged"
+    assert abs(strict.history[-1] / ref - 1) < 2e-11
+    with pytest.raises(ValueError):
+        ttcross.TTCross("ising_d", d, 8, 4, 1e-10, d, stop_rule="sometimes")
