@@ -259,7 +259,7 @@ def run_gpu(args):
         return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt, tune=tune,
                     s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=None,
                     errs={}, probs=probs, batch=None, dd=None, serving=None, mc=None, large=None,
-                    n_ok=n_ok, n_checked=len(checks), single=None)
+                    n_ok=n_ok, n_checked=len(checks), single=None, als=None)
 
     # the fibre-evaluation kernel alone on a large fibre set (D_10, middle mode)
     import numpy as np
@@ -300,6 +300,7 @@ def run_gpu(args):
     fib_tflops = fib_flops / (ms / nl * 1e-3) / 1e12
 
     single = run_single(ctx, probs, refs)
+    als_res = run_als(ctx, refs)
     rel2 = run_rel2(ctx, refs)
     single["default_stop_rule"] = rel2
     batch = run_batch(ctx, refs)
@@ -317,7 +318,44 @@ def run_gpu(args):
     return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt, tune=tune,
                 s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
                 errs=errs, probs=probs, batch=batch, dd=dd, serving=serving, mc=mcres, large=large,
-                n_ok=n_ok, n_checked=len(checks), single=single)
+                n_ok=n_ok, n_checked=len(checks), single=single, als=als_res)
+
+
+def run_als(ctx, refs, reps=3):
+    """The ALS maxvol refresh (Sec. 3.3, Alg. 3): D_8..D_10 of the headline (64 nodes, rank <= 32,
+    tol 1e-10, strict stop) run plainly, and with one refresh of the index sets after the fourth sweep."""
+    import torch
+
+    from paper_1903_11554_amd.workloads import Problem
+    out = {}
+    for d in (8, 9, 10):
+        p = Problem("ising_d", d, 64, 32, 1e-10, seed=d, stop="strict")
+        row = {}
+        for mode in ("plain", "refresh_after_4"):
+            best = None
+            for _ in range(reps):
+                ctx.profile(True)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                job = ctx.job([p])
+                if mode != "plain":
+                    job.sweep(4)
+                    job.refresh()
+                info = job.run()[0]
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                nl, ms = ctx.kernel_time("refresh")
+                job.free()
+                ctx.profile(False)
+                if best is None or dt < best[0]:
+                    best = (dt, info, ms)
+            dt, info, ms = best
+            good, rel = check_result(p, info, refs)
+            row[mode] = {"ms_to_solution": dt * 1e3, "sweeps": info["sweeps"], "evals": info["evals"],
+                         "rel_err_vs_reference": rel, "passes_check": good,
+                         "refresh_kernel_ms": ms if mode != "plain" else 0.0}
+        out[f"ising_d_{d}"] = row
+    return out
 
 
 def run_rel2(ctx, refs, reps=10):
@@ -779,6 +817,7 @@ def main():
         "serving": r["serving"],
         "monte_carlo": r["mc"],
         "large_integrals": r["large"],
+        "als_refresh": r["als"],
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(r["probs"], args.cpu_budget)

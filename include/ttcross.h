@@ -191,6 +191,23 @@ tt_status tt_cross_sweep(tt_job *job, int32_t n_sweeps, tt_info *info);
  * error); fills info.  Status as tt_cross_sweep. */
 tt_status tt_cross_run(tt_job *job, tt_info *info);
 
+/* One ALS maxvol refresh of the index sets of every integral still running, at
+ * fixed ranks (Sec. 3.3, Alg. 3, with the row swaps of Alg. 1, Sec. 2.4): left
+ * to right, bond b's left set becomes the maxvol rows of the r_{b-1} n x r_b
+ * matrix B(I_<=b-1 x [n], I_>b) on the left set refreshed one step before; right
+ * to left, its right set the maxvol columns of B(I_<=b, [n] x I_>b+1).  maxvol:
+ * Gaussian elimination with partial pivoting, then Alg. 1 swaps while the
+ * largest |B(:, I)^-1 B| exceeds 1.01 (at most 4 r swaps).  The sets stay nested;
+ * the cores, the interpolation cores (recomputed from the cores in every later
+ * sweep too) and the integral are rebuilt on them, and the integral replaces the
+ * value after the last sweep (tt_job_history), so the next sweep's relative
+ * change is taken from it.  Each bond's largest |B| takes the refresh's values
+ * into account; every value evaluated counts in tt_info.evals.  TT_FP64 jobs
+ * only: TT_EINVAL for double-double jobs.  TT_ENUMERIC (infos filled, the
+ * integral stopped with TT_STOP_ERROR) if a matrix has lower rank than its bond
+ * or a value is not finite. */
+tt_status tt_cross_refresh(tt_job *job, tt_info *info);
+
 /* A batch of count integrals solved together in one call: tt_cross_init,
  * tt_cross_run and tt_cross_free of one job (every kernel launch serves all of
  * them), info[count] filled with each integral's result.  Status as
@@ -306,7 +323,7 @@ tt_status tt_mc_integrate_noalloc(tt_ctx *ctx, const tt_problem *problem, int32_
  * 0 sweep (pivot search, core updates, quadrature and stopping rule fused in
  * one launch per sweep), 1 core update at init, 2 quadrature at init,
  * 3 rank-1 start, 4 Gauss--Legendre nodes, 5 tt_eval_points, 6 tt_eval_fibers,
- * 7 tt_mc_integrate.
+ * 7 tt_mc_integrate, 8 ALS refresh (tt_cross_refresh, with the rebuild of the cores).
  * Errors: TT_EINVAL (bad kind or NULL outputs). */
 tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
 tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);

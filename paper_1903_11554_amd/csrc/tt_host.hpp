@@ -36,7 +36,7 @@ inline hipError_t& last_hip_error() {
 
 // kernel kinds timed by the optional event profiler
 enum { KK_SWEEP = 0, KK_UPDATE = 1, KK_INTEGRAL = 2, KK_START = 3, KK_GL = 4, KK_EVAL_POINTS = 5,
-       KK_EVAL_FIBERS = 6, KK_MC = 7, KK_COUNT = 8 };
+       KK_EVAL_FIBERS = 6, KK_MC = 7, KK_REFRESH = 8, KK_COUNT = 9 };
 
 struct tt_ctx {
   int device = 0;

@@ -35,6 +35,12 @@ void by_rank(const LaunchArgs& a, int what, int rb) {
     hipLaunchKernelGGL((k_start<Real, TT_FAM, MAXM>), dim3(a.nprob), dim3(kBlock), 0, a.stream, a.desc);
     return;
   }
+  if (what == LAUNCH_ALS) {   // double precision only (the host rejects double-double jobs)
+#if !TT_INST_DD
+    hipLaunchKernelGGL((k_als<TT_FAM, MAXM>), dim3(a.nprob), dim3(kSweepBlock), 0, a.stream, a.desc);
+#endif
+    return;
+  }
   if (what == LAUNCH_INIT_UPDATE) {
     hipLaunchKernelGGL((k_update<Real, TT_FAM, MAXM, 8>), dim3(a.ncore), dim3(kSweepBlock), 0, a.stream,
                        a.desc, a.core_tasks, 1);

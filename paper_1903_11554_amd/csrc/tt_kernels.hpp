@@ -779,33 +779,15 @@ __device__ __forceinline__ double cmax_of(double cmax, double x) {
   return (a <= cmax) ? cmax : (isfinite(a) ? a : __builtin_huge_val());
 }
 
-// C_c = F_c M_c^-1 from scratch (double precision): M_c = F_c(I_<=c, :r), the
-// old cross rows sm.rowidx[0..r0) and, when a pivot was accepted this sweep,
-// prow.  With A = M_c^T, Gaussian elimination with partial pivoting gives
-// P A = L U in LDS (in wave 0, ordered by wave barriers only); every row f of
-// F_c is then solved by the workgroup as A x = f^T, x = U^-1 L^-1 P f^T, in place
-// in C_c (a solve, not a product with an inverse: its residual stays at the
-// rounding level of the factors, so C_c(I_<=c, :) stays the identity to rounding
-// even for a nearly singular cross).  Loops are kept rolled so the routine adds
-// few registers to the sweep kernel.  Marks the core for later sweeps.
+// Gaussian elimination with partial pivoting of the r x r matrix in sm.A (leading
+// dimension RMAX + 1), in wave 0 alone with wave-level ordering only: P A = L U in
+// place (L unit lower, its multipliers below the diagonal), the row permutation in
+// sm.perm (filled by the caller with 0..RMAX-1), sm.zf = 1 if a column has no
+// nonzero pivot.  Every thread of the workgroup calls it; a barrier follows.
 template <int RMAX, class Smem>
-__device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, const int r, const int N, const int prow,
-                                             const int r0, const double* __restrict__ Fc, const int cc,
-                                             double* __restrict__ Cc, const size_t ldC, Smem& sm) {
+__device__ __forceinline__ void lu_pivoted(const int r, Smem& sm) {
   constexpr int LA = RMAX + 1;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    p.rfl[c] = 1;
-    atomicAdd(&p.st->recomputes, 1);
-    if (prow >= 0) sm.rowidx[r0] = prow;
-  }
-  if (tid < RMAX) sm.perm[tid] = tid;
-  __syncthreads();
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const int i = e / r, j = e % r;
-    sm.A[i * LA + j] = Fc[(size_t)sm.rowidx[j] * cc + i];
-  }
-  __syncthreads();
   if (tid < kWave) {   // the elimination runs in wave 0 alone, with wave-level ordering only
     bool zero = false;
 #pragma unroll 1
@@ -853,9 +835,17 @@ __device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, con
     if (tid == 0) sm.zf = zero ? 1 : 0;
   }
   __syncthreads();
-  if (tid == 0 && sm.zf) atomicOr(&p.st->err_flags, 2);
+}
+
+// x = U^-1 L^-1 P f for the rows row = tid, tid + blockDim.x, .. < N of the
+// workgroup, with the factors of lu_pivoted: f(row, q) reads entry q of row f and
+// xat(q, row) is unknown q of that row's solution (read and written in place).
+template <int RMAX, class Smem, class FGet, class XAt>
+__device__ __forceinline__ void solve_rows(const int r, const int N, Smem& sm, FGet&& fget, XAt&& xat) {
+  constexpr int LA = RMAX + 1;
+  const int tid = threadIdx.x;
   // Row solves in blocks of kB unknowns held in registers: the earlier (forward)
-  // or later (backward) unknowns are read from C_c once per block, not once per
+  // or later (backward) unknowns are read from the unknowns' storage once per block, not once per
   // unknown.  The guards on q0 + t < r depend only on the block: no divergence.
   constexpr int kB = 4;
 #pragma unroll 1
@@ -864,10 +854,10 @@ __device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, con
     for (int q0 = 0; q0 < r; q0 += kB) {   // L y = P f (unit lower)
       double acc[kB];
 #pragma unroll
-      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? Fc[(size_t)row * cc + sm.perm[q0 + t]] : 0.0;
+      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? fget(row, sm.perm[q0 + t]) : 0.0;
 #pragma unroll 1
       for (int pp = 0; pp < q0; ++pp) {
-        const double y = Cc[(size_t)pp * ldC + row];
+        const double y = xat(pp, row);
 #pragma unroll
         for (int t = 0; t < kB; ++t)
           if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + pp], y, acc[t]);
@@ -879,16 +869,16 @@ __device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, con
           if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + q0 + u], acc[u], acc[t]);
 #pragma unroll
       for (int t = 0; t < kB; ++t)
-        if (q0 + t < r) Cc[(size_t)(q0 + t) * ldC + row] = acc[t];
+        if (q0 + t < r) xat(q0 + t, row) = acc[t];
     }
 #pragma unroll 1
     for (int q0 = ((r - 1) / kB) * kB; q0 >= 0; q0 -= kB) {   // U x = y
       double acc[kB];
 #pragma unroll
-      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? Cc[(size_t)(q0 + t) * ldC + row] : 0.0;
+      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? xat(q0 + t, row) : 0.0;
 #pragma unroll 1
       for (int pp = q0 + kB; pp < r; ++pp) {
-        const double x = Cc[(size_t)pp * ldC + row];
+        const double x = xat(pp, row);
 #pragma unroll
         for (int t = 0; t < kB; ++t)
           if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + pp], x, acc[t]);
@@ -903,9 +893,42 @@ __device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, con
         }
 #pragma unroll
       for (int t = 0; t < kB; ++t)
-        if (q0 + t < r) Cc[(size_t)(q0 + t) * ldC + row] = acc[t];
+        if (q0 + t < r) xat(q0 + t, row) = acc[t];
     }
   }
+}
+
+// C_c = F_c M_c^-1 from scratch (double precision): M_c = F_c(I_<=c, :r), the
+// old cross rows sm.rowidx[0..r0) and, when a pivot was accepted this sweep,
+// prow.  With A = M_c^T, Gaussian elimination with partial pivoting gives
+// P A = L U in LDS (lu_pivoted); every row f of F_c is then solved by the
+// workgroup as A x = f^T, x = U^-1 L^-1 P f^T, in place in C_c (solve_rows: a
+// solve, not a product with an inverse: its residual stays at the rounding level
+// of the factors, so C_c(I_<=c, :) stays the identity to rounding even for a
+// nearly singular cross).  Loops are kept rolled so the routine adds few
+// registers to the sweep kernel.  Marks the core for later sweeps.
+template <int RMAX, class Smem>
+__device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, const int r, const int N, const int prow,
+                                             const int r0, const double* __restrict__ Fc, const int cc,
+                                             double* __restrict__ Cc, const size_t ldC, Smem& sm) {
+  constexpr int LA = RMAX + 1;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    p.rfl[c] = 1;
+    atomicAdd(&p.st->recomputes, 1);
+    if (prow >= 0) sm.rowidx[r0] = prow;
+  }
+  if (tid < RMAX) sm.perm[tid] = tid;
+  __syncthreads();
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int i = e / r, j = e % r;
+    sm.A[i * LA + j] = Fc[(size_t)sm.rowidx[j] * cc + i];
+  }
+  __syncthreads();
+  lu_pivoted<RMAX>(r, sm);
+  if (tid == 0 && sm.zf) atomicOr(&p.st->err_flags, 2);
+  solve_rows<RMAX>(r, N, sm, [&](int row, int q) { return Fc[(size_t)row * cc + q]; },
+                   [&](int q, int row) -> double& { return Cc[(size_t)q * ldC + row]; });
   __syncthreads();
 }
 
@@ -1105,9 +1128,11 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   double cmax = 0.0;   // largest |entry| of C_c written below (double jobs)
   bool sing = false;   // a zero pivot in the incremental steps
   if (init == 2) {   // every entry re-evaluated on refreshed sets: C_c from F_c with a pivoted solve
-    if (tid < r) sm.rowidx[tid] = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
-    __syncthreads();
-    refresh_core<RMAX>(p, c, r, N, -1, r, Fc, cc, Cc, ldC, sm);
+    if constexpr (!is_dd_t<T>::value) {
+      if (tid < r) sm.rowidx[tid] = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
+      __syncthreads();
+      refresh_core<RMAX>(p, c, r, N, -1, r, Fc, cc, Cc, ldC, sm);
+    }
   } else if (init) {   // rank 1: M_c = (B(i0)), C_c = F_c / M_c
     const int row0 = p.Lpar[(size_t)c * R] * n + p.Lnode[(size_t)c * R];
     const T m00 = Fc[(size_t)row0 * cc];
@@ -1286,6 +1311,233 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     __syncthreads();
     mark(p, msw, mb, 14);
   }
+}
+
+// ------------------------------------------- ALS maxvol refresh (Alg. 3, Alg. 1)
+// One refresh of an integral's index sets at fixed ranks, by one workgroup,
+// bonds in order.  Left to right, bond b: the r_{b-1} n x r_b matrix
+// A = B(I_<=b-1 x [n], I_>b) on the left set of bond b-1 refreshed one step
+// before; its maxvol rows (alpha, i) become I_<=b.  Right to left: the
+// n r_{b+1} x r_b matrix B(I_<=b, [n] x I_>b+1)^T on the refreshed right set of
+// bond b+1; its maxvol rows (j, beta) become I_>b.  maxvol (Sec. 2.4): r rows by
+// Gaussian elimination with partial pivoting, then Alg. 1 steps on
+// C = A A(I,:)^-1, recomputed from A after every swap, while the largest |C|
+// exceeds 1 + kMaxvolDelta (at most 4 r swaps).  The matrices are kept column by
+// column in the storage of the cores (A) and of the interpolation cores (the
+// elimination copy, then C); the cores, interpolation cores and core sums are
+// then rebuilt on the new sets (update_core, init 2), which recomputes every
+// interpolation core from its core in later sweeps as well.
+constexpr double kMaxvolDelta = 1e-2;
+
+template <int MAXM>
+struct AlsSmem {
+  union {
+    struct {
+      double Lx[TT_MAX_RANK * (MAXM + 1)];
+      double Rx[TT_MAX_RANK * (MAXM + 1)];
+      double Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
+    } ev;
+    double A[TT_MAX_RANK * (TT_MAX_RANK + 1)];   // LU of A(I, :)^T
+  };
+  double t[TT_MAX_NODES], w[TT_MAX_NODES];
+  double prow[TT_MAX_RANK];
+  int rows[TT_MAX_RANK], perm[TT_MAX_RANK];
+  double red_v[kSweepBlock / kWave + 1];
+  int red_i[kSweepBlock / kWave + 1];
+  int zf;
+};
+
+// The entries F_c(alpha, i, beta) = B(I_<=c-1[alpha], t_i, I_>c[beta]) of core c on
+// the current sets (alpha < rl, beta < rr), each written to W[at(alpha, i, beta)];
+// returns this thread's largest |B| and sets bad on a non-finite value.
+template <int FAM, int MAXM, class At>
+__device__ __forceinline__ double als_core_values(const ProbDesc& p, const FamilyArgs& fa, const int c,
+                                                  const int rl, const int rr, double* __restrict__ W, At&& at,
+                                                  AlsSmem<MAXM>& sm, bool& bad) {
+  constexpr int LD = MAXM + 1;
+  constexpr bool kStream = MAXM == 0;
+  const int tid = threadIdx.x, m = p.m, n = p.n, R = p.R;
+  const double* __restrict__ gLx = p.Lx;
+  const double* __restrict__ gRx = p.Rx;
+  const bool hasL = c >= 1, hasR = c <= m - 2;
+  if constexpr (!kStream) {
+    for (int e = tid; e < rl * c; e += blockDim.x) {
+      const int a = e / c, k = e % c;
+      sm.ev.Lx[a * LD + k] = gLx[((size_t)(c - 1) * R + a) * m + k];
+    }
+    const int nright = m - c - 1;
+    for (int e = tid; e < rr * nright; e += blockDim.x) {
+      const int a = e / nright, k = c + 1 + e % nright;
+      sm.ev.Rx[a * LD + k] = gRx[((size_t)c * R + a) * m + k];
+    }
+  }
+  for (int a = tid; a < rl; a += blockDim.x) sm.ev.Lw[a] = hasL ? p.Lw[(size_t)(c - 1) * R + a] : 1.0;
+  for (int a = tid; a < rr; a += blockDim.x) sm.ev.Rw[a] = hasR ? p.Rw[(size_t)c * R + a] : 1.0;
+  __syncthreads();
+  double amax = 0.0;
+  const int total = rl * n * rr;
+  for (int e = tid; e < total; e += blockDim.x) {
+    const int al = e / (n * rr), rem = e % (n * rr), i = rem / rr, be = rem % rr;
+    const double Wt = (sm.ev.Lw[al] * sm.w[i]) * sm.ev.Rw[be];
+    double v;
+    if constexpr (kStream) {
+      const double* Lrow = gLx + ((size_t)(hasL ? c - 1 : 0) * R + al) * m;
+      const double* Rrow = gRx + ((size_t)(hasR ? c : 0) * R + be) * m;
+      const Segs sg{Lrow, c, sm.t[i], 0.0, 1, Rrow, m};
+      v = Wt * integrand_seg<FAM>(fa, sg);
+    } else {
+      double y[MAXM];
+#pragma unroll
+      for (int k = 0; k < MAXM; ++k) {
+        double yk = 0.0;
+        if (k < m) {
+          yk = (k < c) ? sm.ev.Lx[al * LD + k] : sm.ev.Rx[be * LD + k];
+          yk = (k == c) ? sm.t[i] : yk;
+        }
+        y[k] = yk;
+      }
+      v = Wt * integrand_fam<double, FAM, MAXM>(fa, y);
+    }
+    bad |= !isfinite(v);
+    amax = fmax(amax, fabs(v));
+    W[at(al, i, be)] = v;
+  }
+  __syncthreads();
+  return amax;
+}
+
+// maxvol rows of the N x r matrix W (column q at W + q N) into sm.rows; V holds
+// N r doubles of working storage.  Returns the number of swaps, or -1 if W has
+// rank below r.
+template <class Smem>
+__device__ __forceinline__ int als_maxvol(const double* __restrict__ W, const int N, const int r,
+                                          double* __restrict__ V, Smem& sm) {
+  constexpr int LA = TT_MAX_RANK + 1;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N * r; e += blockDim.x) V[e] = W[e];
+  __syncthreads();
+  // start: Gaussian elimination with partial (row) pivoting, column by column
+  for (int k = 0; k < r; ++k) {
+    ArgMax a{-1.0, 0x7fffffff};
+    for (int row = tid; row < N; row += blockDim.x) {
+      const double v = fabs(V[(size_t)k * N + row]);
+      if (better(v, row, a.v, a.idx)) { a.v = v; a.idx = row; }
+    }
+    a = block_argmax(a, sm.red_v, sm.red_i);
+    if (!(a.v > 0.0)) return -1;
+    const int pr = a.idx;
+    if (tid == 0) sm.rows[k] = pr;
+    for (int q = tid; q < r; q += blockDim.x) sm.prow[q] = V[(size_t)q * N + pr];
+    __syncthreads();
+    const double piv = sm.prow[k];
+    for (int row = tid; row < N; row += blockDim.x) {
+      const double f = V[(size_t)k * N + row] / piv;
+      for (int q = k + 1; q < r; ++q) V[(size_t)q * N + row] = V[(size_t)q * N + row] - f * sm.prow[q];
+    }
+    __syncthreads();
+  }
+  // Alg. 1 steps: C = W W(I,:)^-1 (A = W(I,:)^T factored, each row solved), swap at max |C|
+  int swaps = 0;
+  for (;;) {
+    if (tid < TT_MAX_RANK) sm.perm[tid] = tid;
+    for (int e = tid; e < r * r; e += blockDim.x) {
+      const int i = e / r, j = e % r;
+      sm.A[i * LA + j] = W[(size_t)i * N + sm.rows[j]];
+    }
+    __syncthreads();
+    lu_pivoted<TT_MAX_RANK>(r, sm);
+    if (sm.zf) return -1;
+    solve_rows<TT_MAX_RANK>(r, N, sm, [&](int row, int q) { return W[(size_t)q * N + row]; },
+                            [&](int q, int row) -> double& { return V[(size_t)q * N + row]; });
+    __syncthreads();
+    ArgMax a{-1.0, 0x7fffffff};
+    for (int row = tid; row < N; row += blockDim.x)
+      for (int q = 0; q < r; ++q) {
+        const double v = fabs(V[(size_t)q * N + row]);
+        if (better(v, row * r + q, a.v, a.idx)) { a.v = v; a.idx = row * r + q; }
+      }
+    a = block_argmax(a, sm.red_v, sm.red_i);
+    if (!(a.v > 1.0 + kMaxvolDelta) || swaps >= 4 * r) break;
+    if (tid == 0) sm.rows[a.idx % r] = a.idx / r;
+    ++swaps;
+    __syncthreads();
+  }
+  return swaps;
+}
+
+template <int FAM, int MAXM>
+__device__ __forceinline__ void als_refresh(const ProbDesc& p, AlsSmem<MAXM>& sm) {
+  const int tid = threadIdx.x;
+  ProbState* st = p.st;
+  const int m = p.m, n = p.n, R = p.R;
+  if (st->done || m < 2) return;
+  const FamilyArgs fa = family_args(p);
+  for (int i = tid; i < n; i += blockDim.x) { sm.t[i] = p.t[i]; sm.w[i] = p.w[i]; }
+  __syncthreads();
+  bool bad = false;
+  int fail = 0;
+  unsigned long long evals = 0;
+  // left to right: I_<=b from core b on the refreshed I_<=b-1 and the current I_>b
+  for (int b = 0; b < m - 1 && !fail; ++b) {
+    const int rl = b > 0 ? p.rank[b - 1] : 1, r = p.rank[b], N = rl * n;
+    double* W = p.F + p.Foff[b];
+    double* V = p.C + p.Coff[b];
+    const double amax = als_core_values<FAM, MAXM>(p, fa, b, rl, r, W,
+        [&](int al, int i, int be) { return (size_t)be * N + (size_t)al * n + i; }, sm, bad);
+    const double am = block_max(amax, sm.red_v);
+    if (__syncthreads_or(bad)) { fail = 1; break; }
+    if (als_maxvol(W, N, r, V, sm) < 0) { fail = 2; break; }
+    double* gLx = p.Lx;
+    for (int e = tid; e < r * (b + 1); e += blockDim.x) {   // row a: I_<=b-1[alpha] + (i)
+      const int a = e / (b + 1), k = e % (b + 1), q = sm.rows[a], al = q / n, i = q % n;
+      gLx[((size_t)b * R + a) * m + k] = (k < b) ? gLx[((size_t)(b - 1) * R + al) * m + k] : sm.t[i];
+    }
+    for (int a = tid; a < r; a += blockDim.x) {
+      const int q = sm.rows[a], al = q / n, i = q % n;
+      p.Lpar[(size_t)b * R + a] = al;
+      p.Lnode[(size_t)b * R + a] = i;
+      p.Lw[(size_t)b * R + a] = (b > 0 ? p.Lw[(size_t)(b - 1) * R + al] : 1.0) * sm.w[i];
+    }
+    if (tid == 0) p.scale[b] = fmax(p.scale[b], am);
+    evals += (unsigned long long)N * r;
+    __syncthreads();
+  }
+  // right to left: I_>b from core b+1 on the refreshed I_<=b and I_>b+1
+  for (int b = m - 2; b >= 0 && !fail; --b) {
+    const int r = p.rank[b], rn = b + 1 <= m - 2 ? p.rank[b + 1] : 1, N = n * rn;
+    double* W = p.F + p.Foff[b + 1];
+    double* V = p.C + (b + 1 <= m - 2 ? p.Coff[b + 1] : p.Coff[b]);
+    const double amax = als_core_values<FAM, MAXM>(p, fa, b + 1, r, rn, W,
+        [&](int al, int j, int be) { return (size_t)al * N + (size_t)j * rn + be; }, sm, bad);
+    const double am = block_max(amax, sm.red_v);
+    if (__syncthreads_or(bad)) { fail = 1; break; }
+    if (als_maxvol(W, N, r, V, sm) < 0) { fail = 2; break; }
+    double* gRx = p.Rx;
+    const int w = m - b - 1;                                  // coordinates b+1 .. m-1
+    for (int e = tid; e < r * w; e += blockDim.x) {           // row a: (j) + I_>b+1[beta]
+      const int a = e / w, k = b + 1 + e % w, q = sm.rows[a], j = q / rn, be = q % rn;
+      gRx[((size_t)b * R + a) * m + k] = (k == b + 1) ? sm.t[j] : gRx[((size_t)(b + 1) * R + be) * m + k];
+    }
+    for (int a = tid; a < r; a += blockDim.x) {
+      const int q = sm.rows[a], j = q / rn, be = q % rn;
+      p.Rnode[(size_t)b * R + a] = j;
+      p.Rpar[(size_t)b * R + a] = be;
+      p.Rw[(size_t)b * R + a] = sm.w[j] * (b + 1 <= m - 2 ? p.Rw[(size_t)(b + 1) * R + be] : 1.0);
+    }
+    if (tid == 0) p.scale[b] = fmax(p.scale[b], am);
+    evals += (unsigned long long)N * r;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    atomicAdd(&st->evals, evals);
+    if (fail) {   // a numeric failure ends the integral (the sets may be half refreshed)
+      atomicOr(&st->err_flags, fail == 1 ? 1 : 2);
+      st->reason = TT_STOP_ERROR;
+      st->done = 1;
+      signal_done(p);
+    }
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------ k_integral
@@ -1545,6 +1797,24 @@ __global__ __launch_bounds__(kSweepBlock) void k_update(ProbDesc* __restrict__ P
   __shared__ UpdateSmem<T, MAXM, RMAX> sm;
   const int2 tk = tasks[blockIdx.x];
   update_core<T, FAM, MAXM, RMAX>(P[tk.x], tk.y, init, sm);
+}
+
+// The ALS refresh of every integral of the job (one workgroup each), followed in
+// the same workgroup by the rebuild of its cores on the new sets.
+template <int FAM, int MAXM>
+union AlsKernelSmem {
+  AlsSmem<MAXM> a;
+  UpdateSmem<double, MAXM, TT_MAX_RANK> u;
+};
+template <int FAM, int MAXM>
+__global__ __launch_bounds__(kSweepBlock) void k_als(ProbDesc* __restrict__ P) {
+  __shared__ AlsKernelSmem<FAM, MAXM> sm;
+  const ProbDesc& p = P[blockIdx.x];
+  als_refresh<FAM, MAXM>(p, sm.a);
+  for (int c = 0; c < p.m; ++c) {
+    update_core<double, FAM, MAXM, TT_MAX_RANK>(p, c, 2, sm.u);
+    __syncthreads();
+  }
 }
 
 template <class T>

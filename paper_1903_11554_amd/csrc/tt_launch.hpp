@@ -19,7 +19,7 @@ struct LaunchArgs {
   hipStream_t stream;
 };
 
-enum { LAUNCH_START = 0, LAUNCH_INIT_UPDATE = 1, LAUNCH_SWEEP = 2 };
+enum { LAUNCH_START = 0, LAUNCH_INIT_UPDATE = 1, LAUNCH_SWEEP = 2, LAUNCH_ALS = 3 };
 
 // what = LAUNCH_*; rbucket (8, 16, 32, 64) bounds every rank reachable in a sweep.
 void launch_paper(const LaunchArgs& a, int what, int rbucket);

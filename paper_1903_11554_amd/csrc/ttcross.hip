@@ -115,7 +115,10 @@ void pinned_give(tt_ctx* c, char* p, size_t bytes) {
 
 void launch(tt_job* j, int what, int rb) {
   LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, j->mbucket, j->ctx->stream};
-  Timed tm(j->ctx, what == LAUNCH_SWEEP ? KK_SWEEP : what == LAUNCH_START ? KK_START : KK_UPDATE);
+  Timed tm(j->ctx, what == LAUNCH_SWEEP   ? KK_SWEEP
+                   : what == LAUNCH_START ? KK_START
+                   : what == LAUNCH_ALS   ? KK_REFRESH
+                                          : KK_UPDATE);
   if (j->dd) {
     launch_paper_dd(a, what, rb);
     return;
@@ -669,6 +672,22 @@ tt_status tt_cross_sweep(tt_job* j, int32_t n_sweeps, tt_info* info) {
   if (s != TT_OK) return s;
   std::vector<ProbState> st;
   s = read_states(j, st);
+  if (s != TT_OK) return s;
+  return sweep_status(st, j->nprob, info);
+}
+
+tt_status tt_cross_refresh(tt_job* j, tt_info* info) {
+  if (!j || j->dd) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  TT_HIP(hipSetDevice(j->ctx->device));
+  if (j->nbond > 0) {
+    launch(j, LAUNCH_ALS, 64);
+    Timed tm(j->ctx, KK_INTEGRAL);
+    hipLaunchKernelGGL(k_integral<double>, dim3(j->nprob), dim3(kIntBlock), 0, j->ctx->stream, j->ddesc, 2);
+  }
+  TT_HIP(hipGetLastError());
+  std::vector<ProbState> st;
+  tt_status s = read_states(j, st);
   if (s != TT_OK) return s;
   return sweep_status(st, j->nprob, info);
 }

@@ -84,12 +84,12 @@ EXPORTS = [
     "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
     "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
     "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue", "tt_mc_integrate",
-    "tt_mc_integrate_noalloc", "tt_job_core", "tt_batch_run", "tt_autotune",
+    "tt_mc_integrate_noalloc", "tt_job_core", "tt_batch_run", "tt_autotune", "tt_cross_refresh",
 ]
 
 STOP_RULE_IDS = {"rel2": 0, "strict": 1}   # tt_stop_rule
 KERNEL_KINDS = {"sweep": 0, "update": 1, "integral": 2, "start": 3, "gl": 4,
-                "eval_points": 5, "eval_fibers": 6, "mc": 7}
+                "eval_points": 5, "eval_fibers": 6, "mc": 7, "refresh": 8}
 MC_RANDOM, MC_LATTICE = 0, 1
 
 _lib = None
@@ -142,6 +142,7 @@ def load_library():
         "tt_job_core": (i32, [vp, i32, i32, P(dbl), P(dbl), i64, P(i32), P(i32)]),
         "tt_batch_run": (i32, [vp, P(_Problem), i32, P(_Info)]),
         "tt_autotune": (i32, [vp, P(_Problem), i32, i32, P(_TuneResult)]),
+        "tt_cross_refresh": (i32, [vp, P(_Info)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -329,6 +330,12 @@ class Job:
         infos = self._infos()
         st = self._checked_infos(self._lib.tt_cross_sweep(self.handle, n, infos), infos, "tt_cross_sweep")
         return st == TT_CONVERGED, self._info_dicts(infos)
+
+    def refresh(self):
+        """tt_cross_refresh: one ALS maxvol refresh of the index sets (Alg. 3) at fixed ranks."""
+        infos = self._infos()
+        self._checked_infos(self._lib.tt_cross_refresh(self.handle, infos), infos, "tt_cross_refresh")
+        return self._info_dicts(infos)
 
     def enqueue(self, n=1):
         """Enqueue n sweeps without waiting (capturable into a HIP graph)."""
