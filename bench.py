@@ -259,7 +259,7 @@ def run_gpu(args):
         return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt, tune=tune,
                     s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=None,
                     errs={}, probs=probs, batch=None, dd=None, serving=None, mc=None, large=None,
-                    n_ok=n_ok, n_checked=len(checks), single=None, als=None)
+                    n_ok=n_ok, n_checked=len(checks), single=None, als=None, qd=None)
 
     # the fibre-evaluation kernel alone on a large fibre set (D_10, middle mode)
     import numpy as np
@@ -301,6 +301,7 @@ def run_gpu(args):
 
     single = run_single(ctx, probs, refs)
     als_res = run_als(ctx, refs)
+    qd_res = run_qd(ctx)
     rel2 = run_rel2(ctx, refs)
     single["default_stop_rule"] = rel2
     batch = run_batch(ctx, refs)
@@ -318,7 +319,45 @@ def run_gpu(args):
     return dict(elapsed=elapsed, lat=lat, total_evals=total_evals, infos=infos, kt=kt, tune=tune,
                 s_evals=s_evals, s_flops=s_flops, s_bytes=s_bytes, sweeps=sweeps, fib=(nl, ms, npts, fib_flops, fib_tflops),
                 errs=errs, probs=probs, batch=batch, dd=dd, serving=serving, mc=mcres, large=large,
-                n_ok=n_ok, n_checked=len(checks), single=single, als=als_res)
+                n_ok=n_ok, n_checked=len(checks), single=single, als=als_res, qd=qd_res)
+
+
+def run_qd(ctx):
+    """Quad-double (f2): D_6 with 5 nodes at full rank against the brute-force sum over the same
+    nodes (the 256-bit value stored with the tests), and D_8 with 32 nodes, rank <= 32, tol 1e-40,
+    against the value the paper prints (limited by 32 nodes and rank 32, not by the arithmetic)."""
+    import mpmath as mp
+    import torch
+
+    from paper_1903_11554_amd.workloads import Problem
+    t2 = None
+    for line in open(os.path.join(ROOT, "tests", "golden", "mp256_ising_small.txt")):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            if f[0] == "6" and f[1] == "5":
+                t2 = f[6]
+    out = {}
+    for name, p, ref in [("d6_n5_full_rank", Problem("ising_d", 6, 5, 32, 1e-45, seed=6, precision="qd"), t2),
+                         ("d8_n32_r32", Problem("ising_d", 8, 32, 32, 1e-40, seed=8, precision="qd", max_sweeps=40),
+                          "1.8959911856917860437277009899220e-05")]:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        job = ctx.job([p])
+        info = job.run()[0]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        parts, e = job.history_parts(0, 4)[-1]
+        job.free()
+        with mp.workdps(80):
+            val = mp.ldexp(mp.fsum(mp.mpf(c) for c in parts), e)
+            rel = float(abs(val / mp.mpf(ref) - 1))
+            sval = mp.nstr(val, 40)
+        out[name] = {"ms_to_solution": dt * 1e3, "sweeps": info["sweeps"], "max_rank": info["max_rank"],
+                     "reason": info["reason"], "evals": info["evals"], "evals_per_s": info["evals"] / dt,
+                     "value": sval, "rel_err_vs_reference": rel,
+                     "reference": "brute-force sum over the same nodes (256-bit)" if name.startswith("d6")
+                     else "the printed D_8 (Sec. 5.5, 129 nodes)"}
+    return out
 
 
 def run_als(ctx, refs, reps=3):
@@ -818,6 +857,7 @@ def main():
         "monte_carlo": r["mc"],
         "large_integrals": r["large"],
         "als_refresh": r["als"],
+        "precision_qd": r["qd"],
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(r["probs"], args.cpu_budget)

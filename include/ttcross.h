@@ -72,8 +72,17 @@ typedef enum {
  *   cores, the pivot errors and the quadrature are all double-double; the pivot
  *   choice and the acceptance test compare the leading double.  Paper-form
  *   integrands (TT_ISING_C, TT_ISING_D, TT_ISING_E) only.
+ * TT_QD: quad-double (four doubles of decreasing magnitude, about 61 significant
+ *   digits), the precision beyond the paper's quadruple: every value as for
+ *   TT_DD; each operation rounds the exact sum of its operands' components (or of
+ *   their exact partial products) to four components.  Paper-form integrands, at
+ *   most TT_QD_MAX_MODES modes and rank TT_QD_MAX_RANK; tt_cross_init, sweep, run,
+ *   integrate, tt_batch_run and the state exports (tt_job_history_parts,
+ *   tt_job_nodes_parts give all four components); the other entry points reject it.
  * All integrals of one job must use the same precision. */
-typedef enum { TT_FP64 = 0, TT_DD = 1 } tt_precision;
+typedef enum { TT_FP64 = 0, TT_DD = 1, TT_QD = 2 } tt_precision;
+#define TT_QD_MAX_MODES 16
+#define TT_QD_MAX_RANK 32
 
 /* Stop reasons reported in tt_info.reason.  TT_STOP_ERROR: the integral was
  * stopped because a sweep raised one of the err_flags bits (its value is not a
@@ -257,6 +266,16 @@ tt_status tt_job_core(tt_job *job, int32_t k, int32_t c, double *F, double *C, i
  * each: t and w rounded to double; t_lo and w_lo (may be NULL) receive the low
  * doubles of the double-double tables (t + t_lo, w + w_lo), for any precision. */
 tt_status tt_job_nodes(tt_job *job, int32_t k, double *t, double *w, double *t_lo, double *w_lo);
+/* The integral after the start and after every sweep (as tt_job_history with
+ * exp2) and the job's unscaled nodes and weights, `parts` (1..4) components per
+ * value, leading component first: 1 for TT_FP64, 2 for TT_DD and 4 for TT_QD
+ * hold every component, further ones are 0.  values: capacity * parts doubles,
+ * exp2: capacity int32 (value = (sum of the components) * 2^exp2); t, w: n * parts
+ * doubles.  Errors: TT_EINVAL (parts outside 1..4, NULL outputs, capacity too
+ * small). */
+tt_status tt_job_history_parts(tt_job *job, int32_t k, int32_t parts, double *values, int32_t *exp2,
+                               int64_t capacity, int64_t *written);
+tt_status tt_job_nodes_parts(tt_job *job, int32_t k, int32_t parts, double *t, double *w);
 void tt_cross_free(tt_job *job);
 
 /* Standalone batched integrand evaluation (the fiber-evaluation kernel of the

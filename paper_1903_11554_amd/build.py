@@ -28,7 +28,8 @@ FLAGS = [
 
 UNITS = [("ttcross.hip", [], "ttcross.o"), ("tt_server.hip", [], "tt_server.o")] + [
     ("tt_inst.hip", [f"-DTT_FAM={f}"], f"tt_inst_{f}.o") for f in range(4)] + [
-    ("tt_inst.hip", ["-DTT_FAM=0", "-DTT_INST_DD=1"], "tt_inst_dd.o")]
+    ("tt_inst.hip", ["-DTT_FAM=0", "-DTT_INST_DD=1"], "tt_inst_dd.o"),
+    ("tt_inst.hip", ["-DTT_FAM=0", "-DTT_INST_QD=1"], "tt_inst_qd.o")]
 
 
 def _run(cmd, verbose):

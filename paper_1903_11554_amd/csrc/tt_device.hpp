@@ -71,16 +71,121 @@ __device__ __forceinline__ dd dd_div(dd x, dd y) {
 }
 __device__ __forceinline__ dd dd_from(double a) { return {a, 0.0}; }
 
+// ------------------------------------------------------------ quad-double
+// A value is the unevaluated sum x0 + x1 + x2 + x3 of four doubles of
+// decreasing magnitude, about 204 bits.  Every operation writes the exact
+// result of its operands' components (their sum, or the exact partial products
+// a_i b_j by two_prod) as a list of doubles and rounds that exact sum to four
+// components (qd_round).  qd_round first turns the list into a nonoverlapping
+// expansion of increasing magnitude by adding one double at a time with
+// error-free sums (Grow-Expansion of Shewchuk, Adaptive Precision
+// Floating-Point Arithmetic, 1997); the sum of a nonoverlapping expansion taken
+// from its smallest component up is within two units in the last place of the
+// exact sum, so four rounds of "take that sum as the next component and subtract
+// it exactly" leave a remainder below 2^-204 of the value.  The operations are
+// out-of-line calls: inlined, each would be thousands of instructions.
+struct qd {
+  double x0, x1, x2, x3;
+};
+constexpr int kQdMaxTerms = 27;   // a b + c: 20 two_prod parts, 3 plain products, 4 components of c
+
+__device__ __noinline__ qd qd_round(const double* __restrict__ t, int n) {
+  double e[kQdMaxTerms + 4];
+  int len = 0;
+  for (int i = 0; i < n; ++i) {
+    double q = t[i];
+    for (int j = 0; j < len; ++j) {
+      const dd r = two_sum(q, e[j]);
+      q = r.hi;
+      e[j] = r.lo;
+    }
+    e[len++] = q;
+  }
+  double x[4];
+  for (int k = 0; k < 4; ++k) {
+    double s = 0.0;
+    for (int j = 0; j < len; ++j) s += e[j];
+    x[k] = s;
+    double q = -s;
+    for (int j = 0; j < len; ++j) {
+      const dd r = two_sum(q, e[j]);
+      q = r.hi;
+      e[j] = r.lo;
+    }
+    e[len++] = q;
+  }
+  return {x[0], x[1], x[2], x[3]};
+}
+__device__ __forceinline__ qd qd_from(double a) { return {a, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ qd qd_neg(qd a) { return {-a.x0, -a.x1, -a.x2, -a.x3}; }
+__device__ __noinline__ qd qd_add(qd a, qd b) {
+  const double t[8] = {a.x0, a.x1, a.x2, a.x3, b.x0, b.x1, b.x2, b.x3};
+  return qd_round(t, 8);
+}
+// s a b + c (s = +1 or -1): the partial products a_i b_j with i + j <= 3 exactly
+// (two_prod), those with i + j = 4 rounded once, the rest (below 2^-260 of a b) dropped
+__device__ __noinline__ qd qd_fma(qd a, qd b, qd c, double s) {
+  const double A[4] = {s * a.x0, s * a.x1, s * a.x2, s * a.x3};
+  const double B[4] = {b.x0, b.x1, b.x2, b.x3};
+  double t[kQdMaxTerms];
+  int n = 0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; i + j <= 3; ++j) {
+      const dd p = two_prod(A[i], B[j]);
+      t[n++] = p.hi;
+      t[n++] = p.lo;
+    }
+  t[n++] = A[1] * B[3];
+  t[n++] = A[2] * B[2];
+  t[n++] = A[3] * B[1];
+  t[n++] = c.x0;
+  t[n++] = c.x1;
+  t[n++] = c.x2;
+  t[n++] = c.x3;
+  return qd_round(t, n);
+}
+__device__ __forceinline__ qd qd_mul(qd a, qd b) { return qd_fma(a, b, qd_from(0.0), 1.0); }
+// c + s b for a double s (exact products of s with b's components)
+__device__ __noinline__ qd qd_axpy_d(double s, qd b, qd c) {
+  double t[12];
+  const double B[4] = {b.x0, b.x1, b.x2, b.x3};
+  for (int j = 0; j < 4; ++j) {
+    const dd p = two_prod(s, B[j]);
+    t[2 * j] = p.hi;
+    t[2 * j + 1] = p.lo;
+  }
+  t[8] = c.x0;
+  t[9] = c.x1;
+  t[10] = c.x2;
+  t[11] = c.x3;
+  return qd_round(t, 12);
+}
+// a / b by long division: five quotient digits q_k = r_k / b_0, r_{k+1} = r_k - q_k b
+__device__ __noinline__ qd qd_div(qd a, qd b) {
+  double q[5];
+  qd r = a;
+  for (int k = 0; k < 5; ++k) {
+    q[k] = r.x0 / b.x0;
+    if (k < 4) r = qd_axpy_d(-q[k], b, r);
+  }
+  return qd_round(q, 5);
+}
+
 // ------------------------------------------------------- working number type
 // The TT kernels are written once over the number type T of a job: double, or
 // dd for the double-double path.  These overloads are the only arithmetic they
 // apply to T values; for double each is the plain operation (n_mad is one FMA).
 template <class T> struct is_dd_t { static constexpr bool value = false; };
 template <> struct is_dd_t<dd> { static constexpr bool value = true; };
+// the extended-precision types (double-double and quad-double)
+template <class T> struct is_ext_t { static constexpr bool value = false; };
+template <> struct is_ext_t<dd> { static constexpr bool value = true; };
+template <> struct is_ext_t<qd> { static constexpr bool value = true; };
 
 template <class T> __device__ __forceinline__ T num(double a);
 template <> __device__ __forceinline__ double num<double>(double a) { return a; }
 template <> __device__ __forceinline__ dd num<dd>(double a) { return {a, 0.0}; }
+template <> __device__ __forceinline__ qd num<qd>(double a) { return qd_from(a); }
 
 __device__ __forceinline__ double n_hi(double a) { return a; }
 __device__ __forceinline__ double n_hi(dd a) { return a.hi; }
@@ -109,6 +214,23 @@ __device__ __forceinline__ dd n_shfl(dd a, int lane) {
 __device__ __forceinline__ double n_shfl_xor(double a, int off) { return __shfl_xor(a, off, kWave); }
 __device__ __forceinline__ dd n_shfl_xor(dd a, int off) {
   return {__shfl_xor(a.hi, off, kWave), __shfl_xor(a.lo, off, kWave)};
+}
+// quad-double: the leading component is the hi part, the second the lo part
+__device__ __forceinline__ double n_hi(qd a) { return a.x0; }
+__device__ __forceinline__ double n_lo(qd a) { return a.x1; }
+__device__ __forceinline__ qd n_add(qd a, qd b) { return qd_add(a, b); }
+__device__ __forceinline__ qd n_sub(qd a, qd b) { return qd_add(a, qd_neg(b)); }
+__device__ __forceinline__ qd n_mul(qd a, qd b) { return qd_mul(a, b); }
+__device__ __forceinline__ qd n_div(qd a, qd b) { return qd_div(a, b); }
+__device__ __forceinline__ qd n_mad(qd a, qd b, qd c) { return qd_fma(a, b, c, 1.0); }
+__device__ __forceinline__ qd n_nmad(qd a, qd b, qd c) { return qd_fma(a, b, c, -1.0); }
+__device__ __forceinline__ qd n_ldexp(qd a, int e) { return {ldexp(a.x0, e), ldexp(a.x1, e), ldexp(a.x2, e), ldexp(a.x3, e)}; }
+__device__ __forceinline__ qd n_shfl(qd a, int lane) {
+  return {__shfl(a.x0, lane, kWave), __shfl(a.x1, lane, kWave), __shfl(a.x2, lane, kWave), __shfl(a.x3, lane, kWave)};
+}
+__device__ __forceinline__ qd n_shfl_xor(qd a, int off) {
+  return {__shfl_xor(a.x0, off, kWave), __shfl_xor(a.x1, off, kWave), __shfl_xor(a.x2, off, kWave),
+          __shfl_xor(a.x3, off, kWave)};
 }
 
 // ---------------------------------------------------------------- SplitMix64

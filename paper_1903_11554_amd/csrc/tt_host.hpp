@@ -53,6 +53,7 @@ struct tt_ctx {
     dd *t2, *w2;       // the same in double-double
     double* ws;        // weights times 2^weight_shift(n), the scale jobs fold in
     dd* ws2;
+    qd *t4, *w4, *ws4;  // quad-double tables, made on the first quad-double job of this n
   };
   std::map<int, GL> gl;                            // n -> device tables
   double* params = nullptr;                        // device scratch for synthetic params
@@ -152,8 +153,10 @@ inline tt_status validate(const tt_problem* p) {
   if (p->n_nodes < 1 || p->n_nodes > TT_MAX_NODES) return TT_EINVAL;
   if (p->rank_cap < 1 || p->rank_cap > TT_MAX_RANK) return TT_EINVAL;
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return TT_EINVAL;
-  if (p->precision != TT_FP64 && p->precision != TT_DD) return TT_EINVAL;
-  if (p->precision == TT_DD && fam_of(p->integrand) != FAM_PAPER) return TT_EINVAL;
+  if (p->precision != TT_FP64 && p->precision != TT_DD && p->precision != TT_QD) return TT_EINVAL;
+  if (p->precision != TT_FP64 && fam_of(p->integrand) != FAM_PAPER) return TT_EINVAL;
+  // quad-double: the register kernels of up to TT_QD_MAX_MODES modes and rank TT_QD_MAX_RANK
+  if (p->precision == TT_QD && (m > TT_QD_MAX_MODES || p->rank_cap > TT_QD_MAX_RANK)) return TT_EINVAL;
   // beyond the register bucket only the streaming kernels (double, paper form and synthetic)
   if (m > TT_MAX_REG_MODES && (p->precision != TT_FP64 || fam_of(p->integrand) == FAM_UFORM)) return TT_EINVAL;
   if (p->max_sweeps < 0 || p->max_sweeps > 1024) return TT_EINVAL;
@@ -189,7 +192,8 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   const int nb = m > 1 ? m - 1 : 0;
   const int ms = max_sweeps_of(p);
   // D: bytes of one value of the job's number type; plain doubles use sizeof(double)
-  const size_t D = p.precision == TT_DD ? sizeof(dd) : sizeof(double), I = sizeof(int32_t);
+  const size_t D = p.precision == TT_QD ? sizeof(qd) : p.precision == TT_DD ? sizeof(dd) : sizeof(double),
+               I = sizeof(int32_t);
   o.Lpar = L.take((size_t)nb * R * I);
   o.Lnode = L.take((size_t)nb * R * I);
   o.Rpar = L.take((size_t)nb * R * I);
@@ -229,28 +233,30 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
 inline int bucket_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : 32; }
 // Mode bucket of the sweep kernels of one integrand class and number type
 // (must match the instantiations in tt_inst.hip); 0 is the streaming bucket
-// for more modes than the register kernels hold.
-inline int bucket_m_for(int fam, bool dd, int m) {
+// for more modes than the register kernels hold.  prec: a tt_precision.
+inline int bucket_m_for(int fam, int prec, int m) {
   if (m > TT_MAX_REG_MODES) return 0;
-  if (fam == FAM_PAPER && !dd) return m <= 4 ? 4 : m <= 8 ? 8 : m <= 10 ? 10 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 24 ? 24 : 32;
+  if (prec == TT_QD) return 16;
+  if (fam == FAM_PAPER && prec == TT_FP64) return m <= 4 ? 4 : m <= 8 ? 8 : m <= 10 ? 10 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 24 ? 24 : 32;
   return bucket_m(m);
 }
 inline int bucket_r(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : 64; }
 // Every mode bucket instantiated for a class and number type (tt_inst.hip), the
 // streaming bucket 0 last where it exists.
-inline std::vector<int> mode_buckets(int fam, bool dd) {
+inline std::vector<int> mode_buckets(int fam, int prec) {
   std::vector<int> b;
-  if (fam == FAM_PAPER && !dd) b = {4, 8, 10, 12, 16, 24, 32};
+  if (prec == TT_QD) return {16};
+  if (fam == FAM_PAPER && prec == TT_FP64) b = {4, 8, 10, 12, 16, 24, 32};
   else b = {8, 16, 32};
-  if (!dd && fam != FAM_UFORM) b.push_back(0);
+  if (prec == TT_FP64 && fam != FAM_UFORM) b.push_back(0);
   return b;
 }
-inline std::array<int, 4> tune_key(int fam, bool dd, int maxm, int maxR) { return {fam, dd ? 1 : 0, maxm, maxR}; }
+inline std::array<int, 4> tune_key(int fam, int prec, int maxm, int maxR) { return {fam, prec, maxm, maxR}; }
 // A mode bucket a job of this class, precision and largest m can launch.
-inline bool variant_valid(int fam, bool dd, int maxm, int mb) {
-  if (mb == 0) return !dd && fam != FAM_UFORM;
+inline bool variant_valid(int fam, int prec, int maxm, int mb) {
+  if (mb == 0) return prec == TT_FP64 && fam != FAM_UFORM;
   if (maxm > TT_MAX_REG_MODES || mb < maxm) return false;
-  for (int b : mode_buckets(fam, dd))
+  for (int b : mode_buckets(fam, prec))
     if (b == mb) return true;
   return false;
 }
@@ -282,9 +288,10 @@ inline void fill_info(const ProbState& s, tt_info* out) {
 }
 
 // Node tables for n, generated on first use (defined in ttcross.hip).  With
-// want_dd the returned pointers are the double-double tables (as double*);
+// prec TT_DD or TT_QD the returned pointers are the double-double or
+// quad-double tables (as double*);
 // with scaled the weights are the rule's times 2^weight_shift(n) (exact).
-tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd = false, bool scaled = false);
+tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, int prec = TT_FP64, bool scaled = false);
 
 inline tt_status family_for(tt_ctx* ctx, const tt_problem* p, FamilyArgs* fa) {
   const int m = modes_of(*p);

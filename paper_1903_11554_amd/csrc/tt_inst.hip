@@ -10,14 +10,19 @@
 #ifndef TT_INST_DD
 #define TT_INST_DD 0
 #endif
-#if TT_INST_DD && TT_FAM != 0
-#error "the double-double kernels exist for the paper-form class only"
+#ifndef TT_INST_QD
+#define TT_INST_QD 0
+#endif
+#if (TT_INST_DD || TT_INST_QD) && TT_FAM != 0
+#error "the double-double and quad-double kernels exist for the paper-form class only"
 #endif
 
 namespace ttx {
 namespace {
 
-#if TT_INST_DD
+#if TT_INST_QD
+using Real = qd;
+#elif TT_INST_DD
 using Real = dd;
 #else
 using Real = double;
@@ -35,8 +40,8 @@ void by_rank(const LaunchArgs& a, int what, int rb) {
     hipLaunchKernelGGL((k_start<Real, TT_FAM, MAXM>), dim3(a.nprob), dim3(kBlock), 0, a.stream, a.desc);
     return;
   }
-  if (what == LAUNCH_ALS) {   // double precision only (the host rejects double-double jobs)
-#if !TT_INST_DD
+  if (what == LAUNCH_ALS) {   // double precision only (the host rejects the other precisions)
+#if !TT_INST_DD && !TT_INST_QD
     hipLaunchKernelGGL((k_als<TT_FAM, MAXM>), dim3(a.nprob), dim3(kSweepBlock), 0, a.stream, a.desc);
 #endif
     return;
@@ -47,10 +52,16 @@ void by_rank(const LaunchArgs& a, int what, int rb) {
     return;
   }
   switch (rb) {
+#if TT_INST_QD
+    case 8:
+    case 16: sweep<MAXM, 16>(a); break;
+    default: sweep<MAXM, 32>(a); break;   // quad-double ranks are at most 32
+#else
     case 8: sweep<MAXM, 8>(a); break;
     case 16: sweep<MAXM, 16>(a); break;
     case 32: sweep<MAXM, 32>(a); break;
     default: sweep<MAXM, 64>(a); break;
+#endif
   }
 }
 
@@ -60,7 +71,9 @@ void by_rank(const LaunchArgs& a, int what, int rb) {
 // the streaming path for more modes than the registers hold (double only,
 // paper-form and synthetic integrands).
 void dispatch(const LaunchArgs& a, int what, int rb) {
-#if TT_FAM == 0 && !TT_INST_DD
+#if TT_INST_QD
+  by_rank<16>(a, what, rb);   // quad-double: one mode bucket (compile time grows fast with each)
+#elif TT_FAM == 0 && !TT_INST_DD
   switch (a.mbucket) {
     case 0: by_rank<0>(a, what, rb); break;
     case 4: by_rank<4>(a, what, rb); break;
@@ -85,7 +98,9 @@ void dispatch(const LaunchArgs& a, int what, int rb) {
 
 }  // namespace
 
-#if TT_INST_DD
+#if TT_INST_QD
+void launch_paper_qd(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }
+#elif TT_INST_DD
 void launch_paper_dd(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }
 #elif TT_FAM == 0
 void launch_paper(const LaunchArgs& a, int what, int rb) { dispatch(a, what, rb); }

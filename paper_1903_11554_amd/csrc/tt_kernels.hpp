@@ -128,9 +128,9 @@ enum { FAM_PAPER = 0, FAM_UFORM = 1, FAM_SYNTH = 2, FAM_ANY = 3 };
 
 template <class T, int FAM, int MAXM>
 __device__ __forceinline__ T integrand_fam(const FamilyArgs& fa, const T (&y)[MAXM]) {
-  if constexpr (is_dd_t<T>::value) {
-    static_assert(FAM == FAM_PAPER, "the double-double path covers the paper-form integrands");
-    return ising_paper<dd, MAXM>(fa.family, fa.m, y);
+  if constexpr (is_ext_t<T>::value) {
+    static_assert(FAM == FAM_PAPER, "the extended-precision paths cover the paper-form integrands");
+    return ising_paper<T, MAXM>(fa.family, fa.m, y);
   } else if constexpr (FAM == FAM_PAPER) {
     return ising_paper<double, MAXM>(fa.family, fa.m, y);
   } else if constexpr (FAM == FAM_UFORM) {
@@ -190,6 +190,9 @@ __device__ __forceinline__ T normalise(T v, int& e) {
 template <class T> __device__ __forceinline__ T* tp(double* p) { return reinterpret_cast<T*>(p); }
 template <class T> __device__ __forceinline__ const T* tp(const double* p) { return reinterpret_cast<const T*>(p); }
 
+// the largest rank a job of number type T can have (quad-double jobs: TT_QD_MAX_RANK)
+template <class T> constexpr int max_rank_of() { return sizeof(T) > 16 ? TT_QD_MAX_RANK : TT_MAX_RANK; }
+
 __device__ __forceinline__ int rowcap(const ProbDesc& p, int c) { return c == 0 ? 1 : p.R; }
 __device__ __forceinline__ int colcap(const ProbDesc& p, int c) { return c == p.m - 1 ? 1 : p.R; }
 
@@ -245,6 +248,50 @@ __device__ inline void gl_node(int n, int k, dd& t_out, dd& w_out) {
   dd wk = dd_div(dd_from(1.0), dd_mul(one_m_x2, dd_mul(dp, dp)));   // = w_x / 2
   t_out = dd_mul_d(dd_add(X, dd_from(1.0)), 0.5);
   w_out = wk;
+}
+
+// Quad-double nodes and weights: two Newton steps in quad-double from the
+// double-double root (each step doubles the correct digits), then the weight
+// 1/((1-x^2) P_n'(x)^2) in quad-double.
+__device__ inline void legendre_qd(int n, qd x, qd& pn, qd& pn1) {
+  qd p0 = qd_from(1.0), p1 = x;
+  if (n == 0) { pn = p0; pn1 = qd_from(0.0); return; }
+  for (int k = 1; k < n; ++k) {
+    // P_{k+1} = ((2k+1) x P_k - k P_{k-1}) / (k+1)
+    const qd a = qd_axpy_d((double)(2 * k + 1), qd_mul(x, p1), qd_from(0.0));
+    const qd p2 = qd_div(qd_axpy_d(-(double)k, p0, a), qd_from((double)(k + 1)));
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  pn1 = p0;
+}
+
+__device__ inline void gl_node_qd(int n, int k, qd& t_out, qd& w_out) {
+  dd t2, w2;
+  gl_node(n, k, t2, w2);
+  // x = 2 t - 1 from the double-double node (exact)
+  qd X = qd_add(qd{2.0 * t2.hi, 2.0 * t2.lo, 0.0, 0.0}, qd_from(-1.0));
+  qd pn, pn1, dp, x2m1;
+  for (int it = 0; it < 3; ++it) {
+    legendre_qd(n, X, pn, pn1);
+    x2m1 = qd_add(qd_mul(X, X), qd_from(-1.0));
+    // P_n'(x) = n (x P_n - P_{n-1}) / (x^2 - 1)
+    dp = qd_div(qd_axpy_d((double)n, qd_add(qd_mul(X, pn), qd_neg(pn1)), qd_from(0.0)), x2m1);
+    if (it < 2) X = qd_add(X, qd_neg(qd_div(pn, dp)));
+  }
+  w_out = qd_div(qd_from(1.0), qd_mul(qd_neg(x2m1), qd_mul(dp, dp)));   // = w_x / 2
+  t_out = n_ldexp(qd_add(X, qd_from(1.0)), -1);
+}
+
+static __global__ void k_gl_qd(int n, qd* __restrict__ t4, qd* __restrict__ w4, int shift, qd* __restrict__ ws4) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    qd tk, wk;
+    gl_node_qd(n, k, tk, wk);
+    t4[n - 1 - k] = tk;   // increasing order
+    w4[n - 1 - k] = wk;
+    ws4[n - 1 - k] = n_ldexp(wk, shift);
+  }
 }
 
 // ws, ws2: the weights times 2^shift (exact), the scale a job folds in
@@ -467,11 +514,11 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
 // ------------------------------------------------------------ search (Alg. 2)
 template <class T, int MAXM>
 struct SearchSmem {
-  T Lx[TT_MAX_RANK * (MAXM + 1)];
-  T Rx[TT_MAX_RANK * (MAXM + 1)];
-  T Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
+  T Lx[max_rank_of<T>() * (MAXM + 1)];
+  T Rx[max_rank_of<T>() * (MAXM + 1)];
+  T Lw[max_rank_of<T>()], Rw[max_rank_of<T>()];
   T t[TT_MAX_NODES], w[TT_MAX_NODES];
-  T vec[TT_MAX_RANK];
+  T vec[max_rank_of<T>()];
   // streaming C_d: B_d's running (P, q, s) over each left row and (P, q, g) over
   // each right row (g: the suffix recurrence started from zero)
   double sL[MAXM == 0 ? 3 * TT_MAX_RANK : 1], sR[MAXM == 0 ? 3 * TT_MAX_RANK : 1];
@@ -750,9 +797,9 @@ template <class T, int MAXM, int RMAX>
 struct UpdateSmem {
   union {
     struct {                       // fibre evaluation stage
-      T Lx[TT_MAX_RANK * (MAXM + 1)];
-      T Rx[TT_MAX_RANK * (MAXM + 1)];
-      T Lw[TT_MAX_RANK], Rw[TT_MAX_RANK];
+      T Lx[max_rank_of<T>() * (MAXM + 1)];
+      T Rx[max_rank_of<T>() * (MAXM + 1)];
+      T Lw[max_rank_of<T>()], Rw[max_rank_of<T>()];
       T t[TT_MAX_NODES], w[TT_MAX_NODES];
       // streaming C_d: row summaries of I_<=c-1 and of the new rows of I_>c
       double sL[MAXM == 0 ? 3 * TT_MAX_RANK : 1], sR[MAXM == 0 ? 3 * TT_MAX_RANK : 1];
@@ -769,9 +816,13 @@ struct UpdateSmem {
 
 // |C_c| above which a core's interpolation core is recomputed (see update_core):
 // an incremental step amplifies the rounding already in C_c by about |C_c|^2, so
-// at 16 a step adds at most ~256 eps; the Ising crosses of the benchmark stay
-// below 5, while C_d with few nodes reaches 1e10.
-constexpr double kDominance = 16.0;
+// at 16 a double step adds at most ~256 eps (3e-14); the Ising crosses of the
+// benchmark stay below 5, while C_d with few nodes reaches 1e10.  Double-double
+// and quad-double values carry 2^-104 and 2^-204 rounding: at 1024 a step adds
+// at most 5e-26 and 1e-55, below the tolerances those jobs are run at, and the
+// rank-64 crosses of D_11 and D_12 with 128 nodes (|C_c| between 16 and 1024)
+// keep their incremental updates.
+template <class T> constexpr double dominance_of() { return sizeof(T) > sizeof(double) ? 1024.0 : 16.0; }
 
 // running max of |x| for the dominance test; a non-finite x counts as infinite
 __device__ __forceinline__ double cmax_of(double cmax, double x) {
@@ -786,6 +837,7 @@ __device__ __forceinline__ double cmax_of(double cmax, double x) {
 // nonzero pivot.  Every thread of the workgroup calls it; a barrier follows.
 template <int RMAX, class Smem>
 __device__ __forceinline__ void lu_pivoted(const int r, Smem& sm) {
+  using T = typename std::remove_reference<decltype(sm.A[0])>::type;
   constexpr int LA = RMAX + 1;
   const int tid = threadIdx.x;
   if (tid < kWave) {   // the elimination runs in wave 0 alone, with wave-level ordering only
@@ -796,7 +848,7 @@ __device__ __forceinline__ void lu_pivoted(const int r, Smem& sm) {
       ArgMax a{-1.0, 0x7fffffff};
       const int i = k + tid;
       if (i < r) {
-        a.v = fabs(sm.A[i * LA + k]);
+        a.v = fabs(n_hi(sm.A[i * LA + k]));
         a.idx = i;
       }
       a = wave_argmax(a);
@@ -805,7 +857,7 @@ __device__ __forceinline__ void lu_pivoted(const int r, Smem& sm) {
       const int pi = a.idx;
       if (pi != k) {
         if (tid < r) {
-          const double tmp = sm.A[k * LA + tid];
+          const T tmp = sm.A[k * LA + tid];
           sm.A[k * LA + tid] = sm.A[pi * LA + tid];
           sm.A[pi * LA + tid] = tmp;
         }
@@ -819,14 +871,14 @@ __device__ __forceinline__ void lu_pivoted(const int r, Smem& sm) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const int i2 = k + 1 + tid;           // multipliers of the rows below, stored in place (L)
-      if (i2 < r) sm.A[i2 * LA + k] = sm.A[i2 * LA + k] / sm.A[k * LA + k];
+      if (i2 < r) sm.A[i2 * LA + k] = n_div(sm.A[i2 * LA + k], sm.A[k * LA + k]);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const int w = r - k - 1;
       for (int e = tid; e < w * w; e += kWave) {
         const int i3 = k + 1 + e / w, j = k + 1 + e % w;
-        sm.A[i3 * LA + j] = fma(-sm.A[i3 * LA + k], sm.A[k * LA + j], sm.A[i3 * LA + j]);
+        sm.A[i3 * LA + j] = n_nmad(sm.A[i3 * LA + k], sm.A[k * LA + j], sm.A[i3 * LA + j]);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -842,6 +894,7 @@ __device__ __forceinline__ void lu_pivoted(const int r, Smem& sm) {
 // xat(q, row) is unknown q of that row's solution (read and written in place).
 template <int RMAX, class Smem, class FGet, class XAt>
 __device__ __forceinline__ void solve_rows(const int r, const int N, Smem& sm, FGet&& fget, XAt&& xat) {
+  using T = typename std::remove_reference<decltype(sm.A[0])>::type;
   constexpr int LA = RMAX + 1;
   const int tid = threadIdx.x;
   // Row solves in blocks of kB unknowns held in registers: the earlier (forward)
@@ -852,44 +905,44 @@ __device__ __forceinline__ void solve_rows(const int r, const int N, Smem& sm, F
   for (int row = tid; row < N; row += blockDim.x) {
 #pragma unroll 1
     for (int q0 = 0; q0 < r; q0 += kB) {   // L y = P f (unit lower)
-      double acc[kB];
+      T acc[kB];
 #pragma unroll
-      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? fget(row, sm.perm[q0 + t]) : 0.0;
+      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? fget(row, sm.perm[q0 + t]) : num<T>(0.0);
 #pragma unroll 1
       for (int pp = 0; pp < q0; ++pp) {
-        const double y = xat(pp, row);
+        const T y = xat(pp, row);
 #pragma unroll
         for (int t = 0; t < kB; ++t)
-          if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + pp], y, acc[t]);
+          if (q0 + t < r) acc[t] = n_nmad(sm.A[(q0 + t) * LA + pp], y, acc[t]);
       }
 #pragma unroll
       for (int t = 1; t < kB; ++t)
 #pragma unroll
         for (int u = 0; u < t; ++u)
-          if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + q0 + u], acc[u], acc[t]);
+          if (q0 + t < r) acc[t] = n_nmad(sm.A[(q0 + t) * LA + q0 + u], acc[u], acc[t]);
 #pragma unroll
       for (int t = 0; t < kB; ++t)
         if (q0 + t < r) xat(q0 + t, row) = acc[t];
     }
 #pragma unroll 1
     for (int q0 = ((r - 1) / kB) * kB; q0 >= 0; q0 -= kB) {   // U x = y
-      double acc[kB];
+      T acc[kB];
 #pragma unroll
-      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? xat(q0 + t, row) : 0.0;
+      for (int t = 0; t < kB; ++t) acc[t] = (q0 + t < r) ? xat(q0 + t, row) : num<T>(0.0);
 #pragma unroll 1
       for (int pp = q0 + kB; pp < r; ++pp) {
-        const double x = xat(pp, row);
+        const T x = xat(pp, row);
 #pragma unroll
         for (int t = 0; t < kB; ++t)
-          if (q0 + t < r) acc[t] = fma(-sm.A[(q0 + t) * LA + pp], x, acc[t]);
+          if (q0 + t < r) acc[t] = n_nmad(sm.A[(q0 + t) * LA + pp], x, acc[t]);
       }
 #pragma unroll
       for (int t = kB - 1; t >= 0; --t)
         if (q0 + t < r) {
 #pragma unroll
           for (int u = t + 1; u < kB; ++u)
-            if (q0 + u < r) acc[t] = fma(-sm.A[(q0 + t) * LA + q0 + u], acc[u], acc[t]);
-          acc[t] = acc[t] / sm.A[(q0 + t) * LA + q0 + t];
+            if (q0 + u < r) acc[t] = n_nmad(sm.A[(q0 + t) * LA + q0 + u], acc[u], acc[t]);
+          acc[t] = n_div(acc[t], sm.A[(q0 + t) * LA + q0 + t]);
         }
 #pragma unroll
       for (int t = 0; t < kB; ++t)
@@ -898,7 +951,7 @@ __device__ __forceinline__ void solve_rows(const int r, const int N, Smem& sm, F
   }
 }
 
-// C_c = F_c M_c^-1 from scratch (double precision): M_c = F_c(I_<=c, :r), the
+// C_c = F_c M_c^-1 from scratch (in the job's number type): M_c = F_c(I_<=c, :r), the
 // old cross rows sm.rowidx[0..r0) and, when a pivot was accepted this sweep,
 // prow.  With A = M_c^T, Gaussian elimination with partial pivoting gives
 // P A = L U in LDS (lu_pivoted); every row f of F_c is then solved by the
@@ -907,10 +960,10 @@ __device__ __forceinline__ void solve_rows(const int r, const int N, Smem& sm, F
 // of the factors, so C_c(I_<=c, :) stays the identity to rounding even for a
 // nearly singular cross).  Loops are kept rolled so the routine adds few
 // registers to the sweep kernel.  Marks the core for later sweeps.
-template <int RMAX, class Smem>
+template <int RMAX, class T, class Smem>
 __device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, const int r, const int N, const int prow,
-                                             const int r0, const double* __restrict__ Fc, const int cc,
-                                             double* __restrict__ Cc, const size_t ldC, Smem& sm) {
+                                             const int r0, const T* __restrict__ Fc, const int cc,
+                                             T* __restrict__ Cc, const size_t ldC, Smem& sm) {
   constexpr int LA = RMAX + 1;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -928,7 +981,7 @@ __device__ __forceinline__ void refresh_core(const ProbDesc& p, const int c, con
   lu_pivoted<RMAX>(r, sm);
   if (tid == 0 && sm.zf) atomicOr(&p.st->err_flags, 2);
   solve_rows<RMAX>(r, N, sm, [&](int row, int q) { return Fc[(size_t)row * cc + q]; },
-                   [&](int q, int row) -> double& { return Cc[(size_t)q * ldC + row]; });
+                   [&](int q, int row) -> T& { return Cc[(size_t)q * ldC + row]; });
   __syncthreads();
 }
 
@@ -1125,14 +1178,12 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
   T* __restrict__ Cc = tp<T>(p.C) + p.Coff[c];
   const size_t ldC = (size_t)rowcap(p, c) * n;
   __syncthreads();   // the evaluation stage's LDS is reused below
-  double cmax = 0.0;   // largest |entry| of C_c written below (double jobs)
+  double cmax = 0.0;   // largest |entry| of C_c written below
   bool sing = false;   // a zero pivot in the incremental steps
   if (init == 2) {   // every entry re-evaluated on refreshed sets: C_c from F_c with a pivoted solve
-    if constexpr (!is_dd_t<T>::value) {
-      if (tid < r) sm.rowidx[tid] = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
-      __syncthreads();
-      refresh_core<RMAX>(p, c, r, N, -1, r, Fc, cc, Cc, ldC, sm);
-    }
+    if (tid < r) sm.rowidx[tid] = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
+    __syncthreads();
+    refresh_core<RMAX>(p, c, r, N, -1, r, Fc, cc, Cc, ldC, sm);
   } else if (init) {   // rank 1: M_c = (B(i0)), C_c = F_c / M_c
     const int row0 = p.Lpar[(size_t)c * R] * n + p.Lnode[(size_t)c * R];
     const T m00 = Fc[(size_t)row0 * cc];
@@ -1232,8 +1283,7 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
         for (int k = 0; k < r0; ++k) e = n_nmad(sm.cp[k], sm.u[k], e);
         LU[(size_t)r0 * R + r0] = e;
         sm.delta = e;
-        // a double job recomputes the core instead (below); double-double flags it
-        if (n_hi(e) == 0.0 && is_dd_t<T>::value) atomicOr(&st->err_flags, 2);
+        // a zero pivot leaves C_c non-finite: the core is then recomputed (below)
       }
       __syncthreads();
       if (mb >= 0) mark(p, msw, mb, 12);
@@ -1276,27 +1326,24 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     if (mb >= 0) mark(p, msw, mb, 13);
     // the largest |C_c| written (infinite for a zero pivot): one value per wave,
     // combined after the barrier below
-    if constexpr (!is_dd_t<T>::value) {
-      const double cm = wave_max(sing ? __builtin_huge_val() : cmax);
-      if ((tid & (kWave - 1)) == 0) sm.rv[tid / kWave] = cm;
-    }
+    const double cm = wave_max(sing ? __builtin_huge_val() : cmax);
+    if ((tid & (kWave - 1)) == 0) sm.rv[tid / kWave] = cm;
   }
   __syncthreads();
-  // ---- recomputation of C_c for crosses far from dominant (double jobs).  The
+  // ---- recomputation of C_c for crosses far from dominant.  The
   //      incremental steps above are exact algebra, but each carries the rounding
   //      already in C_c over with a factor of about |C_c|^2.  Alg. 6 takes each
   //      bond's pivot against the neighbours' previous sets, and on some
   //      integrands (C_d with few nodes) the crosses lose dominance, |C_c|
-  //      reaching 1e4 within a few sweeps.  Once |C_c| exceeds kDominance (or a
+  //      reaching 1e4 within a few sweeps.  Once |C_c| exceeds dominance_of<T>() (or a
   //      pivot is zero) the core is recomputed from F_c with a pivoted LU of the
-  //      cross in this and every later sweep, as the plain definition does.
-  if constexpr (!is_dd_t<T>::value) {
-    if (!init) {
-      double cm = 0.0;
-      for (int w = 0; w < kSweepBlock / kWave; ++w) cm = fmax(cm, sm.rv[w]);
-      if (p.rfl[c] || !(cm <= kDominance))
-        refresh_core<RMAX>(p, c, r, N, accR ? p.piv[c].row : -1, r0, Fc, cc, Cc, ldC, sm);
-    }
+  //      cross in this and every later sweep, as the plain definition does
+  //      (double and double-double jobs alike).
+  if (!init) {
+    double cm = 0.0;
+    for (int w = 0; w < kSweepBlock / kWave; ++w) cm = fmax(cm, sm.rv[w]);
+    if (p.rfl[c] || !(cm <= dominance_of<T>()))
+      refresh_core<RMAX>(p, c, r, N, accR ? p.piv[c].row : -1, r0, Fc, cc, Cc, ldC, sm);
   }
   // ---- S_c(alpha, k) = sum_i C_c(alpha, i, k)
   for (int e = tid; e < rL_new * r; e += blockDim.x) {
@@ -1546,8 +1593,9 @@ constexpr int kIntStageBytes = 49152;   // S staged in LDS at once
 
 template <class T>
 struct IntSmem {
-  static constexpr int kStage = kIntStageBytes / (int)sizeof(T) > TT_MAX_RANK * (TT_MAX_RANK + 1)
-                                     ? kIntStageBytes / (int)sizeof(T) : TT_MAX_RANK * (TT_MAX_RANK + 1);
+  static constexpr int kMaxR = max_rank_of<T>();
+  static constexpr int kStage = kIntStageBytes / (int)sizeof(T) > kMaxR * (kMaxR + 1)
+                                     ? kIntStageBytes / (int)sizeof(T) : kMaxR * (kMaxR + 1);
   static constexpr int kIntBatch = 6;   // staging loads (of one double) in flight per thread
   T v[kWave], v2[kWave];
   T stage[kStage];

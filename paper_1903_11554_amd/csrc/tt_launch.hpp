@@ -27,5 +27,6 @@ void launch_uform(const LaunchArgs& a, int what, int rbucket);
 void launch_synth(const LaunchArgs& a, int what, int rbucket);
 void launch_any(const LaunchArgs& a, int what, int rbucket);
 void launch_paper_dd(const LaunchArgs& a, int what, int rbucket);   // double-double, paper form
+void launch_paper_qd(const LaunchArgs& a, int what, int rbucket);   // quad-double, paper form
 
 }  // namespace ttx

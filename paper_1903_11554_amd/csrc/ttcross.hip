@@ -37,6 +37,8 @@ struct tt_job {
   int maxm = 0, maxR = 1;
   int fam = 3;            // integrand class the job's kernels are specialised for
   bool dd = false;        // double-double job
+  bool qd = false;        // quad-double job
+  int prec = TT_FP64;     // the job's tt_precision
   bool full_bucket = false;   // sweeps were enqueued for graph capture: size kernels for the rank caps
   int mbucket = 0;            // mode bucket of the job's kernels (the rule's, or a tuned one)
   int rank_policy = 0;        // 1: every sweep kernel sized for the rank caps (tuned)
@@ -51,12 +53,13 @@ struct tt_job {
 };
 
 namespace ttx_host {
-// Node tables for n, generated on first use.  With want_dd the returned
-// pointers are the double-double tables (reinterpreted as double*).
-tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd, bool scaled) {
+// Node tables for n, generated on first use.  With prec TT_DD or TT_QD the
+// returned pointers are the double-double or quad-double tables (reinterpreted
+// as double*); the quad-double ones are made on their first request.
+tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, int prec, bool scaled) {
   auto it = ctx->gl.find(n);
   if (it == ctx->gl.end()) {
-    tt_ctx::GL g{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    tt_ctx::GL g{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // inserted first so that tt_ctx_destroy frees whatever was allocated
     it = ctx->gl.emplace(n, g).first;
     tt_ctx::GL& e = it->second;
@@ -73,12 +76,27 @@ tt_status gl_table(tt_ctx* ctx, int n, double** t, double** w, bool want_dd, boo
     }
     TT_HIP(hipGetLastError());
   }
-  const tt_ctx::GL& g = it->second;
-  *t = want_dd ? reinterpret_cast<double*>(g.t2) : g.t;
-  if (scaled)
-    *w = want_dd ? reinterpret_cast<double*>(g.ws2) : g.ws;
-  else
-    *w = want_dd ? reinterpret_cast<double*>(g.w2) : g.w;
+  tt_ctx::GL& g = it->second;
+  if (prec == TT_QD && !g.t4) {
+    TT_HIP(hipMalloc(&g.t4, n * sizeof(qd)));
+    TT_HIP(hipMalloc(&g.w4, n * sizeof(qd)));
+    TT_HIP(hipMalloc(&g.ws4, n * sizeof(qd)));
+    {
+      Timed tm(ctx, KK_GL);
+      hipLaunchKernelGGL(k_gl_qd, dim3((n + 63) / 64), dim3(64), 0, ctx->stream, n, g.t4, g.w4, weight_shift(n), g.ws4);
+    }
+    TT_HIP(hipGetLastError());
+  }
+  if (prec == TT_QD) {
+    *t = reinterpret_cast<double*>(g.t4);
+    *w = reinterpret_cast<double*>(scaled ? g.ws4 : g.w4);
+  } else if (prec == TT_DD) {
+    *t = reinterpret_cast<double*>(g.t2);
+    *w = reinterpret_cast<double*>(scaled ? g.ws2 : g.w2);
+  } else {
+    *t = g.t;
+    *w = scaled ? g.ws : g.w;
+  }
   return TT_OK;
 }
 
@@ -121,6 +139,10 @@ void launch(tt_job* j, int what, int rb) {
                                           : KK_UPDATE);
   if (j->dd) {
     launch_paper_dd(a, what, rb);
+    return;
+  }
+  if (j->qd) {
+    launch_paper_qd(a, what, rb);
     return;
   }
   switch (j->fam) {
@@ -319,12 +341,14 @@ static void tune_load(tt_ctx* c) {
   char line[256];
   while (std::fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
-    int fam, dd, maxm, maxR, mb, pol;
+    int fam, prec, maxm, maxR, mb, pol;
     double rule_ms, tuned_ms;
-    if (std::sscanf(line, "%d %d %d %d %d %d %lf %lf", &fam, &dd, &maxm, &maxR, &mb, &pol, &rule_ms, &tuned_ms) != 8)
+    if (std::sscanf(line, "%d %d %d %d %d %d %lf %lf", &fam, &prec, &maxm, &maxR, &mb, &pol, &rule_ms, &tuned_ms) != 8)
       continue;
-    if (fam < FAM_PAPER || fam > FAM_ANY || (pol != 0 && pol != 1) || !variant_valid(fam, dd != 0, maxm, mb)) continue;
-    c->tune[tune_key(fam, dd != 0, maxm, maxR)] = tt_ctx::Tuned{mb, pol, rule_ms, tuned_ms};
+    if (fam < FAM_PAPER || fam > FAM_ANY || prec < TT_FP64 || prec > TT_QD || (pol != 0 && pol != 1) ||
+        !variant_valid(fam, prec, maxm, mb))
+      continue;
+    c->tune[tune_key(fam, prec, maxm, maxR)] = tt_ctx::Tuned{mb, pol, rule_ms, tuned_ms};
   }
   std::fclose(f);
 }
@@ -334,7 +358,7 @@ static tt_status tune_save(tt_ctx* c) {
   const std::string tmp = c->tune_path + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return TT_EDEVICE;
-  std::fprintf(f, "# ttcross kernel variants: class dd max_modes max_rank mode_bucket rank_policy rule_ms tuned_ms\n");
+  std::fprintf(f, "# ttcross kernel variants: class precision max_modes max_rank mode_bucket rank_policy rule_ms tuned_ms\n");
   for (const auto& e : c->tune)
     std::fprintf(f, "%d %d %d %d %d %d %.6f %.6f\n", e.first[0], e.first[1], e.first[2], e.first[3],
                  e.second.mbucket, e.second.rank_policy, e.second.rule_ms, e.second.tuned_ms);
@@ -400,6 +424,9 @@ void tt_ctx_destroy(tt_ctx* c) {
     hipFree(kv.second.w2);
     hipFree(kv.second.ws);
     hipFree(kv.second.ws2);
+    if (kv.second.t4) hipFree(kv.second.t4);
+    if (kv.second.w4) hipFree(kv.second.w4);
+    if (kv.second.ws4) hipFree(kv.second.ws4);
   }
   if (c->params) hipFree(c->params);
   for (auto& kv : c->arenas) hipFree(kv.second);
@@ -446,11 +473,11 @@ tt_status tt_autotune(tt_ctx* ctx, const tt_problem* problems, int32_t count, in
     maxm = std::max(maxm, modes_of(problems[k]));
     maxR = std::max(maxR, problems[k].rank_cap);
   }
-  const bool dd = problems[0].precision == TT_DD;
-  const int rule_mb = bucket_m_for(fam, dd, maxm);
+  const int prec = problems[0].precision;
+  const int rule_mb = bucket_m_for(fam, prec, maxm);
   std::vector<std::pair<int, int>> cands{{rule_mb, 0}, {rule_mb, 1}};
-  for (int mb : mode_buckets(fam, dd))
-    if (mb != rule_mb && variant_valid(fam, dd, maxm, mb)) {
+  for (int mb : mode_buckets(fam, prec))
+    if (mb != rule_mb && variant_valid(fam, prec, maxm, mb)) {
       cands.push_back({mb, 0});
       cands.push_back({mb, 1});
     }
@@ -500,7 +527,7 @@ tt_status tt_autotune(tt_ctx* ctx, const tt_problem* problems, int32_t count, in
       best_ms = med;
     }
   }
-  ctx->tune[tune_key(fam, dd, maxm, maxR)] = tt_ctx::Tuned{cands[best].first, cands[best].second, rule_ms, best_ms};
+  ctx->tune[tune_key(fam, prec, maxm, maxR)] = tt_ctx::Tuned{cands[best].first, cands[best].second, rule_ms, best_ms};
   out->mode_bucket = cands[best].first;
   out->rank_policy = cands[best].second;
   out->rule_mode_bucket = rule_mb;
@@ -540,13 +567,15 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->ctx = ctx;
   j->nprob = count;
   j->probs.assign(problems, problems + count);
-  j->dd = problems[0].precision == TT_DD;
+  j->prec = problems[0].precision;
+  j->dd = j->prec == TT_DD;
+  j->qd = j->prec == TT_QD;
   // Gauss--Legendre tables are computed once per node count and shared by all jobs of the context
   std::vector<std::pair<double*, double*>> gl(count);
   j->gl64.resize(count);
   for (int k = 0; k < count; ++k) {
     tt_status s = gl_table(ctx, problems[k].n_nodes, &j->gl64[k].first, &j->gl64[k].second);
-    if (s == TT_OK) s = gl_table(ctx, problems[k].n_nodes, &gl[k].first, &gl[k].second, j->dd, true);
+    if (s == TT_OK) s = gl_table(ctx, problems[k].n_nodes, &gl[k].first, &gl[k].second, j->prec, true);
     if (s != TT_OK) {
       delete j;
       return s;
@@ -568,13 +597,13 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
     }
   }
   // kernel variant: the rule's, a tuned one recorded in the context, or tt_autotune's candidate
-  j->mbucket = bucket_m_for(j->fam, j->dd, j->maxm);
+  j->mbucket = bucket_m_for(j->fam, j->prec, j->maxm);
   if (ctx->force_variant) {
     j->mbucket = ctx->forced.mbucket;
     j->rank_policy = ctx->forced.rank_policy;
   } else {
-    auto t = ctx->tune.find(tune_key(j->fam, j->dd, j->maxm, j->maxR));
-    if (t != ctx->tune.end() && variant_valid(j->fam, j->dd, j->maxm, t->second.mbucket)) {
+    auto t = ctx->tune.find(tune_key(j->fam, j->prec, j->maxm, j->maxR));
+    if (t != ctx->tune.end() && variant_valid(j->fam, j->prec, j->maxm, t->second.mbucket)) {
       j->mbucket = t->second.mbucket;
       j->rank_policy = t->second.rank_policy;
     }
@@ -648,7 +677,9 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   if (j->ncore > 0) {
     enqueue_update(j, 4, 1);
     Timed tm(ctx, KK_INTEGRAL);
-    if (j->dd)
+    if (j->qd)
+      hipLaunchKernelGGL(k_integral<qd>, dim3(count), dim3(kIntBlock), 0, ctx->stream, j->ddesc, 1);
+    else if (j->dd)
       hipLaunchKernelGGL(k_integral<dd>, dim3(count), dim3(kIntBlock), 0, ctx->stream, j->ddesc, 1);
     else
       hipLaunchKernelGGL(k_integral<double>, dim3(count), dim3(kIntBlock), 0, ctx->stream, j->ddesc, 1);
@@ -677,7 +708,7 @@ tt_status tt_cross_sweep(tt_job* j, int32_t n_sweeps, tt_info* info) {
 }
 
 tt_status tt_cross_refresh(tt_job* j, tt_info* info) {
-  if (!j || j->dd) return TT_EINVAL;
+  if (!j || j->prec != TT_FP64) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(j->ctx->mu);
   TT_HIP(hipSetDevice(j->ctx->device));
   if (j->nbond > 0) {
@@ -802,7 +833,11 @@ tt_status tt_job_history(tt_job* j, int32_t k, double* values, double* values_lo
   // the device keeps mantissas and exponents
   std::vector<dd> h(nv);
   std::vector<int32_t> e(nv);
-  if (j->dd) {
+  if (j->qd) {
+    std::vector<qd> h4(nv);
+    TT_HIP(hipMemcpy(h4.data(), j->hdesc[k].hist, nv * sizeof(qd), hipMemcpyDeviceToHost));
+    for (int64_t q = 0; q < nv; ++q) h[q] = dd{h4[q].x0, h4[q].x1};
+  } else if (j->dd) {
     TT_HIP(hipMemcpy(h.data(), j->hdesc[k].hist, nv * sizeof(dd), hipMemcpyDeviceToHost));
   } else {
     std::vector<double> h1(nv);
@@ -914,6 +949,46 @@ tt_status tt_job_nodes(tt_job* j, int32_t k, double* t, double* w, double* t_lo,
   return TT_OK;
 }
 
+tt_status tt_job_history_parts(tt_job* j, int32_t k, int32_t parts, double* values, int32_t* exp2,
+                               int64_t capacity, int64_t* written) {
+  if (!j || k < 0 || k >= j->nprob || parts < 1 || parts > 4 || !values || !exp2 || !written) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  std::vector<ProbState> st;
+  tt_status s = read_states(j, st);
+  if (s != TT_OK) return s;
+  const int64_t nv = st[k].sweeps + 1;
+  if (nv > capacity) return TT_EINVAL;
+  const int np = j->qd ? 4 : j->dd ? 2 : 1;   // components stored per value
+  std::vector<double> h((size_t)nv * np);
+  TT_HIP(hipMemcpy(h.data(), j->hdesc[k].hist, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(exp2, j->hdesc[k].hexp, nv * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int64_t q = 0; q < nv; ++q)
+    for (int c = 0; c < parts; ++c) values[q * parts + c] = c < np ? h[(size_t)q * np + c] : 0.0;
+  *written = nv;
+  return TT_OK;
+}
+
+tt_status tt_job_nodes_parts(tt_job* j, int32_t k, int32_t parts, double* t, double* w) {
+  if (!j || k < 0 || k >= j->nprob || parts < 1 || parts > 4 || !t || !w) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(j->ctx->mu);
+  TT_HIP(hipStreamSynchronize(j->ctx->stream));
+  const ProbDesc& d = j->hdesc[k];
+  const tt_ctx::GL& g = j->ctx->gl.at(d.n);
+  // the unscaled tables of the job's precision: 1, 2 or 4 components per value
+  const int np = j->qd ? 4 : j->dd ? 2 : 1;
+  const double* st = j->qd ? (const double*)g.t4 : j->dd ? (const double*)g.t2 : g.t;
+  const double* sw = j->qd ? (const double*)g.w4 : j->dd ? (const double*)g.w2 : g.w;
+  std::vector<double> ht((size_t)d.n * np), hw((size_t)d.n * np);
+  TT_HIP(hipMemcpy(ht.data(), st, ht.size() * sizeof(double), hipMemcpyDeviceToHost));
+  TT_HIP(hipMemcpy(hw.data(), sw, hw.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < d.n; ++i)
+    for (int c = 0; c < parts; ++c) {
+      t[i * parts + c] = c < np ? ht[(size_t)i * np + c] : 0.0;
+      w[i * parts + c] = c < np ? hw[(size_t)i * np + c] : 0.0;
+    }
+  return TT_OK;
+}
+
 tt_status tt_job_core(tt_job* j, int32_t k, int32_t c, double* F, double* C, int64_t capacity, int32_t* rows,
                       int32_t* cols) {
   if (!j || k < 0 || k >= j->nprob || !F || !rows || !cols) return TT_EINVAL;
@@ -928,7 +1003,7 @@ tt_status tt_job_core(tt_job* j, int32_t k, int32_t c, double* F, double* C, int
   const int64_t nr = (int64_t)rl * n;
   if (nr * rr > capacity) return TT_EINVAL;
   const int rowcap = c == 0 ? 1 : R, colcap = c == m - 1 ? 1 : R;
-  const size_t es = j->dd ? sizeof(dd) : sizeof(double);
+  const size_t es = j->qd ? sizeof(qd) : j->dd ? sizeof(dd) : sizeof(double);
   // offsets of core c and interpolation core c inside the job's arrays (host copies of the tables)
   std::vector<int64_t> foff(m), coff(std::max(m - 1, 1));
   {
@@ -941,7 +1016,7 @@ tt_status tt_job_core(tt_job* j, int32_t k, int32_t c, double* F, double* C, int
   TT_HIP(hipMemcpy(fbuf.data(), (char*)d.F + foff[c] * es, fbuf.size(), hipMemcpyDeviceToHost));
   auto lead = [&](const char* base, size_t idx) {
     double v;
-    std::memcpy(&v, base + idx * es, sizeof(double));   // the leading double of a dd value comes first
+    std::memcpy(&v, base + idx * es, sizeof(double));   // the leading double of a dd or qd value comes first
     return v;
   };
   for (int64_t row = 0; row < nr; ++row)
@@ -983,9 +1058,10 @@ tt_status tt_eval_points(tt_ctx* ctx, const tt_problem* p, const int32_t* d_idx,
   if (npts == 0) return TT_OK;
   std::lock_guard<std::mutex> lock(ctx->mu);
   TT_HIP(hipSetDevice(ctx->device));
+  if (p->precision == TT_QD) return TT_EINVAL;
   const bool use_dd = p->precision == TT_DD;
   double *t, *w;
-  tt_status s = gl_table(ctx, p->n_nodes, &t, &w, use_dd);
+  tt_status s = gl_table(ctx, p->n_nodes, &t, &w, use_dd ? TT_DD : TT_FP64);
   if (s != TT_OK) return s;
   FamilyArgs fa;
   s = family_for(ctx, p, &fa);
@@ -1012,9 +1088,10 @@ tt_status tt_eval_fibers(tt_ctx* ctx, const tt_problem* p, int32_t pos, const in
   if ((pos == 0 && r_left != 1) || (pos == m - 1 && r_right != 1)) return TT_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   TT_HIP(hipSetDevice(ctx->device));
+  if (p->precision == TT_QD) return TT_EINVAL;
   const bool use_dd = p->precision == TT_DD;
   double *t, *w;
-  tt_status s = gl_table(ctx, p->n_nodes, &t, &w, use_dd);
+  tt_status s = gl_table(ctx, p->n_nodes, &t, &w, use_dd ? TT_DD : TT_FP64);
   if (s != TT_OK) return s;
   FamilyArgs fa;
   s = family_for(ctx, p, &fa);

@@ -20,7 +20,7 @@ FAMILY_IDS = {
     "prod_exp": 21, "sum2_exp_cos": 22,
 }
 STOP_REASONS = {0: "running", 1: "converged", 2: "rank_cap", 3: "max_sweeps", 4: "error"}
-PRECISION_IDS = {"fp64": 0, "dd": 1}
+PRECISION_IDS = {"fp64": 0, "dd": 1, "qd": 2}
 
 TT_OK, TT_CONVERGED, TT_NOT_CONVERGED, TT_PENDING = 0, 1, 2, 3
 TT_EINVAL, TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC = -1, -2, -3, -4
@@ -85,6 +85,7 @@ EXPORTS = [
     "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
     "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue", "tt_mc_integrate",
     "tt_mc_integrate_noalloc", "tt_job_core", "tt_batch_run", "tt_autotune", "tt_cross_refresh",
+    "tt_job_history_parts", "tt_job_nodes_parts",
 ]
 
 STOP_RULE_IDS = {"rel2": 0, "strict": 1}   # tt_stop_rule
@@ -143,6 +144,8 @@ def load_library():
         "tt_batch_run": (i32, [vp, P(_Problem), i32, P(_Info)]),
         "tt_autotune": (i32, [vp, P(_Problem), i32, i32, P(_TuneResult)]),
         "tt_cross_refresh": (i32, [vp, P(_Info)]),
+        "tt_job_history_parts": (i32, [vp, i32, i32, P(ctypes.c_double), P(i32), i64, P(i64)]),
+        "tt_job_nodes_parts": (i32, [vp, i32, i32, P(ctypes.c_double), P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -367,6 +370,27 @@ class Job:
 
     def history(self, k):
         return self.history_dd(k)[0]
+
+    def history_parts(self, k, parts=4):
+        """[([components], exponent)]: the integral after the start and every sweep is
+        sum(components) * 2^exponent (4 components of a quad-double job)."""
+        p = self.problems[k]
+        cap = (p.max_sweeps if p.max_sweeps > 0 else 4 * p.rank_cap) + 1
+        vals = (ctypes.c_double * (cap * parts))()
+        ex = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int64()
+        _check(self._lib.tt_job_history_parts(self.handle, k, parts, vals, ex, cap, ctypes.byref(n)),
+               "tt_job_history_parts")
+        return [(list(vals[q * parts:(q + 1) * parts]), ex[q]) for q in range(n.value)]
+
+    def nodes_parts(self, k, parts=4):
+        """(t, w): the unscaled nodes and weights, `parts` components each."""
+        n = self.problems[k].n
+        t = (ctypes.c_double * (n * parts))()
+        w = (ctypes.c_double * (n * parts))()
+        _check(self._lib.tt_job_nodes_parts(self.handle, k, parts, t, w), "tt_job_nodes_parts")
+        return ([list(t[i * parts:(i + 1) * parts]) for i in range(n)],
+                [list(w[i * parts:(i + 1) * parts]) for i in range(n)])
 
     def history_dd(self, k):
         """(leading doubles, low doubles) of the integral after the start and every sweep."""

@@ -354,3 +354,22 @@ def test_dd_config3_full_size_against_the_stored_oracle_run():
     else:
         print(f"first divergence {divergence}", flush=True)
         assert dd_rel(ghi[-1], glo[-1], *ref["hist"][-1]) <= 10 * p.tol
+
+
+def test_dd_recomputed_interpolation_cores_against_the_oracle():
+    # C_20 with 9 nodes, rank <= 12: the crosses of Alg. 6 lose dominance (|C_c| near
+    # 4000 within eight sweeps, measured on the oracle), so the double-double cores are
+    # recomputed from F_c with a pivoted solve (R19) once |C_c| passes 1024, as the
+    # oracle recomputes every core from its definition; the values then agree to 1e-24
+    p = Problem("ising_c", 20, 9, 12, 1e-20, seed=20, precision="dd")
+    print(f"dd recompute {p}", flush=True)
+    ctx = gpu_context()
+    job = ctx.job([p])
+    info = job.run()[0]
+    assert info["recomputes"] > 0
+    ref = TTCrossDD(p.family, p.d, p.n, p.rank_cap, p.tol, p.seed)
+    ref.run()
+    compare_dd(job, 0, p, ref, exact_log=False)
+    ghi, glo = job.history_dd(0)
+    assert dd_rel(ghi[-1], glo[-1], ref.history[-1], ref.history_lo[-1]) <= 1e-24
+    job.free()
