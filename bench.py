@@ -26,12 +26,13 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector (FMA = 2 flops)
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per k_sweep launch on this workload from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (KiB per dispatch, mean over every launch of 4 jobs), scaled by
+# WRITE_SIZE (KiB per dispatch, mean over the 81 launches of a warm-up and two
+# timed steps, after the autotuner's candidate runs), scaled by
 # what the same counters read for a 1 GiB device copy (FETCH 2.0, WRITE 1.0).
 # Valid only for the kernel sources they were taken on (hash below); for any
 # other source the traffic is reported as null.
-SWEEP_TRAFFIC = {"source_hash": "03ab7da904a2853b", "fetch_kib": 3383.1, "fetch_scale": 2.0,
-                 "write_kib": 1995.0, "write_scale": 1.0}
+SWEEP_TRAFFIC = {"source_hash": "d6598c78c4d9699c", "fetch_kib": 4769.1, "fetch_scale": 2.0,
+                 "write_kib": 2517.4, "write_scale": 1.0}
 KERNEL_SOURCES = ("tt_device.hpp", "tt_inst.hip", "tt_kernels.hpp", "tt_launch.hpp")
 
 
@@ -767,6 +768,26 @@ def cpu_baseline_all_cores(probs):
                 seconds=wall, integrals_per_s=len(tasks) / wall)
 
 
+def fibre_only(steps):
+    """The saturated fibre-evaluation measurement's launches alone (D_10, 64 x 256 x 64 at mode 4)."""
+    import torch
+
+    from paper_1903_11554_amd import Context, Problem
+    from paper_1903_11554_amd.workloads import random_index_set
+    torch.cuda.set_device(0)
+    ctx = Context(0)
+    pe = Problem("ising_d", 10, 256, 64, 1e-10)
+    m, pos, rl, rr = pe.modes(), 4, 64, 64
+    left = torch.from_numpy(random_index_set(rl, pos, pe.n, 11)).cuda()
+    right = torch.from_numpy(random_index_set(rr, m - pos - 1, pe.n, 12)).cuda()
+    out = torch.empty(rl * pe.n * rr, dtype=torch.float64, device="cuda")
+    for _ in range(max(steps, 1) * 50):
+        ctx.eval_fibers(pe, pos, left.data_ptr(), rl, right.data_ptr(), rr, out.data_ptr())
+    torch.cuda.synchronize()
+    ctx.close()
+    print(f"fibre kernel: {max(steps, 1) * 50} launches of {rl * pe.n * rr} points", flush=True)
+
+
 def copy_calibration(mib=1024, reps=4):
     """A plain device-to-device copy of known size, the yardstick for the HBM byte counters."""
     import torch
@@ -787,6 +808,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fibre-only", action="store_true",
+                    help="only launch the fibre-evaluation kernel on the D_10 set, --steps x 50 times "
+                         "(for profiler counter runs)")
     ap.add_argument("--main-only", action="store_true",
                     help="run only the D_5..D_10 + C_4 steps (for profiler runs of the sweep kernel)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -796,6 +820,9 @@ def main():
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.fibre_only:
+        fibre_only(args.steps)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); integrals are independent "
@@ -828,6 +855,11 @@ def main():
         nl, ms, npts, ff, ft = r["fib"]
         fib = {"kernel": "k_eval_fibers", "points": npts, "avg_launch_ms": ms / nl,
                "tflops": ft, "frac": ft / FP64_PEAK_TFLOPS, "evals_per_s": npts / (ms / nl * 1e-3),
+               "flops_model": "each point priced at a from-scratch evaluation (272 flops for 9 modes); "
+                              "the kernel issues 164 FP64 flops per point (rocprofv3 "
+                              "SQ_INSTS_VALU_{FMA,MUL,ADD}_F64), sharing the runs inside one tuple "
+                              "across the fibre",
+               "issued_tflops": ft * 164.0 / 272.0, "issued_frac": ft * 164.0 / 272.0 / FP64_PEAK_TFLOPS,
                "workload": "D_10 (9 modes) fibre set 64 x 256 x 64 at mode 4"}
     line = {
         "metric": METRIC,
