@@ -132,7 +132,8 @@ typedef struct {
   int32_t max_rank;    /* largest bond rank                                               */
   int32_t reason;      /* TT_RUNNING or a TT_STOP_* code                                  */
   int32_t err_flags;   /* bits: non-finite value (1), singular cross (2), zero start (4),
-                          internal rank bucket overflow (8)                               */
+                          internal rank bucket overflow (8), a core update's wait for
+                          its neighbouring searches timed out (16)                        */
   int64_t evals;       /* integrand evaluations so far (start, samples, fibers, cores)    */
   double  value;       /* integral estimate (TT_DD: its leading double)                   */
   double  rel_change;  /* |I_s - I_{s-1}| / |I_s| of the last sweep                       */
@@ -348,15 +349,15 @@ tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
 tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);
 
 /* Phase marks of the sweep kernel for integral k, recorded for jobs created
- * while profiling is on (otherwise *written = 0): for every sweep and
- * superblock, 16 wall-clock marks (0 start, 1 sets staged, 2 samples done,
- * 3 rook pivoting done, 4 search done, 5 core updates done, 6 quadrature done,
- * 7 end, then inside the workgroup's last core update: 8 hand-over done,
- * 9 pivots appended and sets staged, 10 new entries evaluated, 11 new rows of
- * the interpolation core solved, 12 cross LU bordered, 13 rank-1 update done,
- * 14 core summed; 0 where the workgroup skipped a phase), in ticks
- * of *clock_mhz MHz.  marks is a host buffer of `capacity` int64;
- * sweeps x (m-1) x 16 values are written. */
+ * while profiling is on (otherwise *written = 0): for every sweep, one row of
+ * 16 wall-clock marks per superblock b (row b: 0 start, 1 sets staged,
+ * 2 samples done, 3 rook pivoting done, 4 search done, 7 end), then one per
+ * core c (row m-1+c: 0 start, 8 both neighbouring searches seen, 9 pivots
+ * appended and sets staged, 10 new entries evaluated, 11 new rows of the
+ * interpolation core solved, 12 cross LU bordered, 13 rank-1 update done,
+ * 14 core summed, 5 update done, 6 quadrature done, 7 end); 0 where the
+ * workgroup skipped a phase; in ticks of *clock_mhz MHz.  marks is a host
+ * buffer of `capacity` int64; sweeps x (2m-1) x 16 values are written. */
 tt_status tt_job_phase_times(tt_job *job, int32_t k, int64_t *marks, int64_t capacity, int64_t *written,
                              double *clock_mhz);
 

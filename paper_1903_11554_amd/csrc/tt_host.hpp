@@ -226,7 +226,7 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   o.start = L.take((size_t)(m > 0 ? m : 1) * I);
   o.sync = L.take((size_t)(m + 1) * I);
   o.rfl = L.take((size_t)(m > 0 ? m : 1) * I);
-  o.phase = L.take((size_t)ms * (nb > 0 ? nb : 1) * kPhases * sizeof(long long));
+  o.phase = L.take((size_t)ms * (nb + m > 0 ? nb + m : 1) * kPhases * sizeof(long long));
   return o;
 }
 

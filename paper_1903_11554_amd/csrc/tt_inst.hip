@@ -30,8 +30,9 @@ using Real = double;
 
 template <int MAXM, int RMAX>
 void sweep(const LaunchArgs& a) {
-  hipLaunchKernelGGL((k_sweep<Real, TT_FAM, MAXM, RMAX>), dim3(a.nbond), dim3(kSweepBlock), 0, a.stream,
-                     a.desc, a.bond_tasks);
+  // one workgroup per superblock, then one per core
+  hipLaunchKernelGGL((k_sweep<Real, TT_FAM, MAXM, RMAX>), dim3(a.nbond + a.ncore), dim3(kSweepBlock), 0,
+                     a.stream, a.desc, a.bond_tasks, a.nbond, a.core_tasks, a.sweep_ctr);
 }
 
 template <int MAXM>

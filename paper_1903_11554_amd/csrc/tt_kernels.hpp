@@ -73,19 +73,21 @@ struct ProbDesc {
   int32_t *rfl;                          // [m] 1: core c's interpolation core is recomputed every sweep
   int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
   ProbState *st_host;                    // pinned host copy of the final state (may be null)
-  long long *phase;                      // [max_sweeps][nbonds][kPhases] wall-clock marks, or null
+  long long *phase;                      // [max_sweeps][nbonds + m][kPhases] wall-clock marks, or null
   ProbState *st;
 };
 
-// Phase marks of one superblock's workgroup in one sweep (wall clock, written by thread 0):
-// 0 start, 1 sets staged, 2 samples done, 3 rook pivoting done, 4 search done,
-// 5 core updates done, 6 quadrature done, 7 end; inside the last core update of the
-// workgroup: 8 hand-over done, 9 pivots appended and sets staged, 10 new entries
-// evaluated, 11 new rows solved, 12 cross LU bordered, 13 rank-1 update done, 14 core summed.
+// Phase marks of the sweep kernel's workgroups in one sweep (wall clock, written by
+// thread 0), one row per superblock b, then one row per core c (row nbonds + c).
+// Superblock rows: 0 start, 1 sets staged, 2 samples done, 3 rook pivoting done,
+// 4 search done, 7 end.  Core rows: 0 start, 8 both neighbouring searches seen,
+// 9 pivots appended and sets staged, 10 new entries evaluated, 11 new rows solved,
+// 12 cross LU bordered, 13 rank-1 update done, 14 core summed, 5 update done,
+// 6 quadrature done (the integral's last core), 7 end.
 constexpr int kPhases = 16;
-__device__ __forceinline__ void mark(const ProbDesc& p, int sweep, int b, int slot) {
+__device__ __forceinline__ void mark(const ProbDesc& p, int sweep, int row, int slot) {
   if (p.phase != nullptr && threadIdx.x == 0)
-    p.phase[((size_t)sweep * p.nbonds + b) * kPhases + slot] = (long long)wall_clock64();
+    p.phase[((size_t)sweep * (p.nbonds + p.m) + row) * kPhases + slot] = (long long)wall_clock64();
 }
 
 // Mirror "this integral has stopped" into pinned host memory so the host can
@@ -1878,67 +1880,106 @@ union SweepSmem {
   IntSmem<T> i;
 };
 
-// One sweep of Alg. 6 in one launch, one workgroup per superblock.  Every
-// workgroup searches its superblock; a core is updated by whichever of its two
-// neighbouring superblocks finishes last, and the quadrature by whichever core
-// finishes last.  Each hand-over is a release fence plus an atomic increment,
-// observed by the arriving workgroup after an acquire fence; no workgroup waits
-// for another, so any subset of workgroups may be resident at a time.  The
-// release fence writes this workgroup's results back from its XCD's L2; only the
-// last arriver, which goes on to read the others' results, takes the acquire
-// fence (an L2 invalidate), so the other workgroups keep their caches warm.
+// One sweep of Alg. 6 in one launch: one workgroup per superblock searches it
+// (Alg. 2), one workgroup per core updates the core once both neighbouring
+// searches are done, and the last core of an integral to finish runs the
+// quadrature and the stopping rule.  The two kinds run side by side, so a
+// superblock's workgroup never carries its cores' updates after its own search.
+//
+// Tasks are taken in ticket order (an atomic counter), superblocks first, so a
+// core's workgroup only ever waits for searches that workgroups already running
+// hold: every wait ends whatever subset of workgroups is resident.  Each
+// hand-over is a release fence plus an atomic increment; the core's workgroup
+// polls the counter and takes an acquire fence (an L2 invalidate) before it reads
+// the searches' results.  A wait beyond kWaitTicks of the constant clock gives up
+// (err_flags 16) and the integral stops with an error.  The last workgroup to
+// finish puts the launch counters back to zero for the next launch.
 //
 // The paper-form streaming kernels of rank 8 and 16 (the large integrals, a
 // thousand superblocks per launch) are compiled for four waves per SIMD (at most
-// 128 VGPRs), at a cost of 40 bytes of spill at rank 16.  Measured on C_1024
-// before the row summaries, its sweeps took 13.7 ms instead of 15.8.
+// 128 VGPRs).  Measured on C_1024 before the row summaries, its sweeps took
+// 13.7 ms instead of 15.8.
+constexpr long long kWaitTicks = 1000000000LL;   // 10 s of the 100 MHz constant clock
+
 template <class T, int FAM, int MAXM, int RMAX>
-__global__ __launch_bounds__(kSweepBlock, FAM == 0 && MAXM == 0 && RMAX <= 16 ? 4 : 1) void k_sweep(ProbDesc* __restrict__ P,
-                                                       const int2* __restrict__ tasks) {
-  __shared__ SweepSmem<T, MAXM, RMAX> sm;
-  __shared__ int s_todo[3];
-  __shared__ int s_last;
-  const int2 tk = tasks[blockIdx.x];
-  const ProbDesc& p = P[tk.x];
-  const int b = tk.y, tid = threadIdx.x, m = p.m;
+__device__ __forceinline__ void sweep_search(const ProbDesc& p, const int b, SweepSmem<T, MAXM, RMAX>& sm) {
   if (p.st->done) return;
   const int sweep = p.st->sweeps;
   search_bond<T, FAM, MAXM>(p, b, sm.s);
   __syncthreads();
   mark(p, sweep, b, 4);
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    int nt = 0;
-    for (int c = b; c <= b + 1; ++c) {
-      const int target = (c >= 1 ? 1 : 0) + (c <= m - 2 ? 1 : 0);
-      if (atomicAdd(&p.sync[c], 1) + 1 == target) s_todo[nt++] = c;
-    }
-    s_todo[2] = nt;
-    if (nt > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-  const int nt = s_todo[2];
-  mark(p, sweep, b, 8);
-  for (int q = 0; q < nt; ++q) {
-    const int c = s_todo[q];
-    update_core<T, FAM, MAXM, RMAX>(p, c, 0, sm.u, b);
-    __syncthreads();
-    mark(p, sweep, b, 5);
-    if (tid == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      s_last = (atomicAdd(&p.sync[m], 1) + 1 == m);
-      if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    if (s_last) {
-      integral_problem<T, chain_block_size<T, RMAX>()>(p, 0, sm.i);
-      __syncthreads();
-      for (int k = tid; k <= m; k += blockDim.x) p.sync[k] = 0;   // every hand-over of this sweep is done
-      mark(p, sweep, b, 6);
-    }
-    __syncthreads();
+    atomicAdd(&p.sync[b], 1);
+    atomicAdd(&p.sync[b + 1], 1);
   }
   mark(p, sweep, b, 7);
+}
+
+template <class T, int FAM, int MAXM, int RMAX>
+__device__ __forceinline__ void sweep_core(const ProbDesc& p, const int c, SweepSmem<T, MAXM, RMAX>& sm,
+                                           int& s_flag) {
+  const int tid = threadIdx.x, m = p.m;
+  if (p.st->done || m < 2) return;
+  const int sweep = p.st->sweeps, row = p.nbonds + c;
+  mark(p, sweep, row, 0);
+  if (tid == 0) {
+    const int target = (c >= 1 ? 1 : 0) + (c <= m - 2 ? 1 : 0);
+    const long long t0 = (long long)wall_clock64();
+    int ok = 1;
+    while (__hip_atomic_load(&p.sync[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if ((long long)wall_clock64() - t0 > kWaitTicks) {
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok) atomicOr(&p.st->err_flags, 16);
+    s_flag = ok;
+  }
+  __syncthreads();
+  mark(p, sweep, row, 8);
+  if (s_flag) update_core<T, FAM, MAXM, RMAX>(p, c, 0, sm.u, row);
+  __syncthreads();
+  mark(p, sweep, row, 5);
+  if (tid == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    s_flag = (atomicAdd(&p.sync[m], 1) + 1 == m);
+    if (s_flag) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  if (s_flag) {
+    integral_problem<T, chain_block_size<T, RMAX>()>(p, 0, sm.i);
+    __syncthreads();
+    for (int k = tid; k <= m; k += blockDim.x) p.sync[k] = 0;   // every hand-over of this sweep is done
+    mark(p, sweep, row, 6);
+  }
+  mark(p, sweep, row, 7);
+}
+
+// ctr: two launch counters (tickets taken, workgroups finished), zero at launch.
+// The grid is nbond + ncore workgroups.
+template <class T, int FAM, int MAXM, int RMAX>
+__global__ __launch_bounds__(kSweepBlock, FAM == 0 && MAXM == 0 && RMAX <= 16 ? 4 : 1) void k_sweep(
+    ProbDesc* __restrict__ P, const int2* __restrict__ bond_tasks, int nbond, const int2* __restrict__ core_tasks,
+    int32_t* __restrict__ ctr) {
+  __shared__ SweepSmem<T, MAXM, RMAX> sm;
+  __shared__ int s_task, s_flag;
+  if (threadIdx.x == 0) s_task = atomicAdd(&ctr[0], 1);
+  __syncthreads();
+  const int t = s_task;
+  if (t < nbond) {
+    const int2 tk = bond_tasks[t];
+    sweep_search<T, FAM, MAXM, RMAX>(P[tk.x], tk.y, sm);
+  } else {
+    const int2 tk = core_tasks[t - nbond];
+    sweep_core<T, FAM, MAXM, RMAX>(P[tk.x], tk.y, sm, s_flag);
+  }
+  if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) + 1 == (int)gridDim.x) {   // every ticket was taken
+    __hip_atomic_store(&ctr[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctr[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ------------------------------------------------------- standalone eval

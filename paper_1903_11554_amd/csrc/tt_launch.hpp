@@ -17,6 +17,7 @@ struct LaunchArgs {
   int nprob;
   int mbucket;        // compile-time bound on the number of modes (0: streaming, any number)
   hipStream_t stream;
+  int32_t* sweep_ctr; // two launch counters of the sweep kernel (zero between launches)
 };
 
 enum { LAUNCH_START = 0, LAUNCH_INIT_UPDATE = 1, LAUNCH_SWEEP = 2, LAUNCH_ALS = 3 };

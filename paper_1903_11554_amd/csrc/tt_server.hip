@@ -111,7 +111,7 @@ struct tt_server {
   SubAlloc* alloc = nullptr;
   // device table: sweep descriptors and tasks, init descriptors and core tasks
   char* dtable = nullptr;
-  size_t off_sdesc = 0, off_stask = 0, off_idesc = 0, off_itask = 0, table_bytes = 0;
+  size_t off_sdesc = 0, off_stask = 0, off_score = 0, off_idesc = 0, off_itask = 0, off_ctr = 0, table_bytes = 0;
   // pinned host memory
   int32_t* flags = nullptr;              // [max_active] done flags
   ProbState* mirror = nullptr;           // [max_active] final states
@@ -206,7 +206,7 @@ tt_status start_requests(tt_server* s, std::vector<Running>& fresh) {
   }
   TT_HIP(hipEventRecord(s->stage_ev[si], ctx->stream));
   LaunchArgs a{(ProbDesc*)(s->dtable + s->off_idesc), nullptr, 0, (const int2*)(s->dtable + s->off_itask),
-               (int)itask.size(), (int)fresh.size(), bucket_m_for(fam, false, maxm), ctx->stream};
+               (int)itask.size(), (int)fresh.size(), bucket_m_for(fam, TT_FP64, maxm), ctx->stream, nullptr};
   auto go = [&](int what) {
     switch (fam) {
       case FAM_PAPER: launch_paper(a, what, 8); break;
@@ -232,8 +232,8 @@ tt_status start_requests(tt_server* s, std::vector<Running>& fresh) {
   return TT_OK;
 }
 
-// Upload the running set's descriptors and superblock tasks.
-tt_status upload_running(tt_server* s, int* nbond) {
+// Upload the running set's descriptors, superblock tasks and core tasks.
+tt_status upload_running(tt_server* s, int* nbond, int* ncore) {
   char* stg;
   int si;
   tt_status st = take_stage(s, &stg, &si);
@@ -246,19 +246,27 @@ tt_status upload_running(tt_server* s, int* nbond) {
     d[q] = s->running[q].desc;
     for (int b = 0; b + 1 < s->running[q].m; ++b) tk[nt++] = make_int2((int)q, b);
   }
+  int2* ck = tk + nt;   // core tasks of the integrals that have superblocks
+  int nc = 0;
+  for (size_t q = 0; q < nd; ++q)
+    if (s->running[q].m >= 2)
+      for (int c = 0; c < s->running[q].m; ++c) ck[nc++] = make_int2((int)q, c);
   if (nd) TT_HIP(hipMemcpyAsync(s->dtable + s->off_sdesc, d, nd * sizeof(ProbDesc), hipMemcpyHostToDevice,
                                 s->ctx->stream));
   if (nt) TT_HIP(hipMemcpyAsync(s->dtable + s->off_stask, tk, nt * sizeof(int2), hipMemcpyHostToDevice,
                                 s->ctx->stream));
+  if (nc) TT_HIP(hipMemcpyAsync(s->dtable + s->off_score, ck, nc * sizeof(int2), hipMemcpyHostToDevice,
+                                s->ctx->stream));
   TT_HIP(hipEventRecord(s->stage_ev[si], s->ctx->stream));
   *nbond = nt;
+  *ncore = nc;
   return TT_OK;
 }
 
 void worker_main(tt_server* s) {
   tt_ctx* ctx = s->ctx;
   bool changed = true;
-  int nbond = 0;
+  int nbond = 0, ncore = 0;
   Clock::time_point busy_since{};
   bool busy = false;
   for (;;) {
@@ -326,7 +334,7 @@ void worker_main(tt_server* s) {
         s->stats.admissions += 1;
       }
       if (st == TT_OK && changed) {
-        st = upload_running(s, &nbond);
+        st = upload_running(s, &nbond, &ncore);
         changed = false;
       }
       if (st == TT_OK && nbond > 0) {
@@ -338,7 +346,8 @@ void worker_main(tt_server* s) {
           r.launched += 1;
         }
         LaunchArgs a{(ProbDesc*)(s->dtable + s->off_sdesc), (const int2*)(s->dtable + s->off_stask), nbond,
-                     nullptr, 0, (int)s->running.size(), bucket_m_for(fam, false, maxm), ctx->stream};
+                     (const int2*)(s->dtable + s->off_score), ncore, (int)s->running.size(),
+                     bucket_m_for(fam, TT_FP64, maxm), ctx->stream, (int32_t*)(s->dtable + s->off_ctr)};
         {
           Timed tm(ctx, KK_SWEEP);
           switch (fam) {
@@ -410,10 +419,14 @@ tt_status tt_server_create(tt_ctx* ctx, size_t max_bytes, int32_t max_active, tt
     Layout L;
     s->off_sdesc = L.take(sizeof(ProbDesc) * max_active);
     s->off_stask = L.take(sizeof(int2) * max_active * kMaxBonds);
+    s->off_score = L.take(sizeof(int2) * max_active * TT_MAX_REG_MODES);
     s->off_idesc = L.take(sizeof(ProbDesc) * max_active);
     s->off_itask = L.take(sizeof(int2) * max_active * TT_MAX_REG_MODES);
+    s->off_ctr = L.take(2 * sizeof(int32_t));
     s->table_bytes = L.off;
     if (hipMalloc(&s->dtable, s->table_bytes) != hipSuccess) return fail(TT_ENOMEM);
+    // the sweep kernel's launch counters start at zero (each launch leaves them so)
+    if (hipMemset(s->dtable + s->off_ctr, 0, 2 * sizeof(int32_t)) != hipSuccess) return fail(TT_EDEVICE);
     if (hipHostMalloc((void**)&s->flags, sizeof(int32_t) * max_active, hipHostMallocDefault) != hipSuccess)
       return fail(TT_ENOMEM);
     if (hipHostMalloc((void**)&s->mirror, sizeof(ProbState) * max_active, hipHostMallocDefault) != hipSuccess)

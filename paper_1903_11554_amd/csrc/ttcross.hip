@@ -33,6 +33,7 @@ struct tt_job {
   int2* dbond = nullptr;
   int nbond = 0;
   int2* dcore = nullptr;
+  int32_t* dctr = nullptr;   // the sweep kernel's launch counters (in the table region, zero at upload)
   int ncore = 0;
   int maxm = 0, maxR = 1;
   int fam = 3;            // integrand class the job's kernels are specialised for
@@ -132,7 +133,7 @@ void pinned_give(tt_ctx* c, char* p, size_t bytes) {
 }
 
 void launch(tt_job* j, int what, int rb) {
-  LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, j->mbucket, j->ctx->stream};
+  LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, j->mbucket, j->ctx->stream, j->dctr};
   Timed tm(j->ctx, what == LAUNCH_SWEEP   ? KK_SWEEP
                    : what == LAUNCH_START ? KK_START
                    : what == LAUNCH_ALS   ? KK_REFRESH
@@ -613,6 +614,7 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   const size_t desc_off = L.take(sizeof(ProbDesc) * count);
   const size_t bond_off = L.take(sizeof(int2) * (bond_tasks.size() + 1));
   const size_t core_off = L.take(sizeof(int2) * (core_tasks.size() + 1));
+  const size_t ctr_off = L.take(2 * sizeof(int32_t));
   std::vector<ProbOffsets> offs;
   std::vector<ProbTables> tabs;
   for (int k = 0; k < count; ++k) {
@@ -651,6 +653,7 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->ddesc = (ProbDesc*)(base + desc_off);
   j->dbond = (int2*)(base + bond_off);
   j->dcore = (int2*)(base + core_off);
+  j->dctr = (int32_t*)(base + ctr_off);
   j->nbond = (int)bond_tasks.size();
   j->ncore = (int)core_tasks.size();
   // one pinned block (reused from the context when possible): done flags, then
@@ -920,7 +923,7 @@ tt_status tt_job_phase_times(tt_job* j, int32_t k, int64_t* marks, int64_t capac
   TT_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, j->ctx->device));
   *clock_mhz = rate_khz / 1000.0;
   if (!d.phase) return TT_OK;
-  const int64_t nrec = (int64_t)st[k].sweeps * d.nbonds * kPhases;
+  const int64_t nrec = (int64_t)st[k].sweeps * (d.nbonds + d.m) * kPhases;
   if (nrec > capacity) return TT_EINVAL;
   if (nrec > 0) TT_HIP(hipMemcpy(marks, d.phase, nrec * sizeof(long long), hipMemcpyDeviceToHost));
   *written = nrec;

@@ -439,11 +439,14 @@ class Job:
         return out
 
     def phase_times(self, k):
-        """(marks[sweep, superblock, 16], clock MHz) of the sweep kernel, or None if not profiled."""
+        """(marks[sweep, row, 16], clock MHz) of the sweep kernel, or None if not profiled.
+
+        Rows: the m-1 superblocks, then the m cores."""
         p = self.problems[k]
         nb = max(p.modes() - 1, 0)
+        rows = nb + p.modes() if nb > 0 else 0
         ms = p.max_sweeps if p.max_sweeps > 0 else 4 * p.rank_cap
-        cap = max(1, ms * nb * 16)
+        cap = max(1, ms * rows * 16)
         buf = (ctypes.c_int64 * cap)()
         written = ctypes.c_int64()
         mhz = ctypes.c_double()
@@ -451,7 +454,7 @@ class Job:
                                             ctypes.byref(mhz)), "tt_job_phase_times")
         if written.value == 0:
             return None
-        arr = np.array(buf[:written.value], dtype=np.int64).reshape(-1, nb, 16)
+        arr = np.array(buf[:written.value], dtype=np.int64).reshape(-1, rows, 16)
         return arr, mhz.value
 
     def core(self, k, c):
