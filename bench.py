@@ -842,7 +842,7 @@ def main():
     nl_u, ms_u = r["kt"]["update"]
     achieved = r["s_flops"] / (ms_s * 1e-3) / 1e12
     roof = {"kernel": "k_sweep (one launch per sweep: pivot search of every superblock, core updates, "
-                      "quadrature and stopping rule; one workgroup per superblock)",
+                      "quadrature and stopping rule; one workgroup per superblock and one per core)",
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": sweep_traffic_bytes(),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
