@@ -132,8 +132,9 @@ typedef struct {
   int32_t max_rank;    /* largest bond rank                                               */
   int32_t reason;      /* TT_RUNNING or a TT_STOP_* code                                  */
   int32_t err_flags;   /* bits: non-finite value (1), singular cross (2), zero start (4),
-                          internal rank bucket overflow (8), a core update's wait for
-                          its neighbouring searches timed out (16)                        */
+                          internal rank bucket overflow (8), a wait inside a sweep
+                          (a core update's for its neighbouring searches, or a
+                          superblock's workgroups' for each other) timed out (16)         */
   int64_t evals;       /* integrand evaluations so far (start, samples, fibers, cores)    */
   double  value;       /* integral estimate (TT_DD: its leading double)                   */
   double  rel_change;  /* |I_s - I_{s-1}| / |I_s| of the last sweep                       */
@@ -346,12 +347,24 @@ tt_status tt_mc_integrate_noalloc(tt_ctx *ctx, const tt_problem *problem, int32_
  * 7 tt_mc_integrate, 8 ALS refresh (tt_cross_refresh, with the rebuild of the cores).
  * Errors: TT_EINVAL (bad kind or NULL outputs). */
 tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
+
+/* Workgroups per superblock search for double jobs created after the call
+ * (a launch shape, not part of the method: every group size gives the same
+ * values, pivots and evaluation counts bit for bit).  group 1..8 fixes it; 0
+ * returns to the rule, as many as keep one compute unit per workgroup of a
+ * sweep launch (superblocks x group + cores <= compute units), at most 8.
+ * Double-double and quad-double jobs always search with one workgroup.  The
+ * serving loop's launches use one.  Errors: TT_EINVAL outside 0..8. */
+tt_status tt_ctx_set_search_group(tt_ctx *ctx, int32_t group);
 tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);
 
 /* Phase marks of the sweep kernel for integral k, recorded for jobs created
  * while profiling is on (otherwise *written = 0): for every sweep, one row of
  * 16 wall-clock marks per superblock b (row b: 0 start, 1 sets staged,
- * 2 samples done, 3 rook pivoting done, 4 search done, 7 end), then one per
+ * 2 samples done, 3 rook pivoting done, 4 search done, 7 end; and durations,
+ * not marks, in 8, 9, 10: the samples' point loop, block argmax and exchange
+ * between the superblock's workgroups, 11, 12, 13: the same summed over the
+ * rook steps, 14: the rook steps' set-up), then one per
  * core c (row m-1+c: 0 start, 8 both neighbouring searches seen, 9 pivots
  * appended and sets staged, 10 new entries evaluated, 11 new rows of the
  * interpolation core solved, 12 cross LU bordered, 13 rank-1 update done,

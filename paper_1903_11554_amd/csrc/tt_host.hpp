@@ -76,7 +76,19 @@ struct tt_ctx {
   std::string tune_path;                           // TTCROSS_TUNE_CACHE, or empty
   bool force_variant = false;                      // tt_autotune's candidate for the next job
   Tuned forced{0, 0, 0.0, 0.0};
+  int cus = 0;                                     // compute units of the device
+  int search_group = 0;                            // workgroups per superblock search (0: the rule)
 };
+
+// Workgroups per superblock search of a double job with nbond superblocks and
+// ncore cores: as many as leave one compute unit per workgroup (at most
+// kMaxGroup), so that the whole grid is resident at once; 1 for the extended
+// precisions.
+inline int search_group_rule(int cus, int nbond, int ncore, int prec) {
+  if (prec != TT_FP64 || nbond <= 0) return 1;
+  const int g = (cus - ncore) / nbond;
+  return g < 1 ? 1 : g > kMaxGroup ? kMaxGroup : g;
+}
 
 // Arenas of freed jobs are kept by the context (up to this many bytes) and
 // handed to later jobs of the same or smaller size, so a stream of jobs does
@@ -182,7 +194,7 @@ struct Layout {
 
 struct ProbOffsets {
   size_t Lpar, Lnode, Rpar, Rnode, Lx, Rx, Lw, Rw, F, C, LU, S, rank, piv, scale, log, hist, hexp, start, sync,
-      rfl, phase;
+      rfl, phase, xch;
   std::vector<int64_t> foff, coff;
 };
 
@@ -227,6 +239,7 @@ inline ProbOffsets layout_problem(const tt_problem& p, Layout& L) {
   o.sync = L.take((size_t)(m + 1) * I);
   o.rfl = L.take((size_t)(m > 0 ? m : 1) * I);
   o.phase = L.take((size_t)ms * (nb + m > 0 ? nb + m : 1) * kPhases * sizeof(long long));
+  o.xch = L.take((size_t)(nb > 0 ? nb : 1) * 2 * kMaxGroup * sizeof(XSlot));
   return o;
 }
 
@@ -389,6 +402,7 @@ inline ProbDesc make_desc(const tt_problem& p, const ProbOffsets& o, char* pb, c
   d.done_host = done_host;
   d.st_host = st_host;
   d.phase = profiling ? (long long*)(pb + o.phase) : nullptr;
+  d.xch = (XSlot*)(pb + o.xch);
   d.st = st;
   return d;
 }

@@ -35,6 +35,22 @@ struct PivRec {
 };
 static_assert(sizeof(PivRec) == sizeof(tt_pivot), "PivRec must mirror tt_pivot");
 
+// One record of a clustered search's exchange (double jobs): a member's best |error|
+// v at point idx with its error e and value a (argmax steps), or its largest |B|
+// seen in v and its non-finite flag in idx (the closing step).  Each 64-bit word
+// holds 32 bits of the record and, above them, the tag of the sweep and step it
+// belongs to, and is written and read as one atomic: a reader that sees the tag in
+// every word holds the whole record of that step, with no fence (a word is new or
+// old as a whole).
+struct XSlot {
+  uint64_t w[8];   // v low, v high, idx, e low, e high, a low, a high, unused
+};
+constexpr int kMaxGroup = 8;   // workgroups per superblock at most
+struct XRec {                  // an exchange record unpacked
+  double v, e, a;
+  int idx;
+};
+
 // The integral is value_mant * 2^vexp (with value_lo the low part of the
 // mantissa for double-double jobs), 1/2 <= |value| < 1 or value = 0.
 struct ProbState {
@@ -74,6 +90,7 @@ struct ProbDesc {
   int32_t *done_host;                    // pinned host flag mirrored when the integral stops (may be null)
   ProbState *st_host;                    // pinned host copy of the final state (may be null)
   long long *phase;                      // [max_sweeps][nbonds + m][kPhases] wall-clock marks, or null
+  XSlot *xch;                            // [nbonds][2][kMaxGroup] exchange records of clustered searches
   ProbState *st;
 };
 
@@ -88,6 +105,12 @@ constexpr int kPhases = 16;
 __device__ __forceinline__ void mark(const ProbDesc& p, int sweep, int row, int slot) {
   if (p.phase != nullptr && threadIdx.x == 0)
     p.phase[((size_t)sweep * (p.nbonds + p.m) + row) * kPhases + slot] = (long long)wall_clock64();
+}
+// Superblock rows also carry durations (ticks, summed over the search's steps):
+// 8, 9, 10 the samples' point loop, block argmax and exchange; 11, 12, 13 the same
+// over the rook steps; 14 the rook steps' set-up (the fixed fibre's B~ operand).
+__device__ __forceinline__ void mark_value(const ProbDesc& p, int sweep, int row, int slot, long long v) {
+  if (p.phase != nullptr && threadIdx.x == 0) p.phase[((size_t)sweep * (p.nbonds + p.m) + row) * kPhases + slot] = v;
 }
 
 // Mirror "this integral has stopped" into pinned host memory so the host can
@@ -329,6 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   __shared__ double s_cm[kStream ? kStart + TT_MAX_NODES : 1];   // streaming start candidates: mantissa
   __shared__ int s_ce[kStream ? kStart + TT_MAX_NODES : 1];      // and exponent
   ProbState* st = p.st;
+  // clustered searches match exchange records by tag: none may survive from the
+  // memory's earlier use
+  for (int e = tid; e < p.nbonds * 2 * kMaxGroup * 8; e += blockDim.x) p.xch[e / 8].w[e % 8] = 0;
 
   if constexpr (!kStream) if (m <= 1) {   // no bond: the tensor is a vector (or a scalar for m = 0)
     T val = num<T>(0.0);
@@ -527,7 +553,95 @@ struct SearchSmem {
   double red_v[kSweepBlock / kWave + 1];
   int red_i[kSweepBlock / kWave + 1];
   T e_star, a_star;
+  XRec xres;    // a clustered search's combined record of the last exchange
+  int xfail;
 };
+
+constexpr long long kWaitTicks = 1000000000LL;   // 10 s of the 100 MHz constant clock
+
+// One step's combination across the G workgroups (members) of a superblock's
+// search.  Thread 0 of each member posts its record as tagged words (XSlot); lanes
+// 0..G-1 of wave 0 read the G records of this step until every word carries the
+// step's tag.  argmax: the record of largest v, ties to the lowest idx (the
+// block_argmax rule, so the result is the argmax over every member's points);
+// otherwise v combines by max and idx by or.  publish: the member's earlier global
+// writes are released before its record and acquired by the readers (the closing
+// step, after which member 0 hands the results to the core updates).  Every thread
+// receives the result through LDS; fail is set when a wait exceeded kWaitTicks.
+// Records alternate between two rows by the step's parity: a member can only post
+// step s + 2 after every member has posted step s + 1, hence after every member has
+// read step s.  Called by the whole workgroup.
+__device__ __forceinline__ XRec group_exchange(XSlot* __restrict__ xs, const int g, const int G, const uint32_t tag,
+                                               const bool argmax, const bool publish, const XRec mine, XRec& res,
+                                               int& fail) {
+  XSlot* row = xs + (tag & 1) * kMaxGroup;
+  const uint64_t tg = (uint64_t)tag << 32;
+  if (threadIdx.x == 0) {
+    uint64_t* my = row[g].w;
+    const uint64_t vb = (uint64_t)__double_as_longlong(mine.v), eb = (uint64_t)__double_as_longlong(mine.e),
+                   ab = (uint64_t)__double_as_longlong(mine.a);
+    const uint64_t words[7] = {tg | (vb & 0xffffffffu), tg | (vb >> 32), tg | (uint32_t)mine.idx,
+                               tg | (eb & 0xffffffffu), tg | (eb >> 32),  tg | (ab & 0xffffffffu),
+                               tg | (ab >> 32)};
+    if (publish) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#pragma unroll
+    for (int k = 0; k < 7; ++k) __hip_atomic_store(&my[k], words[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x < kWave) {
+    const int h = threadIdx.x;
+    int ok = 1;
+    XRec r{argmax ? -1.0 : 0.0, 0.0, 0.0, argmax ? 0x7fffffff : 0};
+    if (h < G) {
+      const uint64_t* src = row[h].w;
+      uint64_t w[7];
+      const long long t0 = (long long)wall_clock64();
+      for (;;) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) w[k] = __hip_atomic_load(&src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) all = all && (w[k] >> 32) == tag;
+        if (all) break;
+        if ((long long)wall_clock64() - t0 > kWaitTicks) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (ok) {
+        r.v = __longlong_as_double((long long)((w[0] & 0xffffffffu) | (w[1] << 32)));
+        r.idx = (int)(uint32_t)w[2];
+        r.e = __longlong_as_double((long long)((w[3] & 0xffffffffu) | (w[4] << 32)));
+        r.a = __longlong_as_double((long long)((w[5] & 0xffffffffu) | (w[6] << 32)));
+      }
+    }
+    if (publish) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+    for (int off = 1; off < kMaxGroup; off <<= 1) {   // lanes 0..7 hold the records (or neutral ones)
+      const double ov = __shfl_xor(r.v, off, kWave), oe = __shfl_xor(r.e, off, kWave);
+      const double oa = __shfl_xor(r.a, off, kWave);
+      const int oi = __shfl_xor(r.idx, off, kWave);
+      if (argmax) {
+        if (better(ov, oi, r.v, r.idx)) {
+          r.v = ov;
+          r.e = oe;
+          r.a = oa;
+          r.idx = oi;
+        }
+      } else {
+        r.v = fmax(r.v, ov);
+        r.idx |= oi;
+      }
+    }
+    const int all_ok = __all(ok);
+    if (h == 0) {
+      res = r;
+      fail = !all_ok;
+    }
+  }
+  __syncthreads();
+  return res;
+}
 
 // C_d's value depends on the coordinates only through B_d's prefix sum and suffix
 // recurrence, and both compose over a split of the coordinates: (P1, q1, s1) then
@@ -590,8 +704,16 @@ __device__ __forceinline__ double ising_c_joined(const double* sL, int al, doubl
 // One step of Alg. 2 on superblock b.  The random samples, every column step and
 // every row step run through the same evaluation loop (one inlined integrand).
 // Decisions (argmax, acceptance) are taken on the leading double of |error|.
+//
+// A double job's search may be spread over G workgroups (members g = 0..G-1 of a
+// cluster): member g evaluates the points q with q / blockDim = g mod G, and after
+// each loop the members combine their block argmaxes (group_exchange), so every
+// member takes the decisions one workgroup would take, on the same values.  A last
+// exchange combines the largest |B| seen and the non-finite flags; member 0 then
+// writes the pivot record.  Only member 0 returns true (it is to signal the cores).
 template <class T, int FAM, int MAXM>
-__device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, SearchSmem<T, MAXM>& sm) {
+__device__ __forceinline__ bool search_bond(const ProbDesc& p, const int b, const int g, const int G,
+                                            SearchSmem<T, MAXM>& sm) {
   constexpr int LD = MAXM + 1;
   constexpr bool kStream = MAXM == 0;   // coordinates read from the index-set rows in memory
   const int tid = threadIdx.x;
@@ -602,13 +724,16 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   const int rL = b > 0 ? p.rank[b - 1] : 1;
   const int rR = b < m - 2 ? p.rank[b + 1] : 1;
   if (rb >= R) {
-    if (tid == 0) {
+    if (tid == 0 && g == 0) {
       PivRec rec{-1, -1, 0, 0, 0.0, 0.0, 0, 0};
       p.piv[b] = rec;
       p.log[(size_t)sweep * nb + b] = rec;
     }
-    return;
+    return g == 0;
   }
+  XSlot* const xs = p.xch + (size_t)b * 2 * kMaxGroup;
+  uint32_t xstep = 0;                                        // exchanges of this search so far
+  const uint32_t xtag0 = (uint32_t)(sweep + 1) << 5;         // at most 2 + 2 kRook exchanges
   const FamilyArgs fa = family_args(p);
   const T* __restrict__ gLx = tp<T>(p.Lx);
   const T* __restrict__ gRx = tp<T>(p.Rx);
@@ -616,7 +741,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   const T* __restrict__ gRw = tp<T>(p.Rw);
   const T* __restrict__ gt = tp<T>(p.t);
   const T* __restrict__ gw = tp<T>(p.w);
-  mark(p, sweep, b, 0);
+  if (g == 0) mark(p, sweep, b, 0);
   // stage index-set coordinates, node table and weights in LDS
   if constexpr (!kStream) {
     for (int e = tid; e < rL * b; e += blockDim.x) {
@@ -645,7 +770,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
                     b + 1 <= m - 2 ? m : b + 2, sm.sR, m);
   }
   __syncthreads();
-  mark(p, sweep, b, 1);
+  if (g == 0) mark(p, sweep, b, 1);
 
   const int nrows = rL * n, ncols = n * rR;
   const T* __restrict__ F1 = tp<T>(p.F) + p.Foff[b + 1];
@@ -668,6 +793,9 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
   int mode = 0;            // 0: random samples, 1: column step, 2: row step
   int row = 0, col = 0, iters = 0;
   bool col_fresh = false;  // the last column step was taken at the final column
+  const bool timed = p.phase != nullptr && g == 0 && tid == 0;   // profiled runs: step durations
+  long long tq0 = 0, tq1 = 0, tq2 = 0, tq3 = 0, tq4 = 0, tq5 = 0, tq6 = 0;
+  long long t0 = timed ? (long long)wall_clock64() : 0;
   for (;;) {
     if (mode == 1) {          // B~(:, col) = C_b F_{b+1}(:, col)
       const int j = col / rR, be = col - j * rR;
@@ -676,10 +804,15 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
       if (tid < rb) sm.vec[tid] = Cb[(size_t)tid * ldC + row];
     }
     __syncthreads();
+    long long t1 = 0;
+    if (timed) {
+      t1 = (long long)wall_clock64();
+      if (mode != 0) tq6 += t1 - t0;
+    }
     const int count = mode == 0 ? nsamp : (mode == 1 ? nrows : ncols);
     ArgMax best{-1.0, 0x7fffffff};
     T my_e = num<T>(0.0), my_a = num<T>(0.0);
-    for (int q = tid; q < count; q += blockDim.x) {
+    for (int q = g * (int)blockDim.x + tid; q < count; q += G * (int)blockDim.x) {
       int pr, pc;
       if (mode == 0) {
         const uint32_t id = uniform_below(splitmix_at(p.seed, sample_counter(sweep, b, q)), total);
@@ -741,10 +874,51 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
       seen = fmax(seen, fabs(n_hi(a)));
       if (better(ae, q, best.v, best.idx)) { best.v = ae; best.idx = q; my_e = e; my_a = a; }
     }
+    long long t2 = 0;
+    if (timed) t2 = (long long)wall_clock64();
     best = block_argmax(best, sm.red_v, sm.red_i);
+    if (timed) {
+      const long long t3 = (long long)wall_clock64();
+      if (mode == 0) {
+        tq0 += t2 - t1;
+        tq1 += t3 - t2;
+      } else {
+        tq3 += t2 - t1;
+        tq4 += t3 - t2;
+      }
+      t0 = t3;
+    }
+    if constexpr (!is_ext_t<T>::value) {
+      if (G > 1) {   // the members' argmaxes combined (with the winner's error and value at a row step)
+        if (mode == 2) {
+          if (best.idx % (int)blockDim.x == tid) {
+            sm.e_star = my_e;
+            sm.a_star = my_a;
+          }
+          __syncthreads();
+        }
+        const XRec mine{best.v, mode == 2 ? sm.e_star : 0.0, mode == 2 ? sm.a_star : 0.0, best.idx};
+        const XRec r = group_exchange(xs, g, G, xtag0 + xstep++, true, false, mine, sm.xres, sm.xfail);
+        best.v = r.v;
+        best.idx = r.idx;
+        my_e = r.e;   // held by every thread: the owner test below is replaced
+        my_a = r.a;
+        if (timed) {
+          const long long t4 = (long long)wall_clock64();
+          if (mode == 0) tq2 += t4 - t0;
+          else tq5 += t4 - t0;
+          t0 = t4;
+        }
+        if (sm.xfail) {
+          if (tid == 0) atomicOr(&st->err_flags, 16);
+          invalid = true;
+          break;
+        }
+      }
+    }
     if (!(best.v >= 0.0)) { invalid = true; break; }   // every error non-finite
     if (mode == 0) {
-      mark(p, sweep, b, 2);
+      if (g == 0) mark(p, sweep, b, 2);
       const uint32_t id = uniform_below(splitmix_at(p.seed, sample_counter(sweep, b, best.idx)), total);
       row = (int)(id / (uint32_t)ncols);
       col = (int)(id % (uint32_t)ncols);
@@ -756,7 +930,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
       mode = 2;
       continue;
     }
-    if (best.idx % (int)blockDim.x == tid) {   // the thread that evaluated the winner
+    if (G > 1 ? tid == 0 : best.idx % (int)blockDim.x == tid) {   // the thread that evaluated the winner
       sm.e_star = my_e;
       sm.a_star = my_a;
     }
@@ -768,9 +942,31 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
     if (same || iters == kRook) break;
     mode = 1;
   }
-  mark(p, sweep, b, 3);
+  if (g == 0) {
+    mark(p, sweep, b, 3);
+    mark_value(p, sweep, b, 8, tq0);
+    mark_value(p, sweep, b, 9, tq1);
+    mark_value(p, sweep, b, 10, tq2);
+    mark_value(p, sweep, b, 11, tq3);
+    mark_value(p, sweep, b, 12, tq4);
+    mark_value(p, sweep, b, 13, tq5);
+    mark_value(p, sweep, b, 14, tq6);
+  }
   seen = block_max(seen, sm.red_v);
-  const int any_bad = __syncthreads_or(bad);
+  int any_bad = __syncthreads_or(bad);
+  if constexpr (!is_ext_t<T>::value) {
+    if (G > 1) {   // every member's largest |B| and flags; also: every member's writes are done
+      const XRec r = group_exchange(xs, g, G, xtag0 + xstep++, false, true, XRec{seen, 0.0, 0.0, any_bad}, sm.xres,
+                                    sm.xfail);
+      seen = r.v;
+      any_bad = r.idx;
+      if (sm.xfail) {
+        if (tid == 0) atomicOr(&st->err_flags, 16);
+        invalid = true;
+      }
+    }
+  }
+  if (g != 0) return false;
   // is either half of the pivot already in its set? (one thread per set element)
   const int al_s = row / n, i_s = row - al_s * n;
   const int j_s = col / rR, be_s = col - j_s * rR;
@@ -792,6 +988,7 @@ __device__ __forceinline__ void search_bond(const ProbDesc& p, const int b, Sear
     const int per_step = nrows + ncols;
     atomicAdd(&st->evals, (unsigned long long)(nsamp + iters * per_step));
   }
+  return true;
 }
 
 // ------------------------------------------------------------ core update
@@ -1888,7 +2085,12 @@ union SweepSmem {
 //
 // Tasks are taken in ticket order (an atomic counter), superblocks first, so a
 // core's workgroup only ever waits for searches that workgroups already running
-// hold: every wait ends whatever subset of workgroups is resident.  Each
+// hold: every wait ends whatever subset of workgroups is resident.  A superblock
+// searched by a cluster of G workgroups (consecutive tickets) has members that wait
+// for each other; the running workgroups always hold a prefix of the tickets, every
+// cluster inside that prefix completes without waiting on later tickets, and its
+// exit frees room for the rest of a cluster cut at the prefix's end, so these waits
+// end too.  Each
 // hand-over is a release fence plus an atomic increment; the core's workgroup
 // polls the counter and takes an acquire fence (an L2 invalidate) before it reads
 // the searches' results.  A wait beyond kWaitTicks of the constant clock gives up
@@ -1899,13 +2101,13 @@ union SweepSmem {
 // thousand superblocks per launch) are compiled for four waves per SIMD (at most
 // 128 VGPRs).  Measured on C_1024 before the row summaries, its sweeps took
 // 13.7 ms instead of 15.8.
-constexpr long long kWaitTicks = 1000000000LL;   // 10 s of the 100 MHz constant clock
 
 template <class T, int FAM, int MAXM, int RMAX>
-__device__ __forceinline__ void sweep_search(const ProbDesc& p, const int b, SweepSmem<T, MAXM, RMAX>& sm) {
+__device__ __forceinline__ void sweep_search(const ProbDesc& p, const int b, const int g, const int G,
+                                             SweepSmem<T, MAXM, RMAX>& sm) {
   if (p.st->done) return;
   const int sweep = p.st->sweeps;
-  search_bond<T, FAM, MAXM>(p, b, sm.s);
+  if (!search_bond<T, FAM, MAXM>(p, b, g, G, sm.s)) return;   // members other than 0 are done
   __syncthreads();
   mark(p, sweep, b, 4);
   if (threadIdx.x == 0) {
@@ -1959,21 +2161,23 @@ __device__ __forceinline__ void sweep_core(const ProbDesc& p, const int c, Sweep
 }
 
 // ctr: two launch counters (tickets taken, workgroups finished), zero at launch.
-// The grid is nbond + ncore workgroups.
+// group: workgroups per superblock search (1..kMaxGroup; 1 for double-double and
+// quad-double jobs).  The grid is group * nbond + ncore workgroups; the members of
+// one superblock take consecutive tickets.
 template <class T, int FAM, int MAXM, int RMAX>
 __global__ __launch_bounds__(kSweepBlock, FAM == 0 && MAXM == 0 && RMAX <= 16 ? 4 : 1) void k_sweep(
     ProbDesc* __restrict__ P, const int2* __restrict__ bond_tasks, int nbond, const int2* __restrict__ core_tasks,
-    int32_t* __restrict__ ctr) {
+    int32_t* __restrict__ ctr, int group) {
   __shared__ SweepSmem<T, MAXM, RMAX> sm;
   __shared__ int s_task, s_flag;
   if (threadIdx.x == 0) s_task = atomicAdd(&ctr[0], 1);
   __syncthreads();
   const int t = s_task;
-  if (t < nbond) {
-    const int2 tk = bond_tasks[t];
-    sweep_search<T, FAM, MAXM, RMAX>(P[tk.x], tk.y, sm);
+  if (t < group * nbond) {
+    const int2 tk = bond_tasks[t / group];
+    sweep_search<T, FAM, MAXM, RMAX>(P[tk.x], tk.y, t % group, group, sm);
   } else {
-    const int2 tk = core_tasks[t - nbond];
+    const int2 tk = core_tasks[t - group * nbond];
     sweep_core<T, FAM, MAXM, RMAX>(P[tk.x], tk.y, sm, s_flag);
   }
   if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) + 1 == (int)gridDim.x) {   // every ticket was taken

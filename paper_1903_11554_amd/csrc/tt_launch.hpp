@@ -18,6 +18,7 @@ struct LaunchArgs {
   int mbucket;        // compile-time bound on the number of modes (0: streaming, any number)
   hipStream_t stream;
   int32_t* sweep_ctr; // two launch counters of the sweep kernel (zero between launches)
+  int group;          // workgroups per superblock search (1 for the extended precisions)
 };
 
 enum { LAUNCH_START = 0, LAUNCH_INIT_UPDATE = 1, LAUNCH_SWEEP = 2, LAUNCH_ALS = 3 };

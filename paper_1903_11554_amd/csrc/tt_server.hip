@@ -206,7 +206,7 @@ tt_status start_requests(tt_server* s, std::vector<Running>& fresh) {
   }
   TT_HIP(hipEventRecord(s->stage_ev[si], ctx->stream));
   LaunchArgs a{(ProbDesc*)(s->dtable + s->off_idesc), nullptr, 0, (const int2*)(s->dtable + s->off_itask),
-               (int)itask.size(), (int)fresh.size(), bucket_m_for(fam, TT_FP64, maxm), ctx->stream, nullptr};
+               (int)itask.size(), (int)fresh.size(), bucket_m_for(fam, TT_FP64, maxm), ctx->stream, nullptr, 1};
   auto go = [&](int what) {
     switch (fam) {
       case FAM_PAPER: launch_paper(a, what, 8); break;
@@ -347,7 +347,7 @@ void worker_main(tt_server* s) {
         }
         LaunchArgs a{(ProbDesc*)(s->dtable + s->off_sdesc), (const int2*)(s->dtable + s->off_stask), nbond,
                      (const int2*)(s->dtable + s->off_score), ncore, (int)s->running.size(),
-                     bucket_m_for(fam, TT_FP64, maxm), ctx->stream, (int32_t*)(s->dtable + s->off_ctr)};
+                     bucket_m_for(fam, TT_FP64, maxm), ctx->stream, (int32_t*)(s->dtable + s->off_ctr), 1};
         {
           Timed tm(ctx, KK_SWEEP);
           switch (fam) {

@@ -43,6 +43,7 @@ struct tt_job {
   bool full_bucket = false;   // sweeps were enqueued for graph capture: size kernels for the rank caps
   int mbucket = 0;            // mode bucket of the job's kernels (the rule's, or a tuned one)
   int rank_policy = 0;        // 1: every sweep kernel sized for the rank caps (tuned)
+  int group = 1;              // workgroups per superblock search
   std::vector<std::pair<double*, double*>> gl64;   // per integral: the double node tables
   int launched = 0;       // sweeps enqueued so far
   int max_sweeps_all = 0;
@@ -133,7 +134,8 @@ void pinned_give(tt_ctx* c, char* p, size_t bytes) {
 }
 
 void launch(tt_job* j, int what, int rb) {
-  LaunchArgs a{j->ddesc, j->dbond, j->nbond, j->dcore, j->ncore, j->nprob, j->mbucket, j->ctx->stream, j->dctr};
+  LaunchArgs a{j->ddesc,   j->dbond,       j->nbond, j->dcore, j->ncore,
+               j->nprob,   j->mbucket,     j->ctx->stream, j->dctr, j->group};
   Timed tm(j->ctx, what == LAUNCH_SWEEP   ? KK_SWEEP
                    : what == LAUNCH_START ? KK_START
                    : what == LAUNCH_ALS   ? KK_REFRESH
@@ -393,6 +395,10 @@ tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
   tt_ctx* c = new (std::nothrow) tt_ctx;
   if (!c) return TT_ENOMEM;
   c->device = device;
+  if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    delete c;
+    return TT_EDEVICE;
+  }
   if (scratch_address(device, &c->scratch) != TT_OK) {
     delete c;
     return TT_EDEVICE;
@@ -452,6 +458,13 @@ tt_status tt_ctx_profile(tt_ctx* c, int32_t enable) {
     c->kernel_ms[k] = 0.0;
     c->kernel_launches[k] = 0;
   }
+  return TT_OK;
+}
+
+tt_status tt_ctx_set_search_group(tt_ctx* c, int32_t group) {
+  if (!c || group < 0 || group > kMaxGroup) return TT_EINVAL;
+  std::lock_guard<std::mutex> lock(c->mu);
+  c->search_group = group;
   return TT_OK;
 }
 
@@ -656,6 +669,8 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->dctr = (int32_t*)(base + ctr_off);
   j->nbond = (int)bond_tasks.size();
   j->ncore = (int)core_tasks.size();
+  j->group = ctx->search_group > 0 && j->prec == TT_FP64 ? ctx->search_group
+                                                         : search_group_rule(ctx->cus, j->nbond, j->ncore, j->prec);
   // one pinned block (reused from the context when possible): done flags, then
   // the host image of the table region, the source of the asynchronous upload
   const size_t flags_bytes = (sizeof(int32_t) * count + 255) & ~size_t(255);

@@ -81,7 +81,7 @@ EXPORTS = [
     "tt_cross_init", "tt_cross_sweep", "tt_cross_run", "tt_cross_integrate",
     "tt_job_pivot_log", "tt_job_history", "tt_job_index_sets", "tt_job_nodes",
     "tt_cross_free", "tt_eval_points", "tt_eval_fibers", "tt_status_string",
-    "tt_ctx_profile", "tt_ctx_kernel_time", "tt_job_phase_times",
+    "tt_ctx_profile", "tt_ctx_set_search_group", "tt_ctx_kernel_time", "tt_job_phase_times",
     "tt_server_create", "tt_server_submit", "tt_server_poll", "tt_server_wait",
     "tt_server_get_stats", "tt_server_destroy", "tt_cross_enqueue", "tt_mc_integrate",
     "tt_mc_integrate_noalloc", "tt_job_core", "tt_batch_run", "tt_autotune", "tt_cross_refresh",
@@ -129,6 +129,7 @@ def load_library():
         "tt_eval_fibers": (i32, [vp, P(_Problem), i32, vp, i32, vp, i32, vp]),
         "tt_status_string": (ctypes.c_char_p, [i32]),
         "tt_ctx_profile": (i32, [vp, i32]),
+        "tt_ctx_set_search_group": (i32, [vp, i32]),
         "tt_ctx_kernel_time": (i32, [vp, i32, P(i64), P(dbl)]),
         "tt_job_phase_times": (i32, [vp, i32, P(i64), i64, P(i64), P(dbl)]),
         "tt_server_create": (i32, [vp, ctypes.c_size_t, i32, P(vp)]),
@@ -212,6 +213,10 @@ class Context:
     def profile(self, enable=True):
         """Switch per-kernel event timing on/off (clears the totals)."""
         _check(self._lib.tt_ctx_profile(self.handle, 1 if enable else 0), "tt_ctx_profile")
+
+    def set_search_group(self, group):
+        """Workgroups per superblock search for later double jobs (0: the rule; results are identical)."""
+        _check(self._lib.tt_ctx_set_search_group(self.handle, int(group)), "tt_ctx_set_search_group")
 
     def kernel_time(self, kind):
         """(launches, total_ms) of a kernel kind since profiling was switched on."""
