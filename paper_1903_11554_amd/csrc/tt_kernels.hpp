@@ -1450,39 +1450,43 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     if (accR) {
       const int prow = p.piv[c].row;   // the row of F_c appended to I_<=c this sweep
       // (c) border the LU: w = L^-1 u, l = v U^-1 and the pivot delta, with u = F_c(I_<=c, r0)
-      //     the new column at the old cross rows and v = F_c(prow, :r0)
-      if (tid < kWave) {
-        T wa = (tid < r0) ? Fc[(size_t)sm.rowidx[tid] * cc + r0] : num<T>(0.0);
-        T lq = (tid < r0) ? Fc[(size_t)prow * cc + tid] : num<T>(0.0);
-        if (tid < r0) sm.u[tid] = wa;
-        for (int k2 = 0; k2 < r0; ++k2) {
-          const T wk = n_shfl(wa, k2);
-          if (tid > k2 && tid < r0) wa = n_nmad(sm.A[tid * LA + k2], wk, wa);
-        }
-        for (int k2 = 0; k2 < r0; ++k2) {
-          const T lk = n_div(n_shfl(lq, k2), sm.A[k2 * LA + k2]);
-          if (tid == k2) lq = lk;
-          else if (tid > k2 && tid < r0) lq = n_nmad(lk, sm.A[k2 * LA + tid], lq);
-        }
-        if (tid < r0) {
-          LU[(size_t)r0 * R + tid] = lq;
-          LU[(size_t)tid * R + r0] = wa;
-        }
-      }
-      if (tid < r0) sm.cp[tid] = Cc[(size_t)tid * ldC + prow];   // C_c(prow, :) before the update
-      __syncthreads();
+      //     the new column at the old cross rows and v = F_c(prow, :r0).  The three are
+      //     independent sequential chains, one wave each (lane k holds entry k).
+      //
       // The pivot is the residual of the new cross row, delta = F_c(prow, r0) - C_c(prow, :) u
       // (equal to F_c(prow, r0) - l . w in exact arithmetic), computed with the very operations
       // the update below applies to row prow: the update then gives C_c(prow, :) = e_r0 exactly,
       // keeping the interpolation property at the new cross row.  With the Schur complement of
       // the bordered LU instead, the two roundings differ by about eps |C_c(prow,:)| |u|, which
       // a pivot near the rounding level of the cross turns into an O(1) error of that row.
-      if (tid == 0) {
+      const int wv = tid / kWave, ln = tid % kWave;
+      if (wv == 0) {
+        T wa = (ln < r0) ? Fc[(size_t)sm.rowidx[ln] * cc + r0] : num<T>(0.0);
+        if (ln < r0) sm.u[ln] = wa;
+        for (int k2 = 0; k2 < r0; ++k2) {
+          const T wk = n_shfl(wa, k2);
+          if (ln > k2 && ln < r0) wa = n_nmad(sm.A[ln * LA + k2], wk, wa);
+        }
+        if (ln < r0) LU[(size_t)ln * R + r0] = wa;
+      } else if (wv == 1) {
+        T lq = (ln < r0) ? Fc[(size_t)prow * cc + ln] : num<T>(0.0);
+        for (int k2 = 0; k2 < r0; ++k2) {
+          const T lk = n_div(n_shfl(lq, k2), sm.A[k2 * LA + k2]);
+          if (ln == k2) lq = lk;
+          else if (ln > k2 && ln < r0) lq = n_nmad(lk, sm.A[k2 * LA + ln], lq);
+        }
+        if (ln < r0) LU[(size_t)r0 * R + ln] = lq;
+      } else if (wv == 2) {
+        const T uk = (ln < r0) ? Fc[(size_t)sm.rowidx[ln] * cc + r0] : num<T>(0.0);
+        const T ck = (ln < r0) ? Cc[(size_t)ln * ldC + prow] : num<T>(0.0);   // C_c(prow, :) before the update
+        if (ln < r0) sm.cp[ln] = ck;
         T e = Fc[(size_t)prow * cc + r0];
-        for (int k = 0; k < r0; ++k) e = n_nmad(sm.cp[k], sm.u[k], e);
-        LU[(size_t)r0 * R + r0] = e;
-        sm.delta = e;
-        // a zero pivot leaves C_c non-finite: the core is then recomputed (below)
+        for (int k = 0; k < r0; ++k) e = n_nmad(n_shfl(ck, k), n_shfl(uk, k), e);
+        if (ln == 0) {
+          LU[(size_t)r0 * R + r0] = e;
+          sm.delta = e;
+          // a zero pivot leaves C_c non-finite: the core is then recomputed (below)
+        }
       }
       __syncthreads();
       if (mb >= 0) mark(p, msw, mb, 12);
