@@ -350,11 +350,12 @@ tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
 
 /* Workgroups per superblock search for double jobs created after the call
  * (a launch shape, not part of the method: every group size gives the same
- * values, pivots and evaluation counts bit for bit).  group 1..8 fixes it; 0
- * returns to the rule, as many as keep one compute unit per workgroup of a
- * sweep launch (superblocks x group + cores <= compute units), at most 8.
- * Double-double and quad-double jobs always search with one workgroup.  The
- * serving loop's launches use one.  Errors: TT_EINVAL outside 0..8. */
+ * values, pivots and evaluation counts bit for bit).  group 1..8 fixes it
+ * (over any tuned choice); 0 returns to the tuned group, else the rule: as many
+ * as keep one compute unit per workgroup of a sweep launch (superblocks x group
+ * + cores <= compute units), at most 3.  Double-double and quad-double jobs
+ * always search with one workgroup.  The serving loop's launches use one.
+ * Errors: TT_EINVAL outside 0..8. */
 tt_status tt_ctx_set_search_group(tt_ctx *ctx, int32_t group);
 tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);
 
@@ -420,8 +421,14 @@ void tt_server_destroy(tt_server *server);
  *                kernel, any number of modes, double precision, paper form and
  *                synthetic classes);
  *   rank_policy  0: each sweep's kernel is sized for the ranks reachable in that
- *                sweep; 1: for the rank caps.
- * Without tuning a job takes the smallest mode bucket and policy 0 (the rule).
+ *                sweep; 1: for the rank caps;
+ *   search_group workgroups per superblock search (double jobs; see
+ *                tt_ctx_set_search_group), 0 for the rule's.
+ * Without tuning a job takes the smallest mode bucket, policy 0 and the rule's
+ * search group (the rule).  The candidates: every valid mode bucket with both
+ * policies at the rule's group, and the rule's bucket and policy 0 with search
+ * groups 1, 2, 4 and 6 (double jobs, when tt_ctx_set_search_group has not fixed
+ * the group).
  * tt_autotune runs the given job once per candidate variant (`reps` times each,
  * median wall time from tt_cross_init to the stopping rule), keeps only the
  * variants whose results equal the rule's bit for bit (every value, sweep count
@@ -439,7 +446,7 @@ typedef struct {
   int32_t rule_mode_bucket;
   int32_t candidates;    /* variants timed                                             */
   int32_t matching;      /* of those, variants whose results equal the rule's          */
-  int32_t reserved;
+  int32_t search_group;  /* chosen search group (0: the rule's)                        */
   double  rule_ms;       /* median time of the rule's variant                          */
   double  tuned_ms;      /* median time of the chosen variant                          */
 } tt_tune_result;

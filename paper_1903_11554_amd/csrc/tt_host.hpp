@@ -67,27 +67,31 @@ struct tt_ctx {
   double* scratch = nullptr;                       // this device's static scratch (tt_mc_integrate_noalloc)
   size_t arena_bytes_cached = 0;
   // kernel variants chosen by tt_autotune, per (integrand class, double-double,
-  // largest m, largest rank cap): (mode bucket, rank policy, rule ms, tuned ms)
+  // largest m, largest rank cap): (mode bucket, rank policy, rule ms, tuned ms,
+  // search group; 0: the rule's)
   struct Tuned {
     int mbucket, rank_policy;
     double rule_ms, tuned_ms;
+    int group;
   };
   std::map<std::array<int, 4>, Tuned> tune;
   std::string tune_path;                           // TTCROSS_TUNE_CACHE, or empty
   bool force_variant = false;                      // tt_autotune's candidate for the next job
-  Tuned forced{0, 0, 0.0, 0.0};
+  Tuned forced{0, 0, 0.0, 0.0, 0};
   int cus = 0;                                     // compute units of the device
   int search_group = 0;                            // workgroups per superblock search (0: the rule)
 };
 
 // Workgroups per superblock search of a double job with nbond superblocks and
-// ncore cores: as many as leave one compute unit per workgroup (at most
-// kMaxGroup), so that the whole grid is resident at once; 1 for the extended
-// precisions.
+// ncore cores: as many as leave one compute unit per workgroup, so that the
+// whole grid is resident at once, but at most kRuleGroup (on the headline
+// Ising job 3 measured fastest: each member adds a record to every exchange);
+// 1 for the extended precisions.  tt_autotune may choose another.
+constexpr int kRuleGroup = 3;
 inline int search_group_rule(int cus, int nbond, int ncore, int prec) {
   if (prec != TT_FP64 || nbond <= 0) return 1;
   const int g = (cus - ncore) / nbond;
-  return g < 1 ? 1 : g > kMaxGroup ? kMaxGroup : g;
+  return g < 1 ? 1 : g > kRuleGroup ? kRuleGroup : g;
 }
 
 // Arenas of freed jobs are kept by the context (up to this many bytes) and

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -335,8 +336,9 @@ tt_status scratch_address(int device, double** out) {
 }  // namespace
 
 // ---------------------------------------------------------------- autotuning
-// Cache file: one key per line, "class dd max_modes max_rank mode_bucket
-// rank_policy rule_ms tuned_ms"; lines starting with '#' are comments.  Entries
+// Cache file: one key per line, "class precision max_modes max_rank mode_bucket
+// rank_policy rule_ms tuned_ms search_group" (a line without the last field reads
+// as search group 0, the rule's); lines starting with '#' are comments.  Entries
 // that name a variant the key cannot launch are ignored.
 static void tune_load(tt_ctx* c) {
   FILE* f = std::fopen(c->tune_path.c_str(), "r");
@@ -344,14 +346,15 @@ static void tune_load(tt_ctx* c) {
   char line[256];
   while (std::fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
-    int fam, prec, maxm, maxR, mb, pol;
+    int fam, prec, maxm, maxR, mb, pol, grp = 0;
     double rule_ms, tuned_ms;
-    if (std::sscanf(line, "%d %d %d %d %d %d %lf %lf", &fam, &prec, &maxm, &maxR, &mb, &pol, &rule_ms, &tuned_ms) != 8)
-      continue;
+    const int got = std::sscanf(line, "%d %d %d %d %d %d %lf %lf %d", &fam, &prec, &maxm, &maxR, &mb, &pol, &rule_ms,
+                                &tuned_ms, &grp);
+    if (got != 8 && got != 9) continue;
     if (fam < FAM_PAPER || fam > FAM_ANY || prec < TT_FP64 || prec > TT_QD || (pol != 0 && pol != 1) ||
-        !variant_valid(fam, prec, maxm, mb))
+        !variant_valid(fam, prec, maxm, mb) || grp < 0 || grp > kMaxGroup)
       continue;
-    c->tune[tune_key(fam, prec, maxm, maxR)] = tt_ctx::Tuned{mb, pol, rule_ms, tuned_ms};
+    c->tune[tune_key(fam, prec, maxm, maxR)] = tt_ctx::Tuned{mb, pol, rule_ms, tuned_ms, grp};
   }
   std::fclose(f);
 }
@@ -361,10 +364,12 @@ static tt_status tune_save(tt_ctx* c) {
   const std::string tmp = c->tune_path + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return TT_EDEVICE;
-  std::fprintf(f, "# ttcross kernel variants: class precision max_modes max_rank mode_bucket rank_policy rule_ms tuned_ms\n");
+  std::fprintf(f,
+               "# ttcross kernel variants: class precision max_modes max_rank mode_bucket rank_policy rule_ms tuned_ms "
+               "search_group\n");
   for (const auto& e : c->tune)
-    std::fprintf(f, "%d %d %d %d %d %d %.6f %.6f\n", e.first[0], e.first[1], e.first[2], e.first[3],
-                 e.second.mbucket, e.second.rank_policy, e.second.rule_ms, e.second.tuned_ms);
+    std::fprintf(f, "%d %d %d %d %d %d %.6f %.6f %d\n", e.first[0], e.first[1], e.first[2], e.first[3],
+                 e.second.mbucket, e.second.rank_policy, e.second.rule_ms, e.second.tuned_ms, e.second.group);
   const bool ok = std::fclose(f) == 0;
   if (!ok || std::rename(tmp.c_str(), c->tune_path.c_str()) != 0) return TT_EDEVICE;
   return TT_OK;
@@ -489,12 +494,16 @@ tt_status tt_autotune(tt_ctx* ctx, const tt_problem* problems, int32_t count, in
   }
   const int prec = problems[0].precision;
   const int rule_mb = bucket_m_for(fam, prec, maxm);
-  std::vector<std::pair<int, int>> cands{{rule_mb, 0}, {rule_mb, 1}};
+  // (mode bucket, rank policy, search group; 0: the rule's)
+  std::vector<std::array<int, 3>> cands{{rule_mb, 0, 0}, {rule_mb, 1, 0}};
   for (int mb : mode_buckets(fam, prec))
     if (mb != rule_mb && variant_valid(fam, prec, maxm, mb)) {
-      cands.push_back({mb, 0});
-      cands.push_back({mb, 1});
+      cands.push_back({mb, 0, 0});
+      cands.push_back({mb, 1, 0});
     }
+  if (prec == TT_FP64 && ctx->search_group == 0)
+    for (int g : {1, 2, 4, 6})   // the rule's variant with other search groups
+      cands.push_back({rule_mb, 0, g});
   std::vector<tt_info> ref(count), got(count);
   auto same = [&](const std::vector<tt_info>& a, const std::vector<tt_info>& b) {
     for (int k = 0; k < count; ++k)
@@ -509,7 +518,7 @@ tt_status tt_autotune(tt_ctx* ctx, const tt_problem* problems, int32_t count, in
     std::vector<double> ms;
     bool match = true;
     for (int r = 0; r < reps && match; ++r) {
-      ctx->forced = tt_ctx::Tuned{cands[c].first, cands[c].second, 0.0, 0.0};
+      ctx->forced = tt_ctx::Tuned{cands[c][0], cands[c][1], 0.0, 0.0, cands[c][2]};
       ctx->force_variant = true;
       if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
         ctx->force_variant = false;
@@ -541,13 +550,14 @@ tt_status tt_autotune(tt_ctx* ctx, const tt_problem* problems, int32_t count, in
       best_ms = med;
     }
   }
-  ctx->tune[tune_key(fam, prec, maxm, maxR)] = tt_ctx::Tuned{cands[best].first, cands[best].second, rule_ms, best_ms};
-  out->mode_bucket = cands[best].first;
-  out->rank_policy = cands[best].second;
+  ctx->tune[tune_key(fam, prec, maxm, maxR)] =
+      tt_ctx::Tuned{cands[best][0], cands[best][1], rule_ms, best_ms, cands[best][2]};
+  out->mode_bucket = cands[best][0];
+  out->rank_policy = cands[best][1];
   out->rule_mode_bucket = rule_mb;
   out->candidates = (int32_t)cands.size();
   out->matching = matching;
-  out->reserved = 0;
+  out->search_group = cands[best][2];
   out->rule_ms = rule_ms;
   out->tuned_ms = best_ms;
   return tune_save(ctx);
@@ -612,14 +622,17 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   }
   // kernel variant: the rule's, a tuned one recorded in the context, or tt_autotune's candidate
   j->mbucket = bucket_m_for(j->fam, j->prec, j->maxm);
+  int tuned_group = 0;
   if (ctx->force_variant) {
     j->mbucket = ctx->forced.mbucket;
     j->rank_policy = ctx->forced.rank_policy;
+    tuned_group = ctx->forced.group;
   } else {
     auto t = ctx->tune.find(tune_key(j->fam, j->prec, j->maxm, j->maxR));
     if (t != ctx->tune.end() && variant_valid(j->fam, j->prec, j->maxm, t->second.mbucket)) {
       j->mbucket = t->second.mbucket;
       j->rank_policy = t->second.rank_policy;
+      tuned_group = t->second.group;
     }
   }
   Layout L;
@@ -669,8 +682,10 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->dctr = (int32_t*)(base + ctr_off);
   j->nbond = (int)bond_tasks.size();
   j->ncore = (int)core_tasks.size();
-  j->group = ctx->search_group > 0 && j->prec == TT_FP64 ? ctx->search_group
-                                                         : search_group_rule(ctx->cus, j->nbond, j->ncore, j->prec);
+  if (j->prec != TT_FP64) j->group = 1;
+  else if (ctx->search_group > 0) j->group = ctx->search_group;   // tt_ctx_set_search_group
+  else if (tuned_group > 0) j->group = tuned_group;
+  else j->group = search_group_rule(ctx->cus, j->nbond, j->ncore, j->prec);
   // one pinned block (reused from the context when possible): done flags, then
   // the host image of the table region, the source of the asynchronous upload
   const size_t flags_bytes = (sizeof(int32_t) * count + 255) & ~size_t(255);

@@ -48,7 +48,7 @@ class _Problem(ctypes.Structure):
 class _TuneResult(ctypes.Structure):
     _fields_ = [("mode_bucket", ctypes.c_int32), ("rank_policy", ctypes.c_int32),
                 ("rule_mode_bucket", ctypes.c_int32), ("candidates", ctypes.c_int32),
-                ("matching", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("matching", ctypes.c_int32), ("search_group", ctypes.c_int32),
                 ("rule_ms", ctypes.c_double), ("tuned_ms", ctypes.c_double)]
 
 
@@ -270,7 +270,7 @@ class Context:
         arr = (_Problem * len(problems))(*[_c_problem(p, keep) for p in problems])
         res = _TuneResult()
         _check(self._lib.tt_autotune(self.handle, arr, len(problems), reps, ctypes.byref(res)), "tt_autotune")
-        return {f: getattr(res, f) for f, _ in _TuneResult._fields_ if f != "reserved"}
+        return {f: getattr(res, f) for f, _ in _TuneResult._fields_}
 
     def server(self, max_bytes=1 << 30, max_active=256):
         return Server(self, max_bytes, max_active)

@@ -39,13 +39,16 @@ def test_autotune_records_a_bit_identical_variant(tmp_path, monkeypatch):
     assert res["candidates"] >= 4 and 1 <= res["matching"] <= res["candidates"]
     assert res["mode_bucket"] in (8, 10, 12, 16, 24, 32, 0) and res["mode_bucket"] >= 0
     assert res["tuned_ms"] <= res["rule_ms"] and res["rule_ms"] > 0
+    assert res["search_group"] in (0, 1, 2, 4, 6)
     assert results(ctx, probs) == base             # the tuned variant gives the rule's bits
     ctx.close()
     lines = [l.split() for l in cache.read_text().splitlines() if not l.startswith("#")]
-    assert len(lines) == 1
+    assert len(lines) == 1 and len(lines[0]) == 9
     fam, dd, maxm, maxr, mb, pol = (int(x) for x in lines[0][:6])
     assert (fam, dd, maxm, maxr, mb, pol) == (0, 0, 6, 16, res["mode_bucket"], res["rank_policy"])
-    # a fresh context loads the cache; a stale entry (bucket 4 < 6 modes) is ignored
+    assert int(lines[0][8]) == res["search_group"]
+    # a fresh context loads the cache; a stale entry (bucket 4 < 6 modes, in the
+    # eight-field form without a search group) is ignored
     with open(cache, "a") as f:
         f.write("0 0 6 32 4 0 1.0 0.5\n")
     ctx2 = Context(0)
