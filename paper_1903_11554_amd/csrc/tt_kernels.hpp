@@ -144,6 +144,7 @@ __device__ __forceinline__ void signal_done(const ProbDesc& p) {
 
 constexpr int kBlock = 256;        // start, standalone evaluation
 constexpr int kSweepBlock = 512;   // sweep and update kernels: 8 waves per workgroup
+static_assert(kSweepBlock == 8 * kWave, "the core update assigns its phases to waves 0..7");
 constexpr int kStart = 1024;       // rank-1 start samples
 constexpr int kMaxSamples = 1024;
 constexpr int kRook = 5;
@@ -1399,9 +1400,13 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
     if (tid < r0) sm.rowidx[tid] = p.Lpar[(size_t)c * R + tid] * n + p.Lnode[(size_t)c * R + tid];
     __syncthreads();
     // (a) rows of the new element of I_<=c-1: solve x M_c = f with M_c = L U
-    //     (x L) U = f: forward over columns for g = x L, then backward over rows for x
-    if (accL) {
-      for (int i = tid; i < n; i += blockDim.x) {
+    //     (x L) U = f: forward over columns for g = x L, then backward over rows for x.
+    //     (a) and the bordering (c) below are independent (c reads only old rows of
+    //     C_c); (a) runs on waves 0 and 4..7, (c) on waves 1..3, side by side.
+    const int wv = tid / kWave, ln = tid % kWave;
+    const int aslot = wv == 0 ? 0 : wv - 3;   // waves 0, 4, 5, 6, 7 -> slots 0..4
+    if (accL && (wv == 0 || wv >= 4)) {
+      for (int i = aslot * kWave + ln; i < n; i += 5 * kWave) {
         const int row = rL_old * n + i;
         if constexpr (kRowInRegs) {
           T x[RMAX];
@@ -1451,7 +1456,8 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
       const int prow = p.piv[c].row;   // the row of F_c appended to I_<=c this sweep
       // (c) border the LU: w = L^-1 u, l = v U^-1 and the pivot delta, with u = F_c(I_<=c, r0)
       //     the new column at the old cross rows and v = F_c(prow, :r0).  The three are
-      //     independent sequential chains, one wave each (lane k holds entry k).
+      //     independent sequential chains, one wave each (waves 1, 2, 3; lane k holds
+      //     entry k), run while the other waves solve the new rows (a).
       //
       // The pivot is the residual of the new cross row, delta = F_c(prow, r0) - C_c(prow, :) u
       // (equal to F_c(prow, r0) - l . w in exact arithmetic), computed with the very operations
@@ -1459,8 +1465,7 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
       // keeping the interpolation property at the new cross row.  With the Schur complement of
       // the bordered LU instead, the two roundings differ by about eps |C_c(prow,:)| |u|, which
       // a pivot near the rounding level of the cross turns into an O(1) error of that row.
-      const int wv = tid / kWave, ln = tid % kWave;
-      if (wv == 0) {
+      if (wv == 1) {
         T wa = (ln < r0) ? Fc[(size_t)sm.rowidx[ln] * cc + r0] : num<T>(0.0);
         if (ln < r0) sm.u[ln] = wa;
         for (int k2 = 0; k2 < r0; ++k2) {
@@ -1468,7 +1473,7 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
           if (ln > k2 && ln < r0) wa = n_nmad(sm.A[ln * LA + k2], wk, wa);
         }
         if (ln < r0) LU[(size_t)ln * R + r0] = wa;
-      } else if (wv == 1) {
+      } else if (wv == 2) {
         T lq = (ln < r0) ? Fc[(size_t)prow * cc + ln] : num<T>(0.0);
         for (int k2 = 0; k2 < r0; ++k2) {
           const T lk = n_div(n_shfl(lq, k2), sm.A[k2 * LA + k2]);
@@ -1476,7 +1481,7 @@ __device__ __forceinline__ void update_core(const ProbDesc& p, const int c, cons
           else if (ln > k2 && ln < r0) lq = n_nmad(lk, sm.A[k2 * LA + ln], lq);
         }
         if (ln < r0) LU[(size_t)r0 * R + ln] = lq;
-      } else if (wv == 2) {
+      } else if (wv == 3) {
         const T uk = (ln < r0) ? Fc[(size_t)sm.rowidx[ln] * cc + r0] : num<T>(0.0);
         const T ck = (ln < r0) ? Cc[(size_t)ln * ldC + prow] : num<T>(0.0);   // C_c(prow, :) before the update
         if (ln < r0) sm.cp[ln] = ck;
