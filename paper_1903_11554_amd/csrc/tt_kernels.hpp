@@ -2086,25 +2086,25 @@ union SweepSmem {
   IntSmem<T> i;
 };
 
-// One sweep of Alg. 6 in one launch: one workgroup per superblock searches it
-// (Alg. 2), one workgroup per core updates the core once both neighbouring
-// searches are done, and the last core of an integral to finish runs the
-// quadrature and the stopping rule.  The two kinds run side by side, so a
-// superblock's workgroup never carries its cores' updates after its own search.
+// One sweep of Alg. 6 in one launch: G workgroups per superblock search it
+// together (Alg. 2; G = 1 for the extended precisions), one workgroup per core
+// updates the core once both neighbouring searches are done, and the last core
+// of an integral to finish runs the quadrature and the stopping rule.  The kinds
+// run side by side, so no search waits behind a core update.
 //
 // Tasks are taken in ticket order (an atomic counter), superblocks first, so a
 // core's workgroup only ever waits for searches that workgroups already running
-// hold: every wait ends whatever subset of workgroups is resident.  A superblock
-// searched by a cluster of G workgroups (consecutive tickets) has members that wait
-// for each other; the running workgroups always hold a prefix of the tickets, every
+// hold.  The members of a superblock's search (consecutive tickets) wait for each
+// other; the running workgroups always hold a prefix of the tickets, every
 // cluster inside that prefix completes without waiting on later tickets, and its
-// exit frees room for the rest of a cluster cut at the prefix's end, so these waits
-// end too.  Each
-// hand-over is a release fence plus an atomic increment; the core's workgroup
-// polls the counter and takes an acquire fence (an L2 invalidate) before it reads
-// the searches' results.  A wait beyond kWaitTicks of the constant clock gives up
-// (err_flags 16) and the integral stops with an error.  The last workgroup to
-// finish puts the launch counters back to zero for the next launch.
+// exit frees room for the rest of a cluster cut at the prefix's end.  So every
+// wait ends whatever subset of workgroups is resident.  The hand-over from a
+// search to its cores is a release fence plus an atomic increment by the search's
+// member 0; the core's workgroup polls the counter and takes an acquire fence (an
+// L2 invalidate) before it reads the searches' results.  A wait beyond kWaitTicks
+// of the constant clock gives up (err_flags 16) and the integral stops with an
+// error.  The last workgroup to finish puts the launch counters back to zero for
+// the next launch.
 //
 // The paper-form streaming kernels of rank 8 and 16 (the large integrals, a
 // thousand superblocks per launch) are compiled for four waves per SIMD (at most
