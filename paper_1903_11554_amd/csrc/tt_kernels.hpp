@@ -2351,8 +2351,8 @@ __device__ __forceinline__ void fibre_rows_items(int family, int m, int n, int p
     load_row_pair<T, MAXM>(rp, L, R, pos, pos + 1, nr);
     const T WL = L[MAXM + RS_W], WR = R[MAXM + RS_W];
     const int i0 = c * kFibreNodesPerLane;
-#pragma unroll 1
-    for (int k = 0; k < kFibreNodesPerLane; k += 2) {
+#pragma unroll
+    for (int k = 0; k < kFibreNodesPerLane; k += 2) {   // the node pairs of a lane unrolled: their chains interleave
       const int ia = i0 + k;
       if (ia >= n) break;
       const int ib = ia + 1 < n ? ia + 1 : ia;
