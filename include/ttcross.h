@@ -354,7 +354,8 @@ tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
  * (over any tuned choice); 0 returns to the tuned group, else the rule: as many
  * as keep one compute unit per workgroup of a sweep launch (superblocks x group
  * + cores <= compute units), at most 3.  Double-double and quad-double jobs
- * always search with one workgroup.  The serving loop's launches use one.
+ * always search with one workgroup.  A serving loop's launches take the rule
+ * for their running set, or the group fixed when the server was created.
  * Errors: TT_EINVAL outside 0..8. */
 tt_status tt_ctx_set_search_group(tt_ctx *ctx, int32_t group);
 tt_status tt_ctx_kernel_time(tt_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms);

@@ -107,6 +107,7 @@ struct tt_server {
   tt_ctx* ctx = nullptr;
   size_t max_bytes = 0;
   int max_active = 0;
+  int search_group = 0;                  // the context's fixed search group when the server was created (0: rule)
   char* arena = nullptr;                 // device
   SubAlloc* alloc = nullptr;
   // device table: sweep descriptors and tasks, init descriptors and core tasks
@@ -347,7 +348,8 @@ void worker_main(tt_server* s) {
         }
         LaunchArgs a{(ProbDesc*)(s->dtable + s->off_sdesc), (const int2*)(s->dtable + s->off_stask), nbond,
                      (const int2*)(s->dtable + s->off_score), ncore, (int)s->running.size(),
-                     bucket_m_for(fam, TT_FP64, maxm), ctx->stream, (int32_t*)(s->dtable + s->off_ctr), 1};
+                     bucket_m_for(fam, TT_FP64, maxm), ctx->stream, (int32_t*)(s->dtable + s->off_ctr),
+                     s->search_group > 0 ? s->search_group : search_group_rule(ctx->cus, nbond, ncore, TT_FP64)};
         {
           Timed tm(ctx, KK_SWEEP);
           switch (fam) {
@@ -415,6 +417,7 @@ tt_status tt_server_create(tt_ctx* ctx, size_t max_bytes, int32_t max_active, tt
   {
     std::lock_guard<std::mutex> cl(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(TT_EDEVICE);
+    s->search_group = ctx->search_group;
     if (hipMalloc(&s->arena, max_bytes) != hipSuccess) return fail(TT_ENOMEM);
     Layout L;
     s->off_sdesc = L.take(sizeof(ProbDesc) * max_active);
