@@ -353,7 +353,8 @@ tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
  * values, pivots and evaluation counts bit for bit).  group 1..8 fixes it
  * (over any tuned choice); 0 returns to the tuned group, else the rule: as many
  * as keep one compute unit per workgroup of a sweep launch (superblocks x group
- * + cores <= compute units), at most 3.  Double-double and quad-double jobs
+ * + cores <= compute units), at most 1, 2 or 3 for a launch sized for ranks up
+ * to 8, 16 or more.  Double-double and quad-double jobs
  * always search with one workgroup.  A serving loop's launches take the rule
  * for their running set, or the group fixed when the server was created.
  * Errors: TT_EINVAL outside 0..8. */

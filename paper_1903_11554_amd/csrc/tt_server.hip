@@ -349,7 +349,9 @@ void worker_main(tt_server* s) {
         LaunchArgs a{(ProbDesc*)(s->dtable + s->off_sdesc), (const int2*)(s->dtable + s->off_stask), nbond,
                      (const int2*)(s->dtable + s->off_score), ncore, (int)s->running.size(),
                      bucket_m_for(fam, TT_FP64, maxm), ctx->stream, (int32_t*)(s->dtable + s->off_ctr),
-                     s->search_group > 0 ? s->search_group : search_group_rule(ctx->cus, nbond, ncore, TT_FP64)};
+                     s->search_group > 0 ? s->search_group
+                                         : search_group_for_bucket(search_group_rule(ctx->cus, nbond, ncore, TT_FP64),
+                                                                   bucket_r(rmax))};
         {
           Timed tm(ctx, KK_SWEEP);
           switch (fam) {

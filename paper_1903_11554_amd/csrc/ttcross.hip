@@ -44,7 +44,8 @@ struct tt_job {
   bool full_bucket = false;   // sweeps were enqueued for graph capture: size kernels for the rank caps
   int mbucket = 0;            // mode bucket of the job's kernels (the rule's, or a tuned one)
   int rank_policy = 0;        // 1: every sweep kernel sized for the rank caps (tuned)
-  int group = 1;              // workgroups per superblock search
+  int group = 1;              // workgroups per superblock search (the rule's: its largest)
+  bool group_ruled = false;   // the group is the rule's (not fixed by the context or tuned)
   std::vector<std::pair<double*, double*>> gl64;   // per integral: the double node tables
   int launched = 0;       // sweeps enqueued so far
   int max_sweeps_all = 0;
@@ -135,8 +136,10 @@ void pinned_give(tt_ctx* c, char* p, size_t bytes) {
 }
 
 void launch(tt_job* j, int what, int rb) {
+  // the rule's group depends on the launch's rank bucket; a fixed or tuned one does not
+  const int grp = j->group_ruled ? search_group_for_bucket(j->group, rb) : j->group;
   LaunchArgs a{j->ddesc,   j->dbond,       j->nbond, j->dcore, j->ncore,
-               j->nprob,   j->mbucket,     j->ctx->stream, j->dctr, j->group};
+               j->nprob,   j->mbucket,     j->ctx->stream, j->dctr, grp};
   Timed tm(j->ctx, what == LAUNCH_SWEEP   ? KK_SWEEP
                    : what == LAUNCH_START ? KK_START
                    : what == LAUNCH_ALS   ? KK_REFRESH
@@ -685,7 +688,10 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   if (j->prec != TT_FP64) j->group = 1;
   else if (ctx->search_group > 0) j->group = ctx->search_group;   // tt_ctx_set_search_group
   else if (tuned_group > 0) j->group = tuned_group;
-  else j->group = search_group_rule(ctx->cus, j->nbond, j->ncore, j->prec);
+  else {
+    j->group = search_group_rule(ctx->cus, j->nbond, j->ncore, j->prec);
+    j->group_ruled = true;
+  }
   // one pinned block (reused from the context when possible): done flags, then
   // the host image of the table region, the source of the asynchronous upload
   const size_t flags_bytes = (sizeof(int32_t) * count + 255) & ~size_t(255);
