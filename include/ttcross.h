@@ -348,14 +348,13 @@ tt_status tt_mc_integrate_noalloc(tt_ctx *ctx, const tt_problem *problem, int32_
  * Errors: TT_EINVAL (bad kind or NULL outputs). */
 tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
 
-/* Workgroups per superblock search for double jobs created after the call
+/* Workgroups per superblock search for jobs created after the call
  * (a launch shape, not part of the method: every group size gives the same
  * values, pivots and evaluation counts bit for bit).  group 1..8 fixes it
  * (over any tuned choice); 0 returns to the tuned group, else the rule: as many
  * as keep one compute unit per workgroup of a sweep launch (superblocks x group
  * + cores <= compute units), at most 1, 2 or 3 for a launch sized for ranks up
- * to 8, 16 or more.  Double-double and quad-double jobs
- * always search with one workgroup.  A serving loop's launches take the rule
+ * to 8, 16 or more.  A serving loop's launches take the rule
  * for their running set, or the group fixed when the server was created.
  * Errors: TT_EINVAL outside 0..8. */
 tt_status tt_ctx_set_search_group(tt_ctx *ctx, int32_t group);
@@ -424,13 +423,13 @@ void tt_server_destroy(tt_server *server);
  *                synthetic classes);
  *   rank_policy  0: each sweep's kernel is sized for the ranks reachable in that
  *                sweep; 1: for the rank caps;
- *   search_group workgroups per superblock search (double jobs; see
+ *   search_group workgroups per superblock search (see
  *                tt_ctx_set_search_group), 0 for the rule's.
  * Without tuning a job takes the smallest mode bucket, policy 0 and the rule's
  * search group (the rule).  The candidates: every valid mode bucket with both
  * policies at the rule's group, and the rule's bucket and policy 0 with search
- * groups 1, 2, 4 and 6 (double jobs, when tt_ctx_set_search_group has not fixed
- * the group).
+ * groups 1, 2, 4 and 6 (when tt_ctx_set_search_group has not fixed the
+ * group).
  * tt_autotune runs the given job once per candidate variant (`reps` times each,
  * median wall time from tt_cross_init to the stopping rule), keeps only the
  * variants whose results equal the rule's bit for bit (every value, sweep count

@@ -85,11 +85,12 @@ struct tt_ctx {
 // Workgroups per superblock search of a double job with nbond superblocks and
 // ncore cores: as many as leave one compute unit per workgroup, so that the
 // whole grid is resident at once, but at most kRuleGroup (on the headline
-// Ising job 3 measured fastest: each member adds a record to every exchange);
-// 1 for the extended precisions.  tt_autotune may choose another.
+// Ising job 3 measured fastest: each member adds a record to every exchange).
+// tt_autotune may choose another.
 constexpr int kRuleGroup = 3;
 inline int search_group_rule(int cus, int nbond, int ncore, int prec) {
-  if (prec != TT_FP64 || nbond <= 0) return 1;
+  (void)prec;   // every number type searches the same way
+  if (nbond <= 0) return 1;
   const int g = (cus - ncore) / nbond;
   return g < 1 ? 1 : g > kRuleGroup ? kRuleGroup : g;
 }

@@ -31,7 +31,7 @@ using Real = double;
 template <int MAXM, int RMAX>
 void sweep(const LaunchArgs& a) {
   // group workgroups per superblock, then one per core
-  const int group = (TT_INST_DD || TT_INST_QD || a.group < 1) ? 1 : a.group;
+  const int group = a.group < 1 ? 1 : a.group;
   hipLaunchKernelGGL((k_sweep<Real, TT_FAM, MAXM, RMAX>), dim3(group * a.nbond + a.ncore), dim3(kSweepBlock), 0,
                      a.stream, a.desc, a.bond_tasks, a.nbond, a.core_tasks, a.sweep_ctr, group);
 }

@@ -35,19 +35,24 @@ struct PivRec {
 };
 static_assert(sizeof(PivRec) == sizeof(tt_pivot), "PivRec must mirror tt_pivot");
 
-// One record of a clustered search's exchange (double jobs): a member's best |error|
-// v at point idx with its error e and value a (argmax steps), or its largest |B|
-// seen in v and its non-finite flag in idx (the closing step).  Each 64-bit word
-// holds 32 bits of the record and, above them, the tag of the sweep and step it
-// belongs to, and is written and read as one atomic: a reader that sees the tag in
-// every word holds the whole record of that step, with no fence (a word is new or
-// old as a whole).
+// One record of a clustered search's exchange: a member's best |error| v at point
+// idx with its error e and value a (argmax steps; e and a in the job's number
+// type), or its largest |B| seen in v and its non-finite flag in idx (the closing
+// step).  Each 64-bit word holds 32 bits of the record and, above them, the tag of
+// the sweep and step it belongs to, and is written and read as one atomic: a
+// reader that sees the tag in every word holds the whole record of that step,
+// with no fence (a word is new or old as a whole).  Words: v (2), idx (1), then
+// the doubles of e and of a (2 each): 7 for double, 11 for double-double, 19 for
+// quad-double.
+constexpr int kXWords = 3 + 4 * (int)(sizeof(qd) / sizeof(double));
 struct XSlot {
-  uint64_t w[8];   // v low, v high, idx, e low, e high, a low, a high, unused
+  uint64_t w[kXWords + 1];
 };
 constexpr int kMaxGroup = 8;   // workgroups per superblock at most
+template <class T>
 struct XRec {                  // an exchange record unpacked
-  double v, e, a;
+  double v;
+  T e, a;
   int idx;
 };
 
@@ -355,7 +360,9 @@ __global__ __launch_bounds__(kBlock) void k_start(ProbDesc* __restrict__ P) {
   ProbState* st = p.st;
   // clustered searches match exchange records by tag: none may survive from the
   // memory's earlier use
-  for (int e = tid; e < p.nbonds * 2 * kMaxGroup * 8; e += blockDim.x) p.xch[e / 8].w[e % 8] = 0;
+  constexpr int kSlotWords = (int)(sizeof(XSlot) / sizeof(uint64_t));
+  for (int e = tid; e < p.nbonds * 2 * kMaxGroup * kSlotWords; e += blockDim.x)
+    p.xch[e / kSlotWords].w[e % kSlotWords] = 0;
 
   if constexpr (!kStream) if (m <= 1) {   // no bond: the tensor is a vector (or a scalar for m = 0)
     T val = num<T>(0.0);
@@ -554,7 +561,7 @@ struct SearchSmem {
   double red_v[kSweepBlock / kWave + 1];
   int red_i[kSweepBlock / kWave + 1];
   T e_star, a_star;
-  XRec xres;    // a clustered search's combined record of the last exchange
+  XRec<T> xres;   // a clustered search's combined record of the last exchange
   int xfail;
 };
 
@@ -572,36 +579,51 @@ constexpr long long kWaitTicks = 1000000000LL;   // 10 s of the 100 MHz constant
 // Records alternate between two rows by the step's parity: a member can only post
 // step s + 2 after every member has posted step s + 1, hence after every member has
 // read step s.  Called by the whole workgroup.
-__device__ __forceinline__ XRec group_exchange(XSlot* __restrict__ xs, const int g, const int G, const uint32_t tag,
-                                               const bool argmax, const bool publish, const XRec mine, XRec& res,
-                                               int& fail) {
+template <class T>
+__device__ __forceinline__ XRec<T> group_exchange(XSlot* __restrict__ xs, const int g, const int G,
+                                                  const uint32_t tag, const bool argmax, const bool publish,
+                                                  const XRec<T> mine, XRec<T>& res, int& fail) {
+  constexpr int W = (int)(sizeof(T) / sizeof(double)), NW = 3 + 4 * W;
+  static_assert(NW <= kXWords, "an exchange record fits its slot");
   XSlot* row = xs + (tag & 1) * kMaxGroup;
   const uint64_t tg = (uint64_t)tag << 32;
   if (threadIdx.x == 0) {
     uint64_t* my = row[g].w;
-    const uint64_t vb = (uint64_t)__double_as_longlong(mine.v), eb = (uint64_t)__double_as_longlong(mine.e),
-                   ab = (uint64_t)__double_as_longlong(mine.a);
-    const uint64_t words[7] = {tg | (vb & 0xffffffffu), tg | (vb >> 32), tg | (uint32_t)mine.idx,
-                               tg | (eb & 0xffffffffu), tg | (eb >> 32),  tg | (ab & 0xffffffffu),
-                               tg | (ab >> 32)};
+    uint64_t words[NW];
+    auto put = [&](int k, double x) {
+      const uint64_t bits = (uint64_t)__double_as_longlong(x);
+      words[k] = tg | (bits & 0xffffffffu);
+      words[k + 1] = tg | (bits >> 32);
+    };
+    put(0, mine.v);
+    words[2] = tg | (uint32_t)mine.idx;
+    const double* ec = reinterpret_cast<const double*>(&mine.e);
+    const double* ac = reinterpret_cast<const double*>(&mine.a);
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      put(3 + 2 * c, ec[c]);
+      put(3 + 2 * W + 2 * c, ac[c]);
+    }
     if (publish) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 #pragma unroll
-    for (int k = 0; k < 7; ++k) __hip_atomic_store(&my[k], words[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int k = 0; k < NW; ++k) __hip_atomic_store(&my[k], words[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (threadIdx.x < kWave) {
     const int h = threadIdx.x;
     int ok = 1;
-    XRec r{argmax ? -1.0 : 0.0, 0.0, 0.0, argmax ? 0x7fffffff : 0};
+    XRec<T> r{argmax ? -1.0 : 0.0, num<T>(0.0), num<T>(0.0), argmax ? 0x7fffffff : 0};
+    double* rec = reinterpret_cast<double*>(&r.e);
+    double* rac = reinterpret_cast<double*>(&r.a);
     if (h < G) {
       const uint64_t* src = row[h].w;
-      uint64_t w[7];
+      uint64_t w[NW];
       const long long t0 = (long long)wall_clock64();
       for (;;) {
 #pragma unroll
-        for (int k = 0; k < 7; ++k) w[k] = __hip_atomic_load(&src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < NW; ++k) w[k] = __hip_atomic_load(&src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         bool all = true;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) all = all && (w[k] >> 32) == tag;
+        for (int k = 0; k < NW; ++k) all = all && (w[k] >> 32) == tag;
         if (all) break;
         if ((long long)wall_clock64() - t0 > kWaitTicks) {
           ok = 0;
@@ -610,24 +632,36 @@ __device__ __forceinline__ XRec group_exchange(XSlot* __restrict__ xs, const int
         __builtin_amdgcn_s_sleep(1);
       }
       if (ok) {
-        r.v = __longlong_as_double((long long)((w[0] & 0xffffffffu) | (w[1] << 32)));
+        auto get = [&](int k) { return __longlong_as_double((long long)((w[k] & 0xffffffffu) | (w[k + 1] << 32))); };
+        r.v = get(0);
         r.idx = (int)(uint32_t)w[2];
-        r.e = __longlong_as_double((long long)((w[3] & 0xffffffffu) | (w[4] << 32)));
-        r.a = __longlong_as_double((long long)((w[5] & 0xffffffffu) | (w[6] << 32)));
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          rec[c] = get(3 + 2 * c);
+          rac[c] = get(3 + 2 * W + 2 * c);
+        }
       }
     }
     if (publish) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
     for (int off = 1; off < kMaxGroup; off <<= 1) {   // lanes 0..7 hold the records (or neutral ones)
-      const double ov = __shfl_xor(r.v, off, kWave), oe = __shfl_xor(r.e, off, kWave);
-      const double oa = __shfl_xor(r.a, off, kWave);
+      const double ov = __shfl_xor(r.v, off, kWave);
       const int oi = __shfl_xor(r.idx, off, kWave);
+      double oe[W], oa[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        oe[c] = __shfl_xor(rec[c], off, kWave);
+        oa[c] = __shfl_xor(rac[c], off, kWave);
+      }
       if (argmax) {
         if (better(ov, oi, r.v, r.idx)) {
           r.v = ov;
-          r.e = oe;
-          r.a = oa;
           r.idx = oi;
+#pragma unroll
+          for (int c = 0; c < W; ++c) {
+            rec[c] = oe[c];
+            rac[c] = oa[c];
+          }
         }
       } else {
         r.v = fmax(r.v, ov);
@@ -706,9 +740,9 @@ __device__ __forceinline__ double ising_c_joined(const double* sL, int al, doubl
 // every row step run through the same evaluation loop (one inlined integrand).
 // Decisions (argmax, acceptance) are taken on the leading double of |error|.
 //
-// A double job's search may be spread over G workgroups (members g = 0..G-1 of a
-// cluster): member g evaluates the points q with q / blockDim = g mod G, and after
-// each loop the members combine their block argmaxes (group_exchange), so every
+// A search may be spread over G workgroups (members g = 0..G-1 of a cluster):
+// member g evaluates the points q with q / blockDim = g mod G, and after each
+// loop the members combine their block argmaxes (group_exchange), so every
 // member takes the decisions one workgroup would take, on the same values.  A last
 // exchange combines the largest |B| seen and the non-finite flags; member 0 then
 // writes the pivot record.  Only member 0 returns true (it is to signal the cores).
@@ -889,7 +923,7 @@ __device__ __forceinline__ bool search_bond(const ProbDesc& p, const int b, cons
       }
       t0 = t3;
     }
-    if constexpr (!is_ext_t<T>::value) {
+    {
       if (G > 1) {   // the members' argmaxes combined (with the winner's error and value at a row step)
         if (mode == 2) {
           if (best.idx % (int)blockDim.x == tid) {
@@ -898,8 +932,9 @@ __device__ __forceinline__ bool search_bond(const ProbDesc& p, const int b, cons
           }
           __syncthreads();
         }
-        const XRec mine{best.v, mode == 2 ? sm.e_star : 0.0, mode == 2 ? sm.a_star : 0.0, best.idx};
-        const XRec r = group_exchange(xs, g, G, xtag0 + xstep++, true, false, mine, sm.xres, sm.xfail);
+        const XRec<T> mine{best.v, mode == 2 ? sm.e_star : num<T>(0.0), mode == 2 ? sm.a_star : num<T>(0.0),
+                           best.idx};
+        const XRec<T> r = group_exchange<T>(xs, g, G, xtag0 + xstep++, true, false, mine, sm.xres, sm.xfail);
         best.v = r.v;
         best.idx = r.idx;
         my_e = r.e;   // held by every thread: the owner test below is replaced
@@ -955,10 +990,10 @@ __device__ __forceinline__ bool search_bond(const ProbDesc& p, const int b, cons
   }
   seen = block_max(seen, sm.red_v);
   int any_bad = __syncthreads_or(bad);
-  if constexpr (!is_ext_t<T>::value) {
+  {
     if (G > 1) {   // every member's largest |B| and flags; also: every member's writes are done
-      const XRec r = group_exchange(xs, g, G, xtag0 + xstep++, false, true, XRec{seen, 0.0, 0.0, any_bad}, sm.xres,
-                                    sm.xfail);
+      const XRec<T> r = group_exchange<T>(xs, g, G, xtag0 + xstep++, false, true,
+                                          XRec<T>{seen, num<T>(0.0), num<T>(0.0), any_bad}, sm.xres, sm.xfail);
       seen = r.v;
       any_bad = r.idx;
       if (sm.xfail) {

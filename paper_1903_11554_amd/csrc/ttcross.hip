@@ -504,7 +504,7 @@ tt_status tt_autotune(tt_ctx* ctx, const tt_problem* problems, int32_t count, in
       cands.push_back({mb, 0, 0});
       cands.push_back({mb, 1, 0});
     }
-  if (prec == TT_FP64 && ctx->search_group == 0)
+  if (ctx->search_group == 0)
     for (int g : {1, 2, 4, 6})   // the rule's variant with other search groups
       cands.push_back({rule_mb, 0, g});
   std::vector<tt_info> ref(count), got(count);
@@ -685,8 +685,7 @@ tt_status tt_cross_init(tt_ctx* ctx, const tt_problem* problems, int32_t count, 
   j->dctr = (int32_t*)(base + ctr_off);
   j->nbond = (int)bond_tasks.size();
   j->ncore = (int)core_tasks.size();
-  if (j->prec != TT_FP64) j->group = 1;
-  else if (ctx->search_group > 0) j->group = ctx->search_group;   // tt_ctx_set_search_group
+  if (ctx->search_group > 0) j->group = ctx->search_group;   // tt_ctx_set_search_group
   else if (tuned_group > 0) j->group = tuned_group;
   else {
     j->group = search_group_rule(ctx->cus, j->nbond, j->ncore, j->prec);

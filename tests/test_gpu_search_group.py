@@ -1,4 +1,5 @@
-"""Clustered searches: a superblock searched by G workgroups gives what one gives.
+"""Clustered searches: a superblock searched by G workgroups gives what one gives
+(in double, double-double and quad-double).
 
 The sweep kernel may spread each superblock's search (Alg. 2 inside Alg. 6) over
 G workgroups that combine their block argmaxes after every step.  Every point
@@ -22,6 +23,8 @@ WORKLOADS = {
     "ising_d36_streaming": [Problem("ising_d", 36, 6, 6, 1e-10, seed=6)],
     "ising_c41_rank16": [Problem("ising_c", 41, 12, 14, 1e-12, seed=3, max_sweeps=8)],
     "sum2_d12": [Problem("sum2_exp_cos", 12, 32, 8, 1e-12, seed=9, params=synthetic_params(12, 9))],
+    "ising_d6_d8_double_double": [Problem("ising_d", d, 16, 16, 1e-20, seed=d, precision="dd") for d in (6, 8)],
+    "ising_d5_quad_double": [Problem("ising_d", 5, 5, 8, 1e-40, seed=5, precision="qd")],
 }
 
 
@@ -33,9 +36,11 @@ def run_with_group(probs, group):
         infos = job.run()
         out = []
         for k in range(len(probs)):
+            # the whole value in every number type: its double components and exponent
+            hist = job.history_parts(k, 4) if probs[k].precision != "fp64" else job.history_scaled(k)
             out.append(dict(info={key: infos[k][key] for key in ("sweeps", "reason", "evals", "err_flags",
                                                                    "value", "max_rank")},
-                            log=job.pivot_log(k), hist=job.history_scaled(k), sets=job.index_sets(k)))
+                            log=job.pivot_log(k), hist=hist, sets=job.index_sets(k)))
         job.free()
         return out
     finally:
