@@ -352,9 +352,10 @@ tt_status tt_ctx_profile(tt_ctx *ctx, int32_t enable);
  * (a launch shape, not part of the method: every group size gives the same
  * values, pivots and evaluation counts bit for bit).  group 1..8 fixes it
  * (over any tuned choice); 0 returns to the tuned group, else the rule: as many
- * as keep one compute unit per workgroup of a sweep launch (superblocks x group
- * + cores <= compute units), at most 1, 2 or 3 for a launch sized for ranks up
- * to 8, 16 or more.  A serving loop's launches take the rule
+ * as keep at most two workgroups per compute unit in a sweep launch
+ * (superblocks x group + cores <= 2 x compute units), at most 1, 2 or 3 for a
+ * double launch sized for ranks up to 8, 16 or more, at most 6 for double-double
+ * and quad-double.  A serving loop's launches take the rule
  * for their running set, or the group fixed when the server was created.
  * Errors: TT_EINVAL outside 0..8. */
 tt_status tt_ctx_set_search_group(tt_ctx *ctx, int32_t group);

@@ -82,23 +82,27 @@ struct tt_ctx {
   int search_group = 0;                            // workgroups per superblock search (0: the rule)
 };
 
-// Workgroups per superblock search of a double job with nbond superblocks and
-// ncore cores: as many as leave one compute unit per workgroup, so that the
-// whole grid is resident at once, but at most kRuleGroup (on the headline
-// Ising job 3 measured fastest: each member adds a record to every exchange).
-// tt_autotune may choose another.
-constexpr int kRuleGroup = 3;
+// Workgroups per superblock search of a job with nbond superblocks and ncore
+// cores: as many as keep at most two workgroups per compute unit, capped per
+// number type.  Each member adds a record to every exchange, so the split pays
+// only where the points are costly: on the headline Ising job (double) 3
+// measured fastest, on the double-double job of D_8..D_12 (128 nodes, rank 64)
+// 6 (79.7 ms; 3: 99.4, 4: 89.2, 8: 82.9).  tt_autotune may choose another.
+constexpr int kRuleGroup = 3;      // double
+constexpr int kRuleGroupExt = 6;   // double-double and quad-double
 inline int search_group_rule(int cus, int nbond, int ncore, int prec) {
-  (void)prec;   // every number type searches the same way
   if (nbond <= 0) return 1;
-  const int g = (cus - ncore) / nbond;
-  return g < 1 ? 1 : g > kRuleGroup ? kRuleGroup : g;
+  const int cap = prec == TT_FP64 ? kRuleGroup : kRuleGroupExt;
+  const int g = (2 * cus - ncore) / nbond;
+  return g < 1 ? 1 : g > cap ? cap : g;
 }
-// The rule's group for one sweep launch whose kernel is sized for rank bucket
-// rbucket: the searches of small ranks read little, so the exchanges would cost
-// more than the split saves (headline job, median of 15: 1 / 2 / 3 workgroups
-// for buckets 8 / 16 / 32 took 2.38 ms, 3 for every bucket 2.47 ms).
-inline int search_group_for_bucket(int group_rule, int rbucket) {
+// The rule's group for one sweep launch of a double job whose kernel is sized
+// for rank bucket rbucket: the searches of small ranks read little, so the
+// exchanges would cost more than the split saves (headline job, median of 15:
+// 1 / 2 / 3 workgroups for buckets 8 / 16 / 32 took 2.38 ms, 3 for every bucket
+// 2.47 ms).  Extended-precision launches keep the job's group.
+inline int search_group_for_bucket(int group_rule, int rbucket, int prec) {
+  if (prec != TT_FP64) return group_rule;
   const int g = rbucket <= 8 ? 1 : rbucket <= 16 ? 2 : kRuleGroup;
   return g < group_rule ? g : group_rule;
 }

@@ -351,7 +351,7 @@ void worker_main(tt_server* s) {
                      bucket_m_for(fam, TT_FP64, maxm), ctx->stream, (int32_t*)(s->dtable + s->off_ctr),
                      s->search_group > 0 ? s->search_group
                                          : search_group_for_bucket(search_group_rule(ctx->cus, nbond, ncore, TT_FP64),
-                                                                   bucket_r(rmax))};
+                                                                   bucket_r(rmax), TT_FP64)};
         {
           Timed tm(ctx, KK_SWEEP);
           switch (fam) {

@@ -137,7 +137,7 @@ void pinned_give(tt_ctx* c, char* p, size_t bytes) {
 
 void launch(tt_job* j, int what, int rb) {
   // the rule's group depends on the launch's rank bucket; a fixed or tuned one does not
-  const int grp = j->group_ruled ? search_group_for_bucket(j->group, rb) : j->group;
+  const int grp = j->group_ruled ? search_group_for_bucket(j->group, rb, j->prec) : j->group;
   LaunchArgs a{j->ddesc,   j->dbond,       j->nbond, j->dcore, j->ncore,
                j->nprob,   j->mbucket,     j->ctx->stream, j->dctr, grp};
   Timed tm(j->ctx, what == LAUNCH_SWEEP   ? KK_SWEEP
