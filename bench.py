@@ -26,12 +26,12 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector (FMA = 2 flops)
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per k_sweep launch on this workload from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (KiB per dispatch, mean over the 108 launches of a --no-tune run:
+# WRITE_SIZE (KiB per dispatch, mean over the 100 launches of a --no-tune run:
 # the rule's variant), scaled by what the same counters read for a 1 GiB device
 # copy (FETCH 2.0, WRITE 1.0).  Valid only for the kernel sources they were
 # taken on (hash below); for any other source the traffic is reported as null.
-SWEEP_TRAFFIC = {"source_hash": "68621f4ee2d7b592", "fetch_kib": 5410.0, "fetch_scale": 2.0,
-                 "write_kib": 2689.5, "write_scale": 1.0}
+SWEEP_TRAFFIC = {"source_hash": "68621f4ee2d7b592", "fetch_kib": 5884.1, "fetch_scale": 2.0,
+                 "write_kib": 2903.0, "write_scale": 1.0}
 KERNEL_SOURCES = ("tt_device.hpp", "tt_inst.hip", "tt_kernels.hpp", "tt_launch.hpp")
 
 
@@ -845,7 +845,8 @@ def main():
     nl_u, ms_u = r["kt"]["update"]
     achieved = r["s_flops"] / (ms_s * 1e-3) / 1e12
     roof = {"kernel": "k_sweep (one launch per sweep: pivot search of every superblock, core updates, "
-                      "quadrature and stopping rule; one workgroup per superblock and one per core)",
+                      "quadrature and stopping rule; one to three workgroups per superblock search "
+                      "by rank bucket, one per core)",
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": sweep_traffic_bytes(),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",

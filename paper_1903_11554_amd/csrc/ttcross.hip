@@ -778,7 +778,7 @@ tt_status tt_cross_enqueue(tt_job* j, int32_t n_sweeps) {
 // completed sweep the host reads the pinned done flags that the kernels write,
 // and stops queueing once every integral has stopped.  Sweeps still queued for
 // stopped integrals return at once.
-static const int kQueued = 4;
+static const int kQueued = 2;
 
 tt_status tt_cross_run(tt_job* j, tt_info* info) {
   if (!j) return TT_EINVAL;
