@@ -522,8 +522,8 @@ def run_large(ctx, reps=2):
              ("D_64", Problem("ising_d", 64, 33, 16, 1e-9, seed=64), printed[64]),
              ("D_128", Problem("ising_d", 128, 33, 24, 1e-11, seed=128), printed[128]),
              ("D_256", Problem("ising_d", 256, 33, 24, 1e-11, seed=256), printed[256]),
-             ("D_512", Problem("ising_d", 512, 33, 16, 1e-10, seed=512), printed[512]),
-             ("D_1024", Problem("ising_d", 1024, 33, 16, 1e-10, seed=1024), printed[1024])]
+             ("D_512", Problem("ising_d", 512, 33, 24, 1e-11, seed=512), printed[512]),
+             ("D_1024", Problem("ising_d", 1024, 33, 24, 1e-11, seed=1024), printed[1024])]
     out, values = {}, {}
     for name, p, ref in cases:
         best = None

@@ -199,11 +199,12 @@ def run_d(d, rank, tol):
 
 
 @pytest.mark.parametrize("d,rank,tol,bound", [(64, 16, 1e-9, 1e-8), (128, 24, 1e-11, 1e-11),
-                                              (256, 24, 1e-11, 1e-11), (512, 16, 1e-10, 1e-8),
-                                              (1024, 16, 1e-10, 3e-8)])
+                                              (256, 24, 1e-11, 1e-11), (512, 24, 1e-11, 1e-10),
+                                              (1024, 24, 1e-11, 1e-10)])
 def test_d_large_against_printed_values(d, rank, tol, bound):
     # double precision with 33 nodes against the paper's quadruple-precision values;
-    # D_512 and D_1024 lie below the double range and are compared as mantissa 2^exponent
+    # D_512 and D_1024 lie below the double range and are compared as mantissa 2^exponent;
+    # at rank <= 16 they end 4e-9 and 1e-8 away, at rank <= 24 within 10 tol
     _, rel = run_d(d, rank, tol)
     assert rel < bound
 
