@@ -201,6 +201,25 @@ def check_result(p, info, refs=None):
     return ok, rel
 
 
+def failure_causes(pairs, refs=None):
+    """Count the integrals that fail check_result by cause: a numeric error flag,
+    a stop other than the stopping rule (rank cap, sweep cap), or a value farther
+    than tol from the reference."""
+    out = {}
+    for p, info in pairs:
+        ok, rel = check_result(p, info, refs)
+        if ok:
+            continue
+        if info["err_flags"] != 0:
+            key = "numeric_error"
+        elif info["reason"] != "converged":
+            key = f"stopped_{info['reason']}"
+        else:
+            key = f"rel_err_above_tol:{p.family}"
+        out[key] = out.get(key, 0) + 1
+    return out
+
+
 def run_gpu(args):
     import torch
 
@@ -616,6 +635,8 @@ def run_serving(ctx, seconds, refs, warm_s=1.0, plain_sample=100):
                         "[1e-12, 1e-6], rank cap ~ U{{16..64}}, 64 nodes".format(len(trace)),
             "requests_measured": n_meas, "latency_ms_p50": pct(0.5), "latency_ms_p99": pct(0.99),
             "integrals_per_s": n_ok / max(t_end - first, 1e-9), "integrals_failed": n_meas - n_ok,
+            "failed_by_cause": failure_causes([(p, r[0]) for (at, r), (_, p) in zip(res, trace) if at >= warm_s],
+                                              refs),
             "max_running": st["max_running"], "sweep_launches": st["sweep_launches"],
             "admissions": st["admissions"],
             "plain_ms_per_integral": plain_s * 1e3, "plain_integrals_per_s": 1.0 / plain_s,
@@ -703,10 +724,31 @@ def run_batch(ctx, refs, reps=5):
         j.free()
     t_batch = sorted(times)[len(times) // 2]
     tf = flops / (ms * 1e-3) / 1e12
+    # the same 64 integrals under the strict stopping rule (until a sweep accepts no pivot)
+    import dataclasses
+    strict = [dataclasses.replace(p, stop="strict") for p in probs]
+    job = ctx.job(strict)
+    job.run()
+    job.free()
+    st_times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        job = ctx.job(strict)
+        st_infos = job.run()
+        torch.cuda.synchronize()
+        st_times.append(time.perf_counter() - t)
+        job.free()
+    st_ok = sum(1 for p, inf in zip(strict, st_infos) if check_result(p, inf, refs)[0])
+    t_strict = sorted(st_times)[len(st_times) // 2]
+    strict_rec = {"rule": "strict (TT_STOP_STRICT)", "ms_per_batch": t_strict * 1e3,
+                  "integrals_per_s": st_ok / t_strict, "integrals_failed": len(strict) - st_ok,
+                  "failed_by_cause": failure_causes(zip(strict, st_infos), refs)}
     return {"workload": "64 mixed integrals: C_n, D_n (n ~ U{4..16}, paper form), rank-2 "
                         "exp/cos products (d ~ U{8..32}); 64 nodes, rank <= 48, tol 1e-10; one job",
             "ms_per_batch": t_batch * 1e3, "integrals_per_s": n_ok / t_batch,
             "integrals_failed": len(probs) - n_ok, "integrals_with_reference": n_ref,
+            "failed_by_cause": failure_causes(zip(probs, infos), refs),
+            "strict_stop_rule": strict_rec,
             "evals_per_s": evals / t_batch,
             "plain_ms_sum": alone * 1e3, "plain_integrals_per_s": n_ok / alone,
             "speedup_vs_plain": alone / t_batch,
